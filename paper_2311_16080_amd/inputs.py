@@ -1,0 +1,112 @@
+"""Seeded synthetic inputs shared by the GPU path's tests/benchmark and the oracle.
+
+This module holds no lattice Boltzmann arithmetic: it only produces the
+workload inputs (initial velocity fields, obstacle masks, solid-fraction
+fields, batch parameters) from fixed seeds, in FP64 on the host.  Both sides
+receive the same arrays; each side turns them into populations with its own
+code.
+
+Workloads (shapes follow the paper's test problems):
+* Taylor-Green vortex, Sec. 4.1: u = U0 (sin kx cos ky, -cos kx sin ky).
+* 3-D lid-driven cavity, Sec. 4.2 and Sec. 5: starts at rest (no generator).
+* channel with random spheres: a 3-D obstacle field standing in for the
+  paper's channel/obstacle flows (Sec. 4.3/4.4); centres and radii from
+  numpy's default_rng(3), added until the solid fraction reaches the target.
+* partial bounce-back solid fraction: periodic Gaussian-filtered white noise
+  (default_rng(4) for the design field, 40 for the target run), s = (1 + tanh z)/2,
+  s = 0 in the first and last 16 columns.
+* batched cavities: side lengths, relaxation times and lid speeds from
+  default_rng(5).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def taylor_green_velocity(nx: int, ny: int, u0: float = 0.01) -> np.ndarray:
+    """(nx, ny, 2) float64 Taylor-Green velocity at t = 0 with x_i = i, y_j = j."""
+    kx = 2.0 * np.pi / nx
+    ky = 2.0 * np.pi / ny
+    x = np.arange(nx, dtype=np.float64)[:, None]
+    y = np.arange(ny, dtype=np.float64)[None, :]
+    u = np.empty((nx, ny, 2))
+    u[..., 0] = u0 * np.sin(kx * x) * np.cos(ky * y)
+    u[..., 1] = -u0 * np.cos(kx * x) * np.sin(ky * y)
+    return u
+
+
+def random_velocity(shape, dim: int, seed: int, amp: float = 0.03) -> np.ndarray:
+    """Seeded smooth-free random velocity (shape + (dim,)), for parity cases."""
+    rng = np.random.default_rng(seed)
+    return amp * rng.standard_normal(tuple(shape) + (dim,))
+
+
+def random_density(shape, seed: int, amp: float = 0.01, rho0: float = 1.0) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return rho0 + amp * rng.standard_normal(tuple(shape))
+
+
+def sphere_obstacles(nx: int, ny: int, nz: int, seed: int = 3, rmin: float = 8.0, rmax: float = 32.0,
+                     xlo: int = 64, xhi: int = 960, fraction: float = 0.05, max_spheres: int = 100000) -> np.ndarray:
+    """(nx, ny, nz) uint8 obstacle mask: spheres with centres uniform in
+    [xlo, xhi) x [0, ny) x [0, nz) and radii uniform in [rmin, rmax], added
+    until at least `fraction` of all cells are solid (overlaps allowed).
+    Rasterised in FP64: a cell is solid when its centre lies inside a sphere."""
+    rng = np.random.default_rng(seed)
+    solid = np.zeros((nx, ny, nz), dtype=np.uint8)
+    target = fraction * nx * ny * nz
+    count = 0
+    for _ in range(max_spheres):
+        cx = rng.uniform(xlo, xhi)
+        cy = rng.uniform(0, ny)
+        cz = rng.uniform(0, nz)
+        r = rng.uniform(rmin, rmax)
+        x0, x1 = max(int(np.floor(cx - r)), 0), min(int(np.ceil(cx + r)) + 1, nx)
+        y0, y1 = max(int(np.floor(cy - r)), 0), min(int(np.ceil(cy + r)) + 1, ny)
+        z0, z1 = max(int(np.floor(cz - r)), 0), min(int(np.ceil(cz + r)) + 1, nz)
+        if x0 >= x1 or y0 >= y1 or z0 >= z1:
+            continue
+        X = np.arange(x0, x1, dtype=np.float64)[:, None, None]
+        Y = np.arange(y0, y1, dtype=np.float64)[None, :, None]
+        Z = np.arange(z0, z1, dtype=np.float64)[None, None, :]
+        inside = (X - cx) ** 2 + (Y - cy) ** 2 + (Z - cz) ** 2 <= r * r
+        block = solid[x0:x1, y0:y1, z0:z1]
+        count += int(np.count_nonzero(inside & (block == 0)))
+        block[inside] = 1
+        if count >= target:
+            break
+    return solid
+
+
+def smooth_solid_fraction(nx: int, ny: int, seed: int = 4, sigma: float = 8.0, edge: int = 16) -> np.ndarray:
+    """(nx, ny) float64 field in [0, 1]: periodic Gaussian-filtered (sigma
+    cells) white noise normalised to unit std, mapped by (1 + tanh z)/2;
+    zero in the first and last `edge` columns of x."""
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal((nx, ny))
+    kx = np.fft.fftfreq(nx)[:, None]
+    ky = np.fft.fftfreq(ny)[None, :]
+    g = np.exp(-2.0 * (np.pi * sigma) ** 2 * (kx * kx + ky * ky))
+    z = np.real(np.fft.ifft2(np.fft.fft2(z) * g))
+    z = (z - z.mean()) / z.std()
+    s = 0.5 * (1.0 + np.tanh(z))
+    s[:edge, :] = 0.0
+    s[nx - edge:, :] = 0.0
+    return s
+
+
+def batch_cavities(n: int = 256, seed: int = 5, lmin: int = 64, lmax: int = 256,
+                   tau_lo: float = 0.52, tau_hi: float = 1.0, u_lo: float = 0.05, u_hi: float = 0.1):
+    """Side lengths L_d in [lmin, lmax], tau_d in [tau_lo, tau_hi), lid speeds U_d in [u_lo, u_hi)."""
+    rng = np.random.default_rng(seed)
+    L = rng.integers(lmin, lmax + 1, size=n)
+    tau = rng.uniform(tau_lo, tau_hi, size=n)
+    U = rng.uniform(u_lo, u_hi, size=n)
+    return L.astype(np.int64), tau, U
+
+
+def sample_cells(shape, count: int, seed: int) -> np.ndarray:
+    """`count` distinct flat cell indices of a grid of `shape`, seeded."""
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(shape))
+    return np.sort(rng.choice(n, size=min(count, n), replace=False))
