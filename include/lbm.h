@@ -1,0 +1,263 @@
+/*
+ * lbm.h -- C-ABI of the MI355X lattice Boltzmann stream-collide library
+ * (liblbm.so, hand-written HIP kernels for gfx950).
+ *
+ * The library advances the particle populations f_i of a lattice Boltzmann
+ * simulation: BGK collision to the quadratic equilibrium (paper Sec. 2,
+ * eqs. LBM-BGK, tau, feq), streaming (eq. streaming), the boundary treatment
+ * of Sec. 3.5 (halfway bounce-back with a moving-wall term, Zou-He velocity /
+ * pressure faces, equilibrium outflow, solid cells), the moments rho and u
+ * (eqs. density, velocity), and the discrete adjoint of the step (the
+ * gradients that the paper obtains from automatic differentiation of `step`,
+ * Sec. 3.6 and Sec. 6).
+ *
+ * Conventions
+ *  - Lattices: D2Q9, D3Q19, D3Q27 (Fig. "lattice").  Direction 0 is the rest
+ *    vector; 1..Q-1 follow the figure's order.
+ *  - Grid: nx * ny * nz cells, fields in (x, y, z) C order with z fastest
+ *    (2-D: nz = 1 or 0, y fastest), as the paper's arrays (Sec. 3.3).  Every
+ *    cell is a fluid node unless flagged solid; the six domain faces are
+ *    halfway outside the outermost cell layer.  N = nx*ny*nz < 2^31.
+ *  - Units: dx = dt = 1, cs^2 = 1/3, omega = 1/tau, nu = (tau - 1/2)/3.
+ *  - Pointers are device pointers unless marked host.  The caller owns every
+ *    pointer it passes; it must stay valid until the work enqueued on the
+ *    context's stream has completed.  Nothing is retained after return except
+ *    copies the library makes itself.
+ *  - All calls are ordered on the context's HIP stream (lbm_set_stream); calls
+ *    that return host data synchronise that stream.
+ *  - Errors: 0 on success, a negative LBM_E* code otherwise; no exception or
+ *    abort crosses the ABI.  lbm_last_error() returns a thread-local message
+ *    for the last failing call of this thread.  Argument checks run before any
+ *    device work, so a rejected call has no effect.  An asynchronous device
+ *    fault surfaces as LBM_EDEVICE at the next synchronising call.
+ *  - A context belongs to one host thread at a time.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes -------------------------------------------------------- */
+#define LBM_OK            0
+#define LBM_EINVAL       -1   /* bad argument */
+#define LBM_ENOMEM       -2   /* device (or host) allocation failed */
+#define LBM_EDEVICE      -3   /* HIP runtime / device error */
+#define LBM_ESTATE       -4   /* call not valid in the context's current state */
+#define LBM_EUNSUPPORTED -5   /* valid request this library does not implement */
+
+/* ---- lattices (Fig. "lattice") ------------------------------------------ */
+#define LBM_D2Q9  0
+#define LBM_D3Q19 1
+#define LBM_D3Q27 2
+
+/* ---- face boundary types (Sec. 3.5; Sec. 3.4 for periodic) --------------- */
+#define LBM_PERIODIC        0  /* must be set on both faces of an axis */
+#define LBM_WALL            1  /* halfway bounce-back; tangential u = moving wall */
+#define LBM_ZOUHE_VELOCITY  2  /* Zou-He non-equilibrium bounce-back, velocity u */
+#define LBM_ZOUHE_PRESSURE  3  /* Zou-He, density rho (u normal to the face) */
+#define LBM_EQ_OUTFLOW      4  /* missing populations = feq(rho, u of the cell) */
+
+/* ---- storage / arithmetic types (Sec. 3.7 "computation/storage" pairs) --- */
+#define LBM_F64  0
+#define LBM_F32  1
+#define LBM_F16  2
+#define LBM_BF16 3
+
+/* ---- streaming patterns --------------------------------------------------- */
+#define LBM_INPLACE 0  /* one buffer, AA access pattern (Bailey et al. 2009) */
+#define LBM_DOUBLE  1  /* two buffers, push streaming */
+
+/*
+ * One face of the box.  Faces are ordered -x, +x, -y, +y, -z, +z.
+ *  type : LBM_PERIODIC / LBM_WALL / LBM_ZOUHE_VELOCITY / LBM_ZOUHE_PRESSURE /
+ *         LBM_EQ_OUTFLOW.
+ *  u    : wall velocity (LBM_WALL; its normal component must be 0) or inlet
+ *         velocity (LBM_ZOUHE_VELOCITY).
+ *  rho  : face density (LBM_ZOUHE_PRESSURE, LBM_EQ_OUTFLOW); must be > 0 there.
+ * Rules (else LBM_EINVAL): periodic on both faces of an axis or on neither;
+ * Zou-He / outflow faces on at most one axis, that axis at least 2 cells
+ * long; for 2-D lattices the z faces are ignored.
+ */
+typedef struct {
+    int32_t type;
+    int32_t reserved;
+    double  u[3];
+    double  rho;
+} lbm_face;
+
+typedef struct {
+    lbm_face face[6];
+} lbm_bc;
+
+/*
+ * Options; set before the first lbm_init_equilibrium.
+ *  storage : LBM_F64, LBM_F32 (default), LBM_F16, LBM_BF16.  Populations are
+ *            stored as the deviation h_i = f_i - w_i rho0 (F64/F32) or as
+ *            h_i / w_i (F16/BF16, rounded to nearest even) -- the
+ *            renormalisation around zero that the paper notes single
+ *            precision needs (Sec. 4.1).
+ *  compute : LBM_F64 (only with F64 storage) or LBM_F32 (others).
+ *  pattern : LBM_INPLACE (default) or LBM_DOUBLE.
+ *  rho0    : reference density (default 1).
+ */
+typedef struct {
+    int32_t storage;
+    int32_t compute;
+    int32_t pattern;
+    int32_t reserved;
+    double  rho0;
+} lbm_options;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Thread-local text of the last error of this thread ("" if none). */
+const char *lbm_last_error(void);
+
+/* Library version string. */
+const char *lbm_version(void);
+
+/*
+ * Create a single-domain context (Sec. 3.2 lattice choice, Sec. 3.3 domain,
+ * Sec. 3.5 boundary setup).  lattice: LBM_D2Q9/D3Q19/D3Q27; nx, ny >= 1;
+ * nz >= 1 for 3-D, nz in {0, 1} for D2Q9 (the paper's nz = 0 for 2-D);
+ * tau > 1/2 (nu > 0, eq. tau); bc: host pointer, copied; NULL = all periodic.
+ * Does no device work: the state is allocated on the current HIP device by the
+ * first lbm_init_equilibrium.  Returns NULL on error (see lbm_last_error).
+ */
+lbm_ctx *lbm_create(int lattice, int nx, int ny, int nz, double tau, const lbm_bc *bc);
+
+/*
+ * Create a batch of independent domains of one lattice that advance together
+ * (the batching the paper gets from vmap, Sec. 3.1 / Sec. 6.1).  n >= 1;
+ * nx, ny, nz, tau: host arrays of n; bcs: host array of n lbm_bc (NULL = all
+ * periodic).  Per-domain fields are packed back to back; lbm_batch_offsets
+ * gives each domain's first cell.  Returns NULL on error.
+ */
+lbm_ctx *lbm_create_batch(int lattice, int n, const int *nx, const int *ny, const int *nz,
+                          const double *tau, const lbm_bc *bcs);
+
+/* off: host array of n+1 int64; off[d] = first packed cell of domain d, off[n] = total cells. */
+int lbm_batch_offsets(const lbm_ctx *ctx, int64_t *off);
+
+/* Free everything the context owns (synchronises its stream).  NULL is a no-op. */
+void lbm_destroy(lbm_ctx *ctx);
+
+/* opt: host pointer.  LBM_ESTATE after the state exists. */
+int lbm_set_options(lbm_ctx *ctx, const lbm_options *opt);
+
+/* hip_stream: a hipStream_t (NULL = the null stream). */
+int lbm_set_stream(lbm_ctx *ctx, void *hip_stream);
+
+/*
+ * Solid cells (interior obstacles; bounce-back at their faces).  flags: N
+ * bytes, nonzero = solid; host (on_device = 0) or device (1).  Copied.  NULL
+ * clears.  Valid before or after init; solid cells report rho0, u = 0.
+ */
+int lbm_set_solid(lbm_ctx *ctx, const uint8_t *flags, int on_device);
+
+/*
+ * Partial bounce-back solid fraction s in [0, 1] per cell (gray LBM, Walsh,
+ * Burwinkle & Saar 2009 -- an addition to the paper): after collision,
+ * f_i <- (1 - s) f*_i + s f_opp(i) with the pre-collision opposite population.
+ * s: N float32, host (on_device = 0) or device (1); copied; NULL clears.
+ * s = 0 everywhere is bitwise the plain BGK step.
+ */
+int lbm_set_solid_fraction(lbm_ctx *ctx, const float *s, int on_device);
+
+/*
+ * f <- feq(rho, u) at every fluid cell (eq. feq), allocating the state on
+ * first use.  rho: N values, u: D x N values (component-major: u_x plane,
+ * then u_y, then u_z), both device pointers of `dtype` (LBM_F64 or LBM_F32);
+ * NULL rho = rho0, NULL u = 0.  Resets the step counter to 0.
+ */
+int lbm_init_equilibrium(lbm_ctx *ctx, const void *rho, const void *u, int dtype);
+
+/*
+ * Advance n >= 0 time steps (collide, stream, boundary fill; Sec. 3.6),
+ * asynchronously on the context's stream.  If a tape is recording, the state
+ * is checkpointed every K steps.  Batch contexts advance every domain.
+ */
+int lbm_step(lbm_ctx *ctx, int n);
+
+/* Number of completed steps since the last init / load. */
+int64_t lbm_time(const lbm_ctx *ctx);
+
+/*
+ * Moments of the current state (eqs. density, velocity): rho (N values) and
+ * u (D x N, component-major), device pointers of `dtype` (LBM_F64 or LBM_F32);
+ * either may be NULL.  Solid cells get rho0 and 0.  sums_host (nullable, host)
+ * receives {mass, P_x, P_y, P_z, kinetic energy 1/2 sum rho|u|^2} over fluid
+ * cells, summed in FP64 in a fixed order (deterministic); for a batch context
+ * it receives 5 values per domain.  A non-NULL sums_host synchronises.
+ */
+int lbm_moments(lbm_ctx *ctx, void *rho, void *u, int dtype, double *sums_host);
+
+/*
+ * Start recording a tape for lbm_backward: a bit-exact checkpoint of the
+ * state now and every K >= 1 steps after it.  The segment between
+ * checkpoints is recomputed during the backward pass.  LBM_ENOMEM if the
+ * checkpoints for max_steps steps plus a K-state recompute ring do not fit.
+ */
+int lbm_tape_begin(lbm_ctx *ctx, int K, int max_steps);
+
+/* Stop recording (the tape stays available to lbm_backward). */
+int lbm_tape_end(lbm_ctx *ctx);
+
+/* Drop the tape and free its memory. */
+int lbm_tape_free(lbm_ctx *ctx);
+
+/*
+ * Discrete adjoint of the recorded steps (the gradient the paper obtains from
+ * jax.grad through `step`, Sec. 3.6), seeded at the final state by a loss
+ * L(rho, u) of the final moments:
+ *   dL_drho : N values, dL_du : D x N values (component-major), device
+ *             pointers of `dtype` (LBM_F64 / LBM_F32); either may be NULL (= 0).
+ * Outputs (each nullable; all accumulate nothing -- they are overwritten):
+ *   dL_ds    : device float32[N], gradient w.r.t. the solid fraction s
+ *              (zero if no s field is set);
+ *   dL_dtau  : host double[n_domains], gradient w.r.t. each domain's tau;
+ *   dL_duw   : host double[n_domains * 6 * 3], gradient w.r.t. each face's
+ *              wall velocity (LBM_WALL faces only; other entries 0).
+ * The forward state is left unchanged.  Synchronises.  LBM_ESTATE without a
+ * tape or if the state moved since the tape ended.
+ */
+int lbm_backward(lbm_ctx *ctx, const void *dL_drho, const void *dL_du, int dtype,
+                 float *dL_ds, double *dL_dtau, double *dL_duw);
+
+/*
+ * Capture n_steps >= 1 steps into a HIP graph that lbm_graph_launch replays
+ * with one launch (batch and single contexts).  The graph reads the state at
+ * launch time; it is invalidated by lbm_init_equilibrium / lbm_load /
+ * lbm_set_* calls.
+ */
+int lbm_capture_graph(lbm_ctx *ctx, int n_steps);
+int lbm_graph_launch(lbm_ctx *ctx);
+
+/*
+ * Checkpoint / resume (Sec. 3.7): lbm_state_bytes gives the size of the
+ * opaque image; lbm_save copies it to host memory (synchronises), lbm_load
+ * restores it (bit-exact; the step counter and pattern parity included).
+ */
+size_t lbm_state_bytes(const lbm_ctx *ctx);
+int lbm_save(lbm_ctx *ctx, void *host, size_t bytes);
+int lbm_load(lbm_ctx *ctx, const void *host, size_t bytes);
+
+/* Wait for all work of the context; returns LBM_EDEVICE on a device fault. */
+int lbm_sync(lbm_ctx *ctx);
+
+/*
+ * Streaming copy of `bytes` bytes from src to dst on `hip_stream` (device
+ * pointers, 16-byte aligned, bytes a multiple of 16): the bandwidth probe that
+ * measures the achievable HBM copy rate, the empirical roofline ceiling.
+ */
+int lbm_copy_probe(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -1,0 +1,620 @@
+// capi.hip -- host side of liblbm.so: the C-ABI declared in include/lbm.h.
+//
+// A context owns the population state (one buffer for the in-place pattern,
+// two for the double-buffer one), the solid flags, the solid-fraction field,
+// reduction scratch, the adjoint tape and captured graphs.  Every argument is
+// checked before any device work.  Device memory is allocated on the device
+// that is current at the first lbm_init_equilibrium.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "ctx.hpp"
+#include "kernels.hpp"
+
+using namespace lbm;
+
+static thread_local std::string g_err;
+
+int lbm::fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int lbm::hip_fail(hipError_t e, const char *what) {
+    if (e == hipErrorOutOfMemory) return fail(LBM_ENOMEM, "%s: out of device memory", what);
+    return fail(LBM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+extern "C" const char *lbm_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char *lbm_version(void) { return "lbm-mi355x 0.1 (gfx950)"; }
+
+// ---------------------------------------------------------------------------
+// validation and setup
+// ---------------------------------------------------------------------------
+static int lattice_q(int lattice) { return lattice == LBM_D2Q9 ? 9 : (lattice == LBM_D3Q19 ? 19 : 27); }
+
+int lbm::validate_domain(int lattice, int nx, int ny, int nz, double tau, const lbm_bc *bc) {
+    if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19 && lattice != LBM_D3Q27)
+        return fail(LBM_EINVAL, "unknown lattice %d", lattice);
+    if (nx < 1 || ny < 1) return fail(LBM_EINVAL, "nx, ny must be >= 1 (got %d, %d)", nx, ny);
+    if (lattice == LBM_D2Q9) {
+        if (nz != 0 && nz != 1) return fail(LBM_EINVAL, "D2Q9 needs nz = 0 or 1 (got %d)", nz);
+    } else if (nz < 1) {
+        return fail(LBM_EINVAL, "3-D lattices need nz >= 1 (got %d)", nz);
+    }
+    const int64_t N = (int64_t)nx * ny * (nz < 1 ? 1 : nz);
+    if (N >= ((int64_t)1 << 31)) return fail(LBM_EINVAL, "grid has %lld cells; the limit is 2^31 - 1", (long long)N);
+    if (!(tau > 0.5) || !std::isfinite(tau)) return fail(LBM_EINVAL, "tau must be finite and > 1/2 (got %g)", tau);
+    if (!bc) return LBM_OK;
+    const int naxes = (lattice == LBM_D2Q9) ? 2 : 3;
+    const int n[3] = {nx, ny, nz < 1 ? 1 : nz};
+    int open_axis = -1;
+    for (int a = 0; a < naxes; ++a) {
+        const lbm_face &lo = bc->face[2 * a], &hi = bc->face[2 * a + 1];
+        for (const lbm_face *F : {&lo, &hi}) {
+            if (F->type < LBM_PERIODIC || F->type > LBM_EQ_OUTFLOW)
+                return fail(LBM_EINVAL, "face %d: unknown boundary type %d", (int)(F - bc->face), F->type);
+            for (int c = 0; c < 3; ++c)
+                if (!std::isfinite(F->u[c])) return fail(LBM_EINVAL, "face %d: velocity not finite", (int)(F - bc->face));
+        }
+        if ((lo.type == LBM_PERIODIC) != (hi.type == LBM_PERIODIC))
+            return fail(LBM_EINVAL, "axis %d: periodic must be set on both faces or neither", a);
+        for (int sd = 0; sd < 2; ++sd) {
+            const lbm_face &F = bc->face[2 * a + sd];
+            if (F.type == LBM_WALL && F.u[a] != 0.0)
+                return fail(LBM_EINVAL, "face %d: a wall velocity must be tangential", 2 * a + sd);
+            if (F.type == LBM_ZOUHE_VELOCITY && std::fabs(F.u[a]) >= 1.0)
+                return fail(LBM_EINVAL, "face %d: inlet normal velocity must be below 1", 2 * a + sd);
+            if ((F.type == LBM_ZOUHE_PRESSURE || F.type == LBM_EQ_OUTFLOW) && !(F.rho > 0.0))
+                return fail(LBM_EINVAL, "face %d: density must be > 0", 2 * a + sd);
+            if (F.type == LBM_ZOUHE_VELOCITY || F.type == LBM_ZOUHE_PRESSURE || F.type == LBM_EQ_OUTFLOW) {
+                if (open_axis >= 0 && open_axis != a)
+                    return fail(LBM_EINVAL, "Zou-He / outflow faces must all lie on one axis");
+                open_axis = a;
+                if (n[a] < 2) return fail(LBM_EINVAL, "axis %d carries an open face and needs >= 2 cells", a);
+            }
+        }
+        if (lattice == LBM_D2Q9) {
+            for (int sd = 0; sd < 2; ++sd)
+                if (bc->face[2 * a + sd].u[2] != 0.0)
+                    return fail(LBM_EINVAL, "face %d: a 2-D lattice has no z velocity", 2 * a + sd);
+        }
+    }
+    return LBM_OK;
+}
+
+template <class CT>
+static const FaceTab<CT> *face_table(const lbm_ctx *c);
+template <>
+const FaceTab<double> *face_table<double>(const lbm_ctx *c) { return c->ftd; }
+template <>
+const FaceTab<float> *face_table<float>(const lbm_ctx *c) { return c->ftf; }
+
+template <class CT>
+static void host_face_table(FaceTab<CT> &F, const lbm_face *iface) {
+    std::memset(&F, 0, sizeof F);
+    for (int f = 0; f < 6; ++f) {
+        for (int a = 0; a < 3; ++a) F.uw[f][a] = (CT)iface[f].u[a];
+        F.rho[f] = (CT)iface[f].rho;
+        F.type[f] = iface[f].type;
+    }
+}
+
+// Upload the face tables (device copies of the per-face data).
+static int upload_faces(lbm_ctx *c) {
+    if (!c->ftd) {
+        int rc = dev_alloc((void **)&c->ftd, sizeof(FaceTab<double>), "face table");
+        if (!rc) rc = dev_alloc((void **)&c->ftf, sizeof(FaceTab<float>), "face table");
+        if (rc) return rc;
+    }
+    FaceTab<double> hd;
+    FaceTab<float> hf;
+    host_face_table(hd, c->iface);
+    host_face_table(hf, c->iface);
+    hipError_t e = hipMemcpy(c->ftd, &hd, sizeof hd, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->ftf, &hf, sizeof hf, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "face table upload");
+    return LBM_OK;
+}
+
+// Fill the internal-axis parameter block (both precisions).
+template <class CT>
+static void fill_params(Params<CT> &p, const lbm_ctx *c) {
+    std::memset(&p, 0, sizeof p);
+    p.nX = c->nX;
+    p.nY = c->nY;
+    p.nZ = c->nZ;
+    p.sX = c->nY * c->nZ;
+    p.sY = c->nZ;
+    p.zblocks = c->zblocks;
+    p.plane = c->plane;
+    p.omega = (CT)(1.0 / c->tau);
+    p.rho0 = (CT)c->opt.rho0;
+    for (int f = 0; f < 6; ++f) {
+        const lbm_face &F = c->iface[f];
+        p.ftype[f] = (uint8_t)F.type;
+        for (int a = 0; a < 3; ++a) p.uw[f][a] = (CT)F.u[a];
+        p.frho[f] = (CT)F.rho;
+        if (F.type == LBM_WALL) {
+            p.wallmask |= 1u << f;
+            if (F.u[0] == 0.0 && F.u[1] == 0.0 && F.u[2] == 0.0) p.staticmask |= 1u << f;
+        }
+        if (F.type == LBM_ZOUHE_VELOCITY || F.type == LBM_ZOUHE_PRESSURE) p.zhmask |= 1u << f;
+    }
+    p.zh_pending = c->t > 0 ? 1 : 0;
+    p.ft = face_table<CT>(c);
+    p.flags = c->flags;
+    p.nbm = c->nbm;
+    p.s = c->s;
+}
+
+void lbm::refresh_params(lbm_ctx *c) {
+    fill_params(c->pd, c);
+    fill_params(c->pf, c);
+}
+
+// internal faces / velocities from the caller's (external) description
+static void map_faces(lbm_ctx *c, const lbm_bc *bc) {
+    for (int f = 0; f < 6; ++f) {
+        c->iface[f] = lbm_face{};
+        c->iface[f].type = LBM_PERIODIC;
+        c->iface[f].rho = 1.0;
+    }
+    if (!bc) return;
+    if (c->D == 3) {
+        for (int f = 0; f < 6; ++f) c->iface[f] = bc->face[f];
+    } else {
+        // 2-D (x, y) -> internal (Y, Z); internal X is a dummy axis of length 1
+        for (int f = 0; f < 4; ++f) {
+            lbm_face F = bc->face[f];
+            lbm_face G = F;
+            G.u[0] = 0.0;
+            G.u[1] = F.u[0];
+            G.u[2] = F.u[1];
+            c->iface[f + 2] = G;
+        }
+    }
+}
+
+static void setup_shape(lbm_ctx *c, int lattice, int nx, int ny, int nz, double tau) {
+    c->lattice = lattice;
+    c->Q = lattice_q(lattice);
+    c->D = lattice == LBM_D2Q9 ? 2 : 3;
+    c->nx = nx;
+    c->ny = ny;
+    c->nz = (lattice == LBM_D2Q9) ? 1 : nz;
+    if (c->D == 3) {
+        c->nX = nx;
+        c->nY = ny;
+        c->nZ = nz;
+    } else {
+        c->nX = 1;
+        c->nY = nx;
+        c->nZ = ny;
+    }
+    c->N = (int64_t)c->nX * c->nY * c->nZ;
+    c->plane = (c->N + 127) / 128 * 128;
+    c->tau = tau;
+    int blk = (c->nZ + 63) / 64 * 64;
+    if (blk > kMaxBlock) blk = kMaxBlock;
+    c->block = blk;
+    c->zblocks = (c->nZ + blk - 1) / blk;
+    c->grid = (int64_t)c->nX * c->nY * c->zblocks;
+}
+
+size_t lbm::storage_size(int storage) {
+    switch (storage) {
+        case LBM_F64: return 8;
+        case LBM_F32: return 4;
+        default: return 2;
+    }
+}
+
+extern "C" lbm_ctx *lbm_create(int lattice, int nx, int ny, int nz, double tau, const lbm_bc *bc) {
+    if (validate_domain(lattice, nx, ny, nz, tau, bc) != LBM_OK) return nullptr;
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) {
+        fail(LBM_ENOMEM, "host allocation failed");
+        return nullptr;
+    }
+    setup_shape(c, lattice, nx, ny, nz, tau);
+    map_faces(c, bc);
+    if (bc) c->bc = *bc;
+    c->opt.storage = LBM_F32;
+    c->opt.compute = LBM_F32;
+    c->opt.pattern = LBM_INPLACE;
+    c->opt.rho0 = 1.0;
+    c->ndomains = 1;
+    refresh_params(c);
+    g_err.clear();
+    return c;
+}
+
+extern "C" int lbm_set_options(lbm_ctx *c, const lbm_options *o) {
+    if (!c || !o) return fail(LBM_EINVAL, "null argument");
+    if (c->A) return fail(LBM_ESTATE, "options must be set before the state exists (first lbm_init_equilibrium)");
+    if (o->storage < LBM_F64 || o->storage > LBM_BF16) return fail(LBM_EINVAL, "unknown storage type %d", o->storage);
+    if (o->compute != LBM_F64 && o->compute != LBM_F32) return fail(LBM_EINVAL, "unknown compute type %d", o->compute);
+    if ((o->storage == LBM_F64) != (o->compute == LBM_F64))
+        return fail(LBM_EUNSUPPORTED, "F64 compute goes with F64 storage only; F32/F16/BF16 storage computes in F32");
+    if (o->pattern != LBM_INPLACE && o->pattern != LBM_DOUBLE) return fail(LBM_EINVAL, "unknown pattern %d", o->pattern);
+    if (!(o->rho0 > 0.0) || !std::isfinite(o->rho0)) return fail(LBM_EINVAL, "rho0 must be > 0");
+    if (c->batch && o->pattern != LBM_INPLACE) return fail(LBM_EUNSUPPORTED, "batch contexts use the in-place pattern");
+    c->opt = *o;
+    refresh_params(c);
+    return LBM_OK;
+}
+
+extern "C" int lbm_set_stream(lbm_ctx *c, void *s) {
+    if (!c) return fail(LBM_EINVAL, "null context");
+    c->stream = static_cast<hipStream_t>(s);
+    drop_graph(c);
+    return LBM_OK;
+}
+
+static int ensure_device(lbm_ctx *c) {
+    if (c->device < 0) {
+        int d = 0;
+        hipError_t e = hipGetDevice(&d);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+        c->device = d;
+    }
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    return LBM_OK;
+}
+
+int lbm::dev_alloc(void **p, size_t bytes, const char *what) {
+    *p = nullptr;
+    if (bytes == 0) return LBM_OK;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "hipMalloc(%zu bytes) for %s: %s", bytes, what,
+                    hipGetErrorString(e));
+    }
+    return LBM_OK;
+}
+
+void lbm::dev_free(void *&p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+static int ensure_state(lbm_ctx *c) {
+    int rc = ensure_device(c);
+    if (rc) return rc;
+    if (c->A) return LBM_OK;
+    const size_t bytes = (size_t)c->Q * (size_t)c->plane * storage_size(c->opt.storage);
+    rc = dev_alloc(&c->A, bytes, "population state");
+    if (rc) return rc;
+    if (c->opt.pattern == LBM_DOUBLE) {
+        rc = dev_alloc(&c->B, bytes, "second population buffer");
+        if (rc) {
+            dev_free(c->A);
+            return rc;
+        }
+    }
+    const size_t prow = (size_t)(c->batch ? c->bgrid : c->grid);
+    rc = dev_alloc((void **)&c->partial, prow * 5 * sizeof(double), "reduction scratch");
+    if (!rc) rc = dev_alloc((void **)&c->sums_dev, (size_t)c->ndomains * 5 * sizeof(double), "sums");
+    if (!rc) rc = dev_alloc((void **)&c->rbeg, (size_t)c->ndomains * sizeof(int64_t), "reduction rows");
+    if (!rc) rc = dev_alloc((void **)&c->rend, (size_t)c->ndomains * sizeof(int64_t), "reduction rows");
+    if (!rc) rc = upload_faces(c);
+    if (rc) {
+        free_all(c);
+        return rc;
+    }
+    std::vector<int64_t> b(c->ndomains), e(c->ndomains);
+    if (!c->batch) {
+        b[0] = 0;
+        e[0] = c->grid;
+    } else {
+        for (int d = 0; d < c->ndomains; ++d) {
+            b[d] = c->dom[d].block0;
+            e[d] = c->dom[d].block0 + c->dom[d].nblocks;
+        }
+    }
+    hipError_t he = hipMemcpy(c->rbeg, b.data(), b.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMemcpy(c->rend, e.data(), e.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (he != hipSuccess) {
+        free_all(c);
+        return hip_fail(he, "hipMemcpy");
+    }
+    if (c->batch) {
+        rc = batch_upload(c);
+        if (rc) {
+            free_all(c);
+            return rc;
+        }
+    }
+    refresh_params(c);
+    return LBM_OK;
+}
+
+void lbm::free_all(lbm_ctx *c) {
+    drop_graph(c);
+    tape_release(c);
+    dev_free(c->A);
+    dev_free(c->B);
+    dev_free((void *&)c->partial);
+    dev_free((void *&)c->sums_dev);
+    dev_free((void *&)c->rbeg);
+    dev_free((void *&)c->rend);
+    dev_free((void *&)c->flags);
+    dev_free((void *&)c->nbm);
+    dev_free((void *&)c->s);
+    dev_free((void *&)c->ftd);
+    dev_free((void *&)c->ftf);
+    batch_release(c);
+}
+
+extern "C" void lbm_destroy(lbm_ctx *c) {
+    if (!c) return;
+    if (c->device >= 0) {
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
+    }
+    free_all(c);
+    delete c;
+}
+
+Launch lbm::make_launch(lbm_ctx *c) {
+    Launch g;
+    g.lattice = c->lattice;
+    g.storage = c->opt.storage;
+    g.params = (c->opt.storage == LBM_F64) ? (const void *)&c->pd : (const void *)&c->pf;
+    g.A = c->A;
+    g.B = c->B;
+    g.grid = (unsigned)c->grid;
+    g.block = (unsigned)c->block;
+    g.stream = c->stream;
+    return g;
+}
+
+extern "C" int lbm_set_solid(lbm_ctx *c, const uint8_t *flags, int on_device) {
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if (on_device != 0 && on_device != 1) return fail(LBM_EINVAL, "on_device must be 0 or 1");
+    if (c->batch) return fail(LBM_EUNSUPPORTED, "solid cells are not supported on batch contexts");
+    int rc = ensure_device(c);
+    if (rc) return rc;
+    drop_graph(c);
+    if (!flags) {
+        dev_free((void *&)c->flags);
+        dev_free((void *&)c->nbm);
+        refresh_params(c);
+        return LBM_OK;
+    }
+    const size_t N = (size_t)c->N;
+    if (!c->flags) {
+        rc = dev_alloc((void **)&c->flags, N, "solid flags");
+        if (!rc) rc = dev_alloc((void **)&c->nbm, N * sizeof(uint32_t), "solid neighbour masks");
+        if (rc) {
+            dev_free((void *&)c->flags);
+            dev_free((void *&)c->nbm);
+            return rc;
+        }
+    }
+    void *tmp = nullptr;
+    rc = dev_alloc(&tmp, N, "solid input");
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(tmp, flags, N, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) {
+        refresh_params(c);
+        Launch g = make_launch(c);
+        g.params = &c->pf;
+        e = launch_solid(c->lattice, g, static_cast<const uint8_t *>(tmp), c->flags, c->nbm);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dev_free(tmp);
+    if (e != hipSuccess) return hip_fail(e, "lbm_set_solid");
+    refresh_params(c);
+    return LBM_OK;
+}
+
+extern "C" int lbm_set_solid_fraction(lbm_ctx *c, const float *s, int on_device) {
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if (on_device != 0 && on_device != 1) return fail(LBM_EINVAL, "on_device must be 0 or 1");
+    int rc = ensure_device(c);
+    if (rc) return rc;
+    drop_graph(c);
+    if (!s) {
+        dev_free((void *&)c->s);
+        refresh_params(c);
+        return LBM_OK;
+    }
+    const size_t N = (size_t)c->N;
+    if (!c->s) {
+        rc = dev_alloc((void **)&c->s, N * sizeof(float), "solid fraction");
+        if (rc) return rc;
+    }
+    hipError_t e = hipMemcpyAsync(c->s, s, N * sizeof(float), on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                  c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "lbm_set_solid_fraction");
+    refresh_params(c);
+    return LBM_OK;
+}
+
+extern "C" int lbm_init_equilibrium(lbm_ctx *c, const void *rho, const void *u, int dtype) {
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if ((rho || u) && dtype != LBM_F64 && dtype != LBM_F32) return fail(LBM_EINVAL, "dtype must be LBM_F64 or LBM_F32");
+    int rc = ensure_state(c);
+    if (rc) return rc;
+    drop_graph(c);
+    tape_release(c);
+    c->t = 0;
+    c->moved_since_tape = true;
+    refresh_params(c);
+    hipError_t e;
+    if (c->batch) e = batch_init(c, rho, u, dtype == LBM_F64);
+    else e = launch_init(make_launch(c), rho, u, dtype == LBM_F64, c->N);
+    if (e != hipSuccess) return hip_fail(e, "lbm_init_equilibrium");
+    return LBM_OK;
+}
+
+// One forward step of the whole context (no tape bookkeeping).
+hipError_t lbm::forward_step(lbm_ctx *c) {
+    if (c->batch) {
+        hipError_t e = batch_step(c);
+        c->t += 1;
+        return e;
+    }
+    c->pd.zh_pending = c->pf.zh_pending = c->t > 0 ? 1 : 0;
+    Launch g = make_launch(c);
+    int mode;
+    if (c->opt.pattern == LBM_INPLACE) mode = (int)(c->t & 1);
+    else mode = 2;
+    hipError_t e = launch_step(g, mode, c->s != nullptr);
+    if (c->opt.pattern == LBM_DOUBLE) std::swap(c->A, c->B);
+    c->t += 1;
+    return e;
+}
+
+extern "C" int lbm_step(lbm_ctx *c, int n) {
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+    if (!c->A) return fail(LBM_ESTATE, "state not initialised (call lbm_init_equilibrium)");
+    int rc = ensure_device(c);
+    if (rc) return rc;
+    for (int k = 0; k < n; ++k) {
+        hipError_t e = forward_step(c);
+        if (e != hipSuccess) return hip_fail(e, "lbm_step");
+        rc = tape_after_step(c);
+        if (rc) return rc;
+    }
+    if (n > 0 && !c->tape_recording) c->moved_since_tape = true;
+    return LBM_OK;
+}
+
+extern "C" int64_t lbm_time(const lbm_ctx *c) { return c ? c->t : -1; }
+
+extern "C" int lbm_moments(lbm_ctx *c, void *rho, void *u, int dtype, double *sums_host) {
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if ((rho || u) && dtype != LBM_F64 && dtype != LBM_F32) return fail(LBM_EINVAL, "dtype must be LBM_F64 or LBM_F32");
+    if (!c->A) return fail(LBM_ESTATE, "state not initialised (call lbm_init_equilibrium)");
+    int rc = ensure_device(c);
+    if (rc) return rc;
+    refresh_params(c);
+    hipError_t e;
+    const bool odd = (c->opt.pattern == LBM_INPLACE) && (c->t & 1);
+    if (c->batch) e = batch_moments(c, odd, rho, u, dtype == LBM_F64, c->partial);
+    else e = launch_moments(make_launch(c), odd, rho, u, dtype == LBM_F64, c->partial, c->N);
+    if (e == hipSuccess) e = launch_reduce(c->partial, c->rbeg, c->rend, c->sums_dev, c->ndomains, c->stream);
+    if (e == hipSuccess && sums_host) {
+        std::vector<double> tmp((size_t)c->ndomains * 5);
+        e = hipMemcpyAsync(tmp.data(), c->sums_dev, tmp.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess) {
+            // internal axes -> caller axes
+            for (int d = 0; d < c->ndomains; ++d) {
+                double *o = sums_host + 5 * d;
+                const double *m = tmp.data() + 5 * d;
+                o[0] = m[0];
+                if (c->D == 3) {
+                    o[1] = m[1];
+                    o[2] = m[2];
+                    o[3] = m[3];
+                } else {
+                    o[1] = m[2];
+                    o[2] = m[3];
+                    o[3] = 0.0;
+                }
+                o[4] = m[4];
+            }
+        }
+    }
+    if (e != hipSuccess) return hip_fail(e, "lbm_moments");
+    return LBM_OK;
+}
+
+extern "C" int lbm_sync(lbm_ctx *c) {
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if (c->device < 0) return LBM_OK;
+    (void)hipSetDevice(c->device);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "lbm_sync");
+    return LBM_OK;
+}
+
+// ---- checkpoint / resume ----------------------------------------------------
+struct StateHeader {
+    char magic[8];
+    int32_t lattice, storage, pattern, Q;
+    int64_t N, plane, t;
+};
+
+extern "C" size_t lbm_state_bytes(const lbm_ctx *c) {
+    if (!c) return 0;
+    return sizeof(StateHeader) + (size_t)c->Q * (size_t)c->plane * storage_size(c->opt.storage);
+}
+
+extern "C" int lbm_save(lbm_ctx *c, void *host, size_t bytes) {
+    if (!c || !host) return fail(LBM_EINVAL, "null argument");
+    if (!c->A) return fail(LBM_ESTATE, "state not initialised");
+    if (bytes < lbm_state_bytes(c)) return fail(LBM_EINVAL, "buffer too small: need %zu bytes", lbm_state_bytes(c));
+    int rc = ensure_device(c);
+    if (rc) return rc;
+    StateHeader h;
+    std::memcpy(h.magic, "LBMSTAT1", 8);
+    h.lattice = c->lattice;
+    h.storage = c->opt.storage;
+    h.pattern = c->opt.pattern;
+    h.Q = c->Q;
+    h.N = c->N;
+    h.plane = c->plane;
+    h.t = c->t;
+    std::memcpy(host, &h, sizeof h);
+    const size_t sb = lbm_state_bytes(c) - sizeof h;
+    hipError_t e = hipMemcpyAsync(static_cast<char *>(host) + sizeof h, c->A, sb, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "lbm_save");
+    return LBM_OK;
+}
+
+extern "C" int lbm_load(lbm_ctx *c, const void *host, size_t bytes) {
+    if (!c || !host) return fail(LBM_EINVAL, "null argument");
+    if (bytes < sizeof(StateHeader)) return fail(LBM_EINVAL, "buffer too small");
+    StateHeader h;
+    std::memcpy(&h, host, sizeof h);
+    if (std::memcmp(h.magic, "LBMSTAT1", 8) != 0) return fail(LBM_EINVAL, "not a state image");
+    if (h.lattice != c->lattice || h.storage != c->opt.storage || h.pattern != c->opt.pattern || h.N != c->N ||
+        h.plane != c->plane || h.Q != c->Q)
+        return fail(LBM_EINVAL, "state image does not match this context (lattice/storage/pattern/shape)");
+    if (bytes < lbm_state_bytes(c)) return fail(LBM_EINVAL, "buffer too small: need %zu bytes", lbm_state_bytes(c));
+    int rc = ensure_state(c);
+    if (rc) return rc;
+    drop_graph(c);
+    tape_release(c);
+    const size_t sb = lbm_state_bytes(c) - sizeof h;
+    hipError_t e = hipMemcpyAsync(c->A, static_cast<const char *>(host) + sizeof h, sb, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "lbm_load");
+    c->t = h.t;
+    c->moved_since_tape = true;
+    refresh_params(c);
+    return LBM_OK;
+}
+
+extern "C" int lbm_copy_probe(void *dst, const void *src, size_t bytes, void *stream) {
+    if (!dst || !src) return fail(LBM_EINVAL, "null pointer");
+    if ((bytes & 15) || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15))
+        return fail(LBM_EINVAL, "pointers and size must be 16-byte aligned");
+    hipError_t e = launch_copy(dst, src, bytes, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "lbm_copy_probe");
+    return LBM_OK;
+}

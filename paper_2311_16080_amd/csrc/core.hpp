@@ -1,0 +1,343 @@
+// core.hpp -- per-cell device arithmetic and the kernel parameter block.
+//
+// State format.  Populations are stored as deviations from the rest state,
+// h_i = f_i - w_i rho0, one plane per direction (structure of arrays, Z
+// contiguous).  FP16/BF16 storage keeps h_i / w_i (rounded to nearest even)
+// and the kernels widen to FP32.  This is the renormalisation around zero
+// that the paper says single precision needs (Sec. 4.1).
+//
+// Step semantics (paper Sec. 3.6: collide, post-collision BC, stream,
+// post-stream BC).  One kernel pass per time step does, per fluid cell:
+//   read   : the Q populations f(x, t) (post-stream, post-boundary);
+//   close  : on a Zou-He face cell, the unknown populations from the known
+//            ones (the post-stream BC of the previous step, applied where the
+//            knowns are first all in registers);
+//   collide: moments (eqs. density, velocity), equilibrium (eq. feq), BGK
+//            relaxation (eq. LBM-BGK), optional partial bounce-back mix;
+//   write  : each post-collision value to the cell it streams to
+//            (eq. streaming), or, where that cell is not fluid, the boundary
+//            value of the population that comes back to this cell instead:
+//            halfway bounce-back (+ moving-wall term), or the equilibrium of an
+//            outflow / perimeter face.  These are exactly the values the next
+//            step would have to fill, computed where they are known.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <utility>
+
+#include "lattice.hpp"
+
+namespace lbm {
+
+enum : uint8_t { F_PERIODIC = 0, F_WALL = 1, F_ZH_VEL = 2, F_ZH_PRES = 3, F_OUT = 4 };
+
+constexpr int kMaxBlock = 256;
+
+// Per-face data read with a runtime face index (boundary lanes only).  Kept in
+// device memory: indexing the by-value kernel argument block with a runtime
+// index would force a private copy of the whole block.
+template <class CT>
+struct FaceTab {
+    CT uw[6][3];
+    CT rho[6];
+    int type[6];
+    int pad[2];
+};
+
+template <class CT>
+struct Params {
+    int nX, nY, nZ;        // internal extents (Z contiguous)
+    int sX, sY;            // cell strides of X and Y (Z stride 1)
+    int zblocks;           // blocks per Z row
+    int64_t plane;         // elements per direction plane
+    uint32_t wallmask;     // faces of type wall
+    uint32_t staticmask;   // wall faces with zero velocity
+    uint32_t zhmask;       // Zou-He faces
+    uint32_t pad0;
+    uint8_t ftype[8];
+    CT uw[6][3];           // wall / inlet velocity per face (internal axes)
+    CT frho[6];            // face density (pressure / outflow)
+    CT omega;              // 1 / tau
+    CT rho0;
+    int zh_pending;        // the state read needs the Zou-He closure (t > 0)
+    int pad1;
+    const uint8_t *flags;  // N bytes or null: bit0 solid, bit1 a neighbour is solid
+    const uint32_t *nbm;   // N words: bit k set when x - c_k is a solid cell
+    const float *s;        // N or null: partial bounce-back solid fraction
+    const FaceTab<CT> *ft; // device copy of the face data
+};
+
+// ---- storage formats -------------------------------------------------------
+struct bf16_t {
+    uint16_t bits;
+};
+
+template <class ST>
+struct Store;
+
+template <>
+struct Store<double> {
+    using CT = double;
+    static constexpr bool scaled = false;
+    __device__ static double ld(const double *p) { return *p; }
+    __device__ static void st(double *p, double v) { *p = v; }
+};
+template <>
+struct Store<float> {
+    using CT = float;
+    static constexpr bool scaled = false;
+    __device__ static float ld(const float *p) { return *p; }
+    __device__ static void st(float *p, float v) { *p = v; }
+};
+template <>
+struct Store<_Float16> {
+    using CT = float;
+    static constexpr bool scaled = true;
+    __device__ static float ld(const _Float16 *p) { return (float)*p; }
+    __device__ static void st(_Float16 *p, float v) { *p = (_Float16)v; }  // round to nearest even
+};
+template <>
+struct Store<bf16_t> {
+    using CT = float;
+    static constexpr bool scaled = true;
+    __device__ static float ld(const bf16_t *p) { return __uint_as_float(((uint32_t)p->bits) << 16); }
+    __device__ static void st(bf16_t *p, float v) {
+        uint32_t u = __float_as_uint(v);
+        uint16_t r;
+        if ((u & 0x7fffffffu) > 0x7f800000u) r = (uint16_t)((u >> 16) | 0x40u);     // quiet NaN
+        else r = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);                // nearest even
+        p->bits = r;
+    }
+};
+
+// load / store of population i with the storage scale
+template <class L, class ST, int I>
+__device__ __forceinline__ typename Store<ST>::CT ldh(const ST *base, int64_t plane, int64_t cell) {
+    using CT = typename Store<ST>::CT;
+    CT v = Store<ST>::ld(base + (int64_t)I * plane + cell);
+    if constexpr (Store<ST>::scaled) v *= (CT)weight<L>(I);
+    return v;
+}
+template <class L, class ST, int I>
+__device__ __forceinline__ void sth(ST *base, int64_t plane, int64_t cell, typename Store<ST>::CT v) {
+    using CT = typename Store<ST>::CT;
+    if constexpr (Store<ST>::scaled) v *= (CT)(1.0 / weight<L>(I));
+    Store<ST>::st(base + (int64_t)I * plane + cell, v);
+}
+
+// compile-time loop
+template <int N, class F, int... Is>
+__device__ __forceinline__ void unroll_impl(F &&f, std::integer_sequence<int, Is...>) {
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void unroll(F &&f) {
+    unroll_impl<N>(f, std::make_integer_sequence<int, N>{});
+}
+
+// ---- neighbour classification (only for cells on a face or next to a solid)
+enum : int { NB_FLUID = 0, NB_WALL = 1, NB_ZH = 2, NB_OUT = 3 };
+
+struct Nb {
+    int kind;
+    int face;      // moving wall face (NB_WALL, -1 = static) or open face
+    int64_t cell;  // NB_FLUID: source cell (periodic wrap applied)
+};
+
+// Source y = x - c_k of population k at cell (X, Y, Z).
+template <class L, class CT>
+__device__ __forceinline__ Nb classify_src(const Params<CT> &p, int X, int Y, int Z, int k, uint32_t nbm) {
+    int yx = X - L::c[k][0], yy = Y - L::c[k][1], yz = Z - L::c[k][2];
+    uint32_t crossed = 0;
+    if (yx < 0) { if (p.ftype[0] == F_PERIODIC) yx += p.nX; else crossed |= 1u; }
+    else if (yx >= p.nX) { if (p.ftype[1] == F_PERIODIC) yx -= p.nX; else crossed |= 2u; }
+    if (yy < 0) { if (p.ftype[2] == F_PERIODIC) yy += p.nY; else crossed |= 4u; }
+    else if (yy >= p.nY) { if (p.ftype[3] == F_PERIODIC) yy -= p.nY; else crossed |= 8u; }
+    if (yz < 0) { if (p.ftype[4] == F_PERIODIC) yz += p.nZ; else crossed |= 16u; }
+    else if (yz >= p.nZ) { if (p.ftype[5] == F_PERIODIC) yz -= p.nZ; else crossed |= 32u; }
+    Nb r;
+    r.face = -1;
+    r.cell = 0;
+    if (!crossed) {
+        r.kind = ((nbm >> k) & 1u) ? NB_WALL : NB_FLUID;
+        r.cell = ((int64_t)yx * p.nY + yy) * p.nZ + yz;
+        return r;
+    }
+    const uint32_t walls = crossed & p.wallmask;
+    if (walls) {
+        r.kind = NB_WALL;
+        r.face = (walls & p.staticmask) ? -1 : (int)__builtin_ctz(walls);
+        return r;
+    }
+    r.face = (int)__builtin_ctz(crossed);
+    r.kind = (p.ft->type[r.face] == F_OUT) ? NB_OUT : NB_ZH;
+    return r;
+}
+
+// ---- equilibrium in deviation form: feq_i - w_i rho0 -------------------------
+template <class L, int I, class CT>
+__device__ __forceinline__ CT heq(CT drho, CT rho, CT ux, CT uy, CT uz, CT usq15) {
+    const CT cu = (CT)3 * ((CT)L::c[I][0] * ux + (CT)L::c[I][1] * uy + (CT)L::c[I][2] * uz);
+    return (CT)weight<L>(I) * (drho + rho * (cu + (CT)0.5 * cu * cu - usq15));
+}
+
+// ---- Zou-He closure at a face cell (the generic 2-D/3-D non-equilibrium
+// bounce-back; reduces to Zou & He's D2Q9 formulas, cited in Sec. 4.3) ------
+// Zou-He closure (non-equilibrium bounce-back; the paper cites Zou & He for
+// its inlet/outlet, Sec. 4.3) at a cell on open face `face` with inward
+// normal n.  U = {c.n = 1} unknown, Z = {c.n = 0}, O = {c.n = -1} known:
+//   velocity face: rho = (sum_Z f + 2 sum_O f) / (1 - u_w.n), u = u_w
+//   pressure face: rho = rho_w, u = n (1 - (sum_Z f + 2 sum_O f) / rho_w)
+//   f_i = f_opp(i) + 6 w_i rho c_i.u - sum_t c_it N_t               (i in U)
+//   N_t = (sum_Z f_j c_jt - 2/3 rho u_t) / sum_U c_kt^2            (t tangential)
+// In deviation variables the rho0 parts cancel except in rho itself
+// (sum_Z w + 2 sum_O w = 1).  The face is a runtime value and every choice
+// below is a value select, so the populations stay in registers.
+template <class L, class CT>
+__device__ __forceinline__ void zouhe(CT *h, const Params<CT> &p, int face) {
+    const int ax = face >> 1;
+    const int sg = (face & 1) ? -1 : 1;
+    int cn[L::Q];
+    unroll<L::Q>([&](auto I) {
+        const int ca = (ax == 0) ? L::c[I][0] : ((ax == 1) ? L::c[I][1] : L::c[I][2]);
+        cn[I] = sg * ca;
+    });
+    CT SZ = 0, SO = 0;
+    unroll<L::Q>([&](auto I) {
+        SZ += (cn[I] == 0) ? h[I] : (CT)0;
+        SO += (cn[I] == -1) ? h[I] : (CT)0;
+    });
+    const CT known = SZ + (CT)2 * SO;  // sum_Z f + 2 sum_O f - rho0
+    const FaceTab<CT> &F = *p.ft;
+    CT rho, u[3];
+    if (F.type[face] == F_ZH_VEL) {
+        u[0] = F.uw[face][0];
+        u[1] = F.uw[face][1];
+        u[2] = F.uw[face][2];
+        const CT un = (CT)sg * ((ax == 0) ? u[0] : ((ax == 1) ? u[1] : u[2]));
+        rho = p.rho0 + (known + p.rho0 * un) / ((CT)1 - un);
+    } else {
+        rho = F.rho[face];
+        const CT un = (rho - p.rho0 - known) / rho;
+        u[0] = (ax == 0) ? (CT)sg * un : (CT)0;
+        u[1] = (ax == 1) ? (CT)sg * un : (CT)0;
+        u[2] = (ax == 2) ? (CT)sg * un : (CT)0;
+    }
+    CT Nt[3];
+    unroll<3>([&](auto T) {
+        CT num = 0;
+        unroll<L::Q>([&](auto I) {
+            if constexpr (L::c[I][T] != 0) num += (cn[I] == 0) ? (CT)L::c[I][T] * h[I] : (CT)0;
+        });
+        const CT v = (num - (CT)(2.0 / 3.0) * rho * u[T]) * (CT)(1.0 / L::den_t);
+        Nt[T] = (ax == T) ? (CT)0 : v;
+    });
+    // in place: the opposite of an unknown is always a known, never rewritten
+    unroll<L::Q>([&](auto I) {
+        constexpr int O = opp<L>(I);
+        const CT cu = (CT)L::c[I][0] * u[0] + (CT)L::c[I][1] * u[1] + (CT)L::c[I][2] * u[2];
+        CT v = h[O] + (CT)(6.0 * weight<L>(I)) * rho * cu;
+        unroll<3>([&](auto T) {
+            if constexpr (L::c[I][T] != 0) v -= (CT)L::c[I][T] * Nt[T];
+        });
+        h[I] = (cn[I] == 1) ? v : h[I];
+    });
+}
+
+// Edge bits of a cell: which box faces it sits on.
+template <class CT>
+__device__ __forceinline__ uint32_t edge_bits(const Params<CT> &p, int X, int Y, int Z) {
+    return (uint32_t)(X == 0) | ((uint32_t)(X == p.nX - 1) << 1) | ((uint32_t)(Y == 0) << 2) |
+           ((uint32_t)(Y == p.nY - 1) << 3) | ((uint32_t)(Z == 0) << 4) | ((uint32_t)(Z == p.nZ - 1) << 5);
+}
+
+// Which directions have a source that is not a plain in-box fluid neighbour.
+template <class L>
+__device__ __forceinline__ uint32_t irregular_mask(uint32_t e, uint32_t nbm) {
+    uint32_t m = nbm;
+    unroll<L::Q>([&](auto I) {
+        constexpr uint32_t dm = src_face_bits<L>(I);
+        if constexpr (dm != 0)
+            if (e & dm) m |= 1u << I;
+    });
+    return m;
+}
+
+// Zou-He face of a cell (-1 if none): on an open Zou-He face and not on a wall face.
+template <class CT>
+__device__ __forceinline__ int zh_face_of(const Params<CT> &p, uint32_t e) {
+    const uint32_t z = e & p.zhmask;
+    if (!z || (e & p.wallmask)) return -1;
+    return (int)__builtin_ctz(z);
+}
+
+// Collision (eq. LBM-BGK) of the deviations h -> post-collision hp, returning
+// the moments.  Partial bounce-back: hp_i = (1 - s) h*_i + s h_opp(i).
+template <class L, class CT>
+__device__ __forceinline__ void collide(const CT *h, CT *hp, const Params<CT> &p, CT s, bool has_s,
+                                        CT &rho_out, CT &ux, CT &uy, CT &uz) {
+    CT drho = 0, jx = 0, jy = 0, jz = 0;
+    unroll<L::Q>([&](auto I) {
+        drho += h[I];
+        if constexpr (L::c[I][0] != 0) jx += (CT)L::c[I][0] * h[I];
+        if constexpr (L::c[I][1] != 0) jy += (CT)L::c[I][1] * h[I];
+        if constexpr (L::c[I][2] != 0) jz += (CT)L::c[I][2] * h[I];
+    });
+    const CT rho = p.rho0 + drho;
+    const CT inv = (CT)1 / rho;
+    ux = jx * inv;
+    uy = jy * inv;
+    uz = jz * inv;
+    const CT usq15 = (CT)1.5 * (ux * ux + uy * uy + uz * uz);
+    const CT om = p.omega;
+    unroll<L::Q>([&](auto I) {
+        const CT e = heq<L, I>(drho, rho, ux, uy, uz, usq15);
+        hp[I] = h[I] - om * (h[I] - e);
+    });
+    if (has_s) {
+        CT t[L::Q];
+        unroll<L::Q>([&](auto I) { t[I] = ((CT)1 - s) * hp[I] + s * h[opp<L>(I)]; });
+        unroll<L::Q>([&](auto I) { hp[I] = t[I]; });
+    }
+    rho_out = rho;
+}
+
+// Boundary value of population k = opp(i) at this cell when its source
+// x - c_k = x + c_i is not fluid (nb = classification of that source).
+//   wall / solid : hp_i + 6 w_k rho0 (c_k . u_w)          (halfway bounce-back)
+//   outflow      : feq_k(rho_face, u(x,t)) - w_k rho0
+//   Zou-He face, perimeter cell : equilibrium with (rho0, u_in) or (rho_w, u(x,t))
+//   Zou-He face, otherwise      : hp_i (unused: the closure replaces it)
+template <class L, int I, class CT>
+__device__ __forceinline__ CT fill_value(const Params<CT> &p, const Nb &nb, CT hpi, bool perimeter,
+                                         CT rho, CT ux, CT uy, CT uz) {
+    constexpr int K = opp<L>(I);
+    if (nb.kind == NB_WALL) {
+        if (nb.face < 0) return hpi;
+        const FaceTab<CT> &F = *p.ft;
+        const CT cu = (CT)L::c[K][0] * F.uw[nb.face][0] + (CT)L::c[K][1] * F.uw[nb.face][1] +
+                      (CT)L::c[K][2] * F.uw[nb.face][2];
+        return hpi + (CT)(6.0 * weight<L>(K)) * p.rho0 * cu;
+    }
+    if (nb.kind == NB_OUT || (nb.kind == NB_ZH && perimeter)) {
+        const FaceTab<CT> &F = *p.ft;
+        CT r, vx, vy, vz;
+        if (nb.kind == NB_ZH && F.type[nb.face] == F_ZH_VEL) {
+            r = p.rho0;
+            vx = F.uw[nb.face][0];
+            vy = F.uw[nb.face][1];
+            vz = F.uw[nb.face][2];
+        } else {
+            r = F.rho[nb.face];
+            vx = ux;
+            vy = uy;
+            vz = uz;
+        }
+        const CT usq15 = (CT)1.5 * (vx * vx + vy * vy + vz * vz);
+        return heq<L, K>(r - p.rho0, r, vx, vy, vz, usq15);
+    }
+    return hpi;
+    (void)rho;
+}
+
+}  // namespace lbm

@@ -1,0 +1,109 @@
+// ctx.hpp -- the context object behind the opaque lbm_ctx handle (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "kernels.hpp"
+
+namespace lbm {
+
+// One domain of a batch context.
+struct Domain {
+    int nx, ny, nz;       // caller axes
+    int nX, nY, nZ;       // internal axes
+    int64_t cell0;        // first packed cell
+    int64_t N;
+    int64_t block0;       // first block of this domain in a batch launch
+    int64_t nblocks;
+    int zblocks;
+    double tau;
+    lbm_face iface[6];    // internal faces
+};
+
+struct TapeState;
+struct BatchState;
+
+}  // namespace lbm
+
+struct lbm_ctx {
+    // shape
+    int lattice = 0, Q = 0, D = 0;
+    int nx = 0, ny = 0, nz = 0;      // caller axes
+    int nX = 0, nY = 0, nZ = 0;      // internal axes (Z contiguous)
+    int64_t N = 0;                   // cells
+    int64_t plane = 0;               // elements per direction plane
+    double tau = 1.0;
+    lbm_bc bc{};                     // faces as given
+    lbm_face iface[6]{};             // faces in internal axes
+    lbm_options opt{};
+    int block = 256, zblocks = 1;
+    int64_t grid = 1;
+
+    // device
+    int device = -1;
+    hipStream_t stream = nullptr;
+    void *A = nullptr, *B = nullptr;  // population buffers
+    uint8_t *flags = nullptr;
+    uint32_t *nbm = nullptr;
+    float *s = nullptr;
+    double *partial = nullptr, *sums_dev = nullptr;
+    int64_t *rbeg = nullptr, *rend = nullptr;
+    lbm::Params<double> pd{};
+    lbm::Params<float> pf{};
+    lbm::FaceTab<double> *ftd = nullptr;   // device face tables
+    lbm::FaceTab<float> *ftf = nullptr;
+
+    // time
+    int64_t t = 0;
+
+    // batch
+    bool batch = false;
+    int ndomains = 1;
+    std::vector<lbm::Domain> dom;
+    int64_t bgrid = 0;
+    lbm::BatchState *bs = nullptr;
+
+    // tape (adjoint)
+    lbm::TapeState *tape = nullptr;
+    bool tape_recording = false;
+    bool moved_since_tape = true;
+
+    // captured graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_steps = 0;
+    int64_t graph_t0 = 0;
+    void *graph_A = nullptr;
+};
+
+namespace lbm {
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+int validate_domain(int lattice, int nx, int ny, int nz, double tau, const lbm_bc *bc);
+void refresh_params(lbm_ctx *c);
+size_t storage_size(int storage);
+int dev_alloc(void **p, size_t bytes, const char *what);
+void dev_free(void *&p);
+void free_all(lbm_ctx *c);
+Launch make_launch(lbm_ctx *c);
+hipError_t forward_step(lbm_ctx *c);
+
+// graph.hip
+void drop_graph(lbm_ctx *c);
+
+// tape.hip
+int tape_after_step(lbm_ctx *c);
+void tape_release(lbm_ctx *c);
+
+// batch.hip
+int batch_upload(lbm_ctx *c);
+void batch_release(lbm_ctx *c);
+hipError_t batch_init(lbm_ctx *c, const void *rho, const void *u, bool f64);
+hipError_t batch_step(lbm_ctx *c);
+hipError_t batch_moments(lbm_ctx *c, bool odd, void *rho, void *u, bool f64, double *partial);
+
+}  // namespace lbm

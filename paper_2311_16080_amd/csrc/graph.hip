@@ -1,0 +1,75 @@
+// graph.hip -- capture of n forward steps into one HIP graph (replayed with a
+// single launch).
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "ctx.hpp"
+
+using namespace lbm;
+
+void lbm::drop_graph(lbm_ctx *c) {
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+    c->graph_steps = 0;
+}
+
+extern "C" int lbm_capture_graph(lbm_ctx *c, int n) {
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if (n < 1) return fail(LBM_EINVAL, "n_steps must be >= 1");
+    if (!c->A) return fail(LBM_ESTATE, "state not initialised");
+    if (!c->stream) return fail(LBM_EINVAL, "graph capture needs a non-null stream (lbm_set_stream)");
+    if (c->tape_recording) return fail(LBM_ESTATE, "cannot capture while a tape is recording");
+    (void)hipSetDevice(c->device);
+    drop_graph(c);
+    const int64_t t0 = c->t;
+    void *A0 = c->A, *B0 = c->B;
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < n && le == hipSuccess; ++k) le = forward_step(c);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->stream, &g);
+    c->t = t0;
+    c->A = A0;
+    c->B = B0;
+    refresh_params(c);
+    if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(le, "kernel launch during capture");
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    c->graph = g;
+    c->graph_exec = x;
+    c->graph_steps = n;
+    c->graph_t0 = t0;
+    c->graph_A = A0;
+    return LBM_OK;
+}
+
+extern "C" int lbm_graph_launch(lbm_ctx *c) {
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if (!c->graph_exec) return fail(LBM_ESTATE, "no graph captured");
+    if (c->tape_recording) return fail(LBM_ESTATE, "cannot replay a graph while a tape is recording");
+    const bool same_parity = ((c->t ^ c->graph_t0) & 1) == 0;
+    const bool same_buffers = c->A == c->graph_A;
+    const bool zh = c->pf.zhmask != 0;
+    if (!same_buffers || (c->opt.pattern == LBM_INPLACE && !same_parity) || (zh && ((c->t > 0) != (c->graph_t0 > 0))))
+        return fail(LBM_ESTATE, "the state's step parity / buffers differ from those at capture");
+    (void)hipSetDevice(c->device);
+    hipError_t e = hipGraphLaunch(c->graph_exec, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    c->t += c->graph_steps;
+    if (c->opt.pattern == LBM_DOUBLE && (c->graph_steps & 1)) std::swap(c->A, c->B);
+    c->moved_since_tape = true;
+    refresh_params(c);
+    return LBM_OK;
+}

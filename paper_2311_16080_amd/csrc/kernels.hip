@@ -1,0 +1,86 @@
+// kernels.hip -- non-templated kernels and the lattice dispatch of the
+// single-domain forward path (gfx950).  The templated kernels live in
+// kernels_impl.hpp and are instantiated per lattice in kernels_d*.hip.
+#include "kernels.hpp"
+
+namespace lbm {
+
+template <class L>
+hipError_t dispatch_storage(const Launch &g, int op, int a0, bool b0, const void *p0, const void *p1, void *q0,
+                            void *q1, double *partial, int64_t N);
+template <class L>
+hipError_t solid_t(const Launch &g, const uint8_t *solid, uint8_t *flags, uint32_t *nbm);
+
+// Sum rows [begin[d], end[d]) of the partials into out[d*5 .. d*5+4], one
+// block per output row, in a fixed order.
+__global__ void __launch_bounds__(256) k_reduce(const double *__restrict__ partial, const int64_t *__restrict__ begin,
+                                                const int64_t *__restrict__ end, double *__restrict__ out) {
+    __shared__ double red[5][256];
+    const int d = (int)blockIdx.x;
+    const int t = (int)threadIdx.x;
+    double m[5] = {0, 0, 0, 0, 0};
+    for (int64_t b = begin[d] + t; b < end[d]; b += 256)
+        for (int k = 0; k < 5; ++k) m[k] += partial[b * 5 + k];
+    for (int k = 0; k < 5; ++k) red[k][t] = m[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int k = 0; k < 5; ++k) red[k][t] += red[k][t + w];
+        __syncthreads();
+    }
+    if (t == 0)
+        for (int k = 0; k < 5; ++k) out[d * 5 + k] = red[k][0];
+}
+
+__global__ void __launch_bounds__(256) k_copy(float4 *__restrict__ dst, const float4 *__restrict__ src, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+static hipError_t dispatch(const Launch &g, int op, int a0, bool b0, const void *p0, const void *p1, void *q0,
+                           void *q1, double *partial, int64_t N) {
+    switch (g.lattice) {
+        case LAT_D2Q9: return dispatch_storage<D2Q9>(g, op, a0, b0, p0, p1, q0, q1, partial, N);
+        case LAT_D3Q19: return dispatch_storage<D3Q19>(g, op, a0, b0, p0, p1, q0, q1, partial, N);
+        case LAT_D3Q27: return dispatch_storage<D3Q27>(g, op, a0, b0, p0, p1, q0, q1, partial, N);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_step(const Launch &g, int mode, bool has_s) {
+    return dispatch(g, OP_STEP, mode, has_s, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
+}
+
+hipError_t launch_init(const Launch &g, const void *rho, const void *u, int in_f64, int64_t N) {
+    return dispatch(g, OP_INIT, in_f64, false, rho, u, nullptr, nullptr, nullptr, N);
+}
+
+hipError_t launch_moments(const Launch &g, bool odd, void *rho, void *u, int out_f64, double *partial, int64_t N) {
+    return dispatch(g, OP_MOMENTS, out_f64, odd, nullptr, nullptr, rho, u, partial, N);
+}
+
+hipError_t launch_reduce(const double *partial, const int64_t *begin, const int64_t *end, double *out, int rows,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce, dim3(rows), dim3(256), 0, s, partial, begin, end, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_solid(int lattice, const Launch &g, const uint8_t *solid, uint8_t *flags, uint32_t *nbm) {
+    switch (lattice) {
+        case LAT_D2Q9: return solid_t<D2Q9>(g, solid, flags, nbm);
+        case LAT_D3Q19: return solid_t<D3Q19>(g, solid, flags, nbm);
+        default: return solid_t<D3Q27>(g, solid, flags, nbm);
+    }
+}
+
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    const int64_t n = (int64_t)(bytes / 16);
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<float4 *>(dst),
+                       static_cast<const float4 *>(src), n);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

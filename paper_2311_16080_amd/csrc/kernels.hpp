@@ -1,0 +1,36 @@
+// kernels.hpp -- internal interface between the C-ABI host code and the
+// kernel launchers (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "core.hpp"
+
+namespace lbm {
+
+enum : int { LAT_D2Q9 = 0, LAT_D3Q19 = 1, LAT_D3Q27 = 2 };
+enum : int { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
+enum : int { OP_STEP = 0, OP_INIT = 1, OP_MOMENTS = 2 };
+
+// One launch: lattice, storage, a Params<CT> block, buffers, shape.
+struct Launch {
+    int lattice;
+    int storage;
+    const void *params;  // Params<double> for F64 storage, Params<float> otherwise
+    void *A;             // state buffer
+    void *B;             // second buffer (double-buffer pattern)
+    unsigned grid;
+    unsigned block;
+    hipStream_t stream;
+};
+
+hipError_t launch_step(const Launch &g, int mode, bool has_s);
+hipError_t launch_init(const Launch &g, const void *rho, const void *u, int in_f64, int64_t N);
+hipError_t launch_moments(const Launch &g, bool odd, void *rho, void *u, int out_f64, double *partial, int64_t N);
+hipError_t launch_reduce(const double *partial, const int64_t *begin, const int64_t *end, double *out, int rows,
+                         hipStream_t s);
+hipError_t launch_solid(int lattice, const Launch &g, const uint8_t *solid, uint8_t *flags, uint32_t *nbm);
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,344 @@
+// kernels_impl.hpp -- kernel templates of the single-domain forward path,
+// instantiated per lattice by kernels_d2q9.hip / kernels_d3q19.hip /
+// kernels_d3q27.hip.
+#pragma once
+//
+//
+//   k_step      fused stream + collide + boundary fill, one pass per step
+//               (MODE 0: in-place even step, MODE 1: in-place odd step,
+//                MODE 2: double-buffer push step)
+//   k_init      f = feq(rho, u) in the storage format          (eq. feq)
+//   k_moments   rho, u of the current state + FP64 block sums  (eqs. density, velocity)
+//   k_reduce    fixed-order reduction of the block sums
+//   k_solid     solid flags -> per-cell flag byte + solid-neighbour mask
+//   k_copy      streaming copy (achievable-bandwidth probe)
+//
+// In-place streaming uses the AA access pattern (Bailey, Myre, Walsh, Lilja &
+// Saar 2009): the even step reads a cell's populations and writes the
+// post-collision values back into the same cell's opposite slots; the odd step
+// gathers from the neighbours' opposite slots and pushes to the neighbours'
+// natural slots.  Each cell reads and writes the same address set within a
+// step, so one buffer suffices and there is no race.  Every step moves exactly
+// 2 Q values per cell.
+#include "kernels.hpp"
+
+
+namespace lbm {
+
+// Block -> (X, Y, Z-chunk).  Workgroups are handed to the 8 XCDs round robin;
+// remapping makes each XCD process one contiguous range of rows, so the rows
+// a block's neighbours touch mostly sit in the same XCD's L2.
+template <class CT>
+__device__ __forceinline__ bool block_cell(const Params<CT> &p, int &X, int &Y, int &Z) {
+    const int G = (int)gridDim.x;
+    int b = (int)blockIdx.x;
+    if ((G & 7) == 0) b = (b & 7) * (G >> 3) + (b >> 3);
+    const int zc = b % p.zblocks;
+    const int r = b / p.zblocks;
+    Y = r % p.nY;
+    X = r / p.nY;
+    Z = zc * (int)blockDim.x + (int)threadIdx.x;
+    return Z < p.nZ;
+}
+
+template <class L, class ST, int MODE, bool HAS_S>
+__global__ void __launch_bounds__(kMaxBlock) k_step(const Params<typename Store<ST>::CT> p, ST *__restrict__ A,
+                                                    ST *__restrict__ B) {
+    using CT = typename Store<ST>::CT;
+    constexpr int Q = L::Q;
+    int X, Y, Z;
+    if (!block_cell(p, X, Y, Z)) return;
+    const int64_t cell = ((int64_t)X * p.nY + Y) * p.nZ + Z;
+    uint32_t nbm = 0;
+    if (p.flags) {
+        const uint8_t fl = p.flags[cell];
+        if (fl & 1) return;                 // solid cells carry no state
+        if (fl & 2) nbm = p.nbm[cell];
+    }
+    const uint32_t e = edge_bits(p, X, Y, Z);
+    const uint32_t irr = irregular_mask<L>(e, nbm);
+    const int64_t P = p.plane;
+
+    CT h[Q];
+    if constexpr (MODE == 1) {
+        unroll<Q>([&](auto I) {
+            constexpr int O = opp<L>(I);
+            if (!((irr >> I) & 1u)) {
+                const int64_t src = cell - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
+                h[I] = ldh<L, ST, O>(A, P, src);
+            } else {
+                const Nb nb = classify_src<L>(p, X, Y, Z, I, nbm);
+                h[I] = (nb.kind == NB_FLUID) ? ldh<L, ST, O>(A, P, nb.cell) : ldh<L, ST, I>(A, P, cell);
+            }
+        });
+    } else {
+        unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(A, P, cell); });
+    }
+
+    const int zf = zh_face_of(p, e);
+    if (zf >= 0 && (MODE == 1 || p.zh_pending)) zouhe<L>(h, p, zf);
+
+    CT hp[Q];
+    CT rho, ux, uy, uz;
+    CT s = 0;
+    if constexpr (HAS_S) s = (CT)p.s[cell];
+    collide<L>(h, hp, p, s, HAS_S, rho, ux, uy, uz);
+    const bool perim = (e & p.wallmask) != 0;
+
+    ST *W = (MODE == 2) ? B : A;
+    unroll<Q>([&](auto I) {
+        constexpr int O = opp<L>(I);
+        if (!((irr >> O) & 1u)) {
+            if constexpr (MODE == 0) {
+                sth<L, ST, O>(W, P, cell, hp[I]);
+            } else {
+                const int64_t dst = cell + ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
+                sth<L, ST, I>(W, P, dst, hp[I]);
+            }
+        } else {
+            const Nb nb = classify_src<L>(p, X, Y, Z, O, nbm);   // the cell x + c_i
+            if (nb.kind == NB_FLUID) {
+                if constexpr (MODE == 0) sth<L, ST, O>(W, P, cell, hp[I]);
+                else sth<L, ST, I>(W, P, nb.cell, hp[I]);
+            } else {
+                sth<L, ST, O>(W, P, cell, fill_value<L, I>(p, nb, hp[I], perim, rho, ux, uy, uz));
+            }
+        }
+    });
+}
+
+// f = feq(rho, u) written in natural order.  rho: N, u: D planes of N in the
+// caller's axes; IT = float or double.
+template <class L, class ST, class IT>
+__global__ void __launch_bounds__(kMaxBlock) k_init(const Params<typename Store<ST>::CT> p, ST *__restrict__ A,
+                                                    const IT *__restrict__ rho_in, const IT *__restrict__ u_in,
+                                                    int64_t N) {
+    using CT = typename Store<ST>::CT;
+    int X, Y, Z;
+    if (!block_cell(p, X, Y, Z)) return;
+    const int64_t cell = ((int64_t)X * p.nY + Y) * p.nZ + Z;
+    const bool solid = p.flags && (p.flags[cell] & 1);
+    CT rho = rho_in ? (CT)rho_in[cell] : p.rho0;
+    CT u[3] = {0, 0, 0};
+    if (u_in) {
+        if constexpr (L::D == 2) {
+            u[1] = (CT)u_in[cell];
+            u[2] = (CT)u_in[N + cell];
+        } else {
+            u[0] = (CT)u_in[cell];
+            u[1] = (CT)u_in[N + cell];
+            u[2] = (CT)u_in[2 * N + cell];
+        }
+    }
+    const CT usq15 = (CT)1.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const CT drho = rho - p.rho0;
+    unroll<L::Q>([&](auto I) {
+        CT v = solid ? (CT)0 : heq<L, I>(drho, rho, u[0], u[1], u[2], usq15);
+        sth<L, ST, I>(A, p.plane, cell, v);
+    });
+}
+
+// Moments of the current state.  ODD = the state is the AA buffer after an
+// even step (post-collision values in swapped slots): the populations are
+// gathered as the odd step would.  Writes rho, u (caller axes, OT) and one
+// row of FP64 partial sums per block: mass, P_X, P_Y, P_Z, kinetic energy.
+template <class L, class ST, class OT, bool ODD>
+__global__ void __launch_bounds__(kMaxBlock) k_moments(const Params<typename Store<ST>::CT> p,
+                                                       const ST *__restrict__ A, OT *__restrict__ rho_out,
+                                                       OT *__restrict__ u_out, double *__restrict__ partial,
+                                                       int64_t N) {
+    using CT = typename Store<ST>::CT;
+    constexpr int Q = L::Q;
+    __shared__ double red[5][kMaxBlock];
+    int X, Y, Z;
+    const bool inside = block_cell(p, X, Y, Z);
+    double m[5] = {0, 0, 0, 0, 0};
+    if (inside) {
+        const int64_t cell = ((int64_t)X * p.nY + Y) * p.nZ + Z;
+        uint32_t nbm = 0;
+        bool solid = false;
+        if (p.flags) {
+            const uint8_t fl = p.flags[cell];
+            solid = fl & 1;
+            if (fl & 2) nbm = p.nbm[cell];
+        }
+        CT rho = p.rho0, ux = 0, uy = 0, uz = 0;
+        if (!solid) {
+            const uint32_t e = edge_bits(p, X, Y, Z);
+            const uint32_t irr = irregular_mask<L>(e, nbm);
+            CT h[Q];
+            if constexpr (ODD) {
+                unroll<Q>([&](auto I) {
+                    constexpr int O = opp<L>(I);
+                    if (!((irr >> I) & 1u)) {
+                        const int64_t src =
+                            cell - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
+                        h[I] = ldh<L, ST, O>(A, p.plane, src);
+                    } else {
+                        const Nb nb = classify_src<L>(p, X, Y, Z, I, nbm);
+                        h[I] = (nb.kind == NB_FLUID) ? ldh<L, ST, O>(A, p.plane, nb.cell)
+                                                     : ldh<L, ST, I>(A, p.plane, cell);
+                    }
+                });
+            } else {
+                unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(A, p.plane, cell); });
+            }
+            const int zf = zh_face_of(p, e);
+            if (zf >= 0 && (ODD || p.zh_pending)) zouhe<L>(h, p, zf);
+            CT drho = 0, jx = 0, jy = 0, jz = 0;
+            unroll<Q>([&](auto I) {
+                drho += h[I];
+                if constexpr (L::c[I][0] != 0) jx += (CT)L::c[I][0] * h[I];
+                if constexpr (L::c[I][1] != 0) jy += (CT)L::c[I][1] * h[I];
+                if constexpr (L::c[I][2] != 0) jz += (CT)L::c[I][2] * h[I];
+            });
+            rho = p.rho0 + drho;
+            const CT inv = (CT)1 / rho;
+            ux = jx * inv;
+            uy = jy * inv;
+            uz = jz * inv;
+            const double r = (double)rho, vx = (double)ux, vy = (double)uy, vz = (double)uz;
+            m[0] = r;
+            m[1] = r * vx;
+            m[2] = r * vy;
+            m[3] = r * vz;
+            m[4] = 0.5 * r * (vx * vx + vy * vy + vz * vz);
+        }
+        if (rho_out) rho_out[cell] = (OT)rho;
+        if (u_out) {
+            if constexpr (L::D == 2) {
+                u_out[cell] = (OT)uy;
+                u_out[N + cell] = (OT)uz;
+            } else {
+                u_out[cell] = (OT)ux;
+                u_out[N + cell] = (OT)uy;
+                u_out[2 * N + cell] = (OT)uz;
+            }
+        }
+    }
+    if (!partial) return;
+    const int t = (int)threadIdx.x;
+    unroll<5>([&](auto K) { red[K][t] = m[K]; });
+    __syncthreads();
+    for (int w = (int)blockDim.x / 2; w > 0; w >>= 1) {
+        if (t < w) unroll<5>([&](auto K) { red[K][t] += red[K][t + w]; });
+        __syncthreads();
+    }
+    if (t == 0) unroll<5>([&](auto K) { partial[(int64_t)blockIdx.x * 5 + K] = red[K][0]; });
+}
+
+// Per-cell flag byte (bit0 solid, bit1 some source x - c_k is solid) and the
+// solid-neighbour mask, from N solid bytes.  Periodic faces wrap.
+template <class L>
+__global__ void __launch_bounds__(kMaxBlock) k_solid(const Params<float> p, const uint8_t *__restrict__ solid,
+                                                     uint8_t *__restrict__ flags, uint32_t *__restrict__ nbm) {
+    int X, Y, Z;
+    if (!block_cell(p, X, Y, Z)) return;
+    const int64_t cell = ((int64_t)X * p.nY + Y) * p.nZ + Z;
+    if (solid[cell]) {
+        flags[cell] = 1;
+        nbm[cell] = 0;
+        return;
+    }
+    uint32_t m = 0;
+    for (int k = 1; k < L::Q; ++k) {
+        int y[3] = {X - L::c[k][0], Y - L::c[k][1], Z - L::c[k][2]};
+        const int n[3] = {p.nX, p.nY, p.nZ};
+        bool in = true;
+        for (int a = 0; a < 3; ++a) {
+            if (y[a] < 0) {
+                if (p.ftype[2 * a] == F_PERIODIC) y[a] += n[a];
+                else in = false;
+            } else if (y[a] >= n[a]) {
+                if (p.ftype[2 * a + 1] == F_PERIODIC) y[a] -= n[a];
+                else in = false;
+            }
+        }
+        if (in && solid[((int64_t)y[0] * p.nY + y[1]) * p.nZ + y[2]]) m |= 1u << k;
+    }
+    nbm[cell] = m;
+    flags[cell] = m ? 2 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (dispatch on lattice and storage type).
+// ---------------------------------------------------------------------------
+template <class L, class ST>
+hipError_t step_t(const Launch &g, int mode, bool has_s) {
+    using CT = typename Store<ST>::CT;
+    const Params<CT> &p = *static_cast<const Params<CT> *>(g.params);
+    ST *A = static_cast<ST *>(g.A);
+    ST *B = static_cast<ST *>(g.B);
+#define LBM_STEP_CASE(M, S)                                                                   \
+    if (mode == M && has_s == S) {                                                            \
+        hipLaunchKernelGGL((k_step<L, ST, M, S>), dim3(g.grid), dim3(g.block), 0, g.stream, p, A, B); \
+        return hipGetLastError();                                                             \
+    }
+    LBM_STEP_CASE(0, false)
+    LBM_STEP_CASE(1, false)
+    LBM_STEP_CASE(2, false)
+    LBM_STEP_CASE(0, true)
+    LBM_STEP_CASE(1, true)
+    LBM_STEP_CASE(2, true)
+#undef LBM_STEP_CASE
+    return hipErrorInvalidValue;
+}
+
+template <class L, class ST>
+hipError_t init_t(const Launch &g, const void *rho, const void *u, int in_f64, int64_t N) {
+    using CT = typename Store<ST>::CT;
+    const Params<CT> &p = *static_cast<const Params<CT> *>(g.params);
+    ST *A = static_cast<ST *>(g.A);
+    if (in_f64)
+        hipLaunchKernelGGL((k_init<L, ST, double>), dim3(g.grid), dim3(g.block), 0, g.stream, p, A,
+                           static_cast<const double *>(rho), static_cast<const double *>(u), N);
+    else
+        hipLaunchKernelGGL((k_init<L, ST, float>), dim3(g.grid), dim3(g.block), 0, g.stream, p, A,
+                           static_cast<const float *>(rho), static_cast<const float *>(u), N);
+    return hipGetLastError();
+}
+
+template <class L, class ST>
+hipError_t moments_t(const Launch &g, bool odd, void *rho, void *u, int out_f64, double *partial, int64_t N) {
+    using CT = typename Store<ST>::CT;
+    const Params<CT> &p = *static_cast<const Params<CT> *>(g.params);
+    const ST *A = static_cast<const ST *>(g.A);
+#define LBM_MOM_CASE(OT, ODD)                                                                                  \
+    hipLaunchKernelGGL((k_moments<L, ST, OT, ODD>), dim3(g.grid), dim3(g.block), 0, g.stream, p, A,           \
+                       static_cast<OT *>(rho), static_cast<OT *>(u), partial, N);
+    if (out_f64) {
+        if (odd) { LBM_MOM_CASE(double, true) } else { LBM_MOM_CASE(double, false) }
+    } else {
+        if (odd) { LBM_MOM_CASE(float, true) } else { LBM_MOM_CASE(float, false) }
+    }
+#undef LBM_MOM_CASE
+    return hipGetLastError();
+}
+
+template <class L>
+hipError_t dispatch_storage(const Launch &g, int op, int a0, bool b0, const void *p0, const void *p1,
+                                   void *q0, void *q1, double *partial, int64_t N) {
+    switch (g.storage) {
+#define LBM_ST_CASE(TAG, ST)                                                                    \
+    case TAG:                                                                                   \
+        if (op == OP_STEP) return step_t<L, ST>(g, a0, b0);                                     \
+        if (op == OP_INIT) return init_t<L, ST>(g, p0, p1, a0, N);                              \
+        if (op == OP_MOMENTS) return moments_t<L, ST>(g, b0, q0, q1, a0, partial, N);           \
+        return hipErrorInvalidValue;
+        LBM_ST_CASE(ST_F64, double)
+        LBM_ST_CASE(ST_F32, float)
+        LBM_ST_CASE(ST_F16, _Float16)
+        LBM_ST_CASE(ST_BF16, bf16_t)
+#undef LBM_ST_CASE
+    }
+    return hipErrorInvalidValue;
+}
+
+template <class L>
+hipError_t solid_t(const Launch &g, const uint8_t *solid, uint8_t *flags, uint32_t *nbm) {
+    const Params<float> &p = *static_cast<const Params<float> *>(g.params);
+    hipLaunchKernelGGL(k_solid<L>, dim3(g.grid), dim3(g.block), 0, g.stream, p, solid, flags, nbm);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

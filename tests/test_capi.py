@@ -1,0 +1,129 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol that
+include/lbm.h declares, and rejects bad arguments before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2311_16080_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported():
+    L = lbm.lib()
+    names = _declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(lbm.SIGNATURES), set(names) ^ set(lbm.SIGNATURES)
+
+
+def test_version():
+    assert "gfx950" in lbm.lib().lbm_version().decode()
+
+
+@pytest.mark.parametrize("args,msg", [
+    ((7, 8, 8, 8, 0.8), "unknown lattice"),
+    ((lbm.D3Q19, 0, 8, 8, 0.8), "nx, ny"),
+    ((lbm.D3Q19, 8, 8, 0, 0.8), "nz >= 1"),
+    ((lbm.D2Q9, 8, 8, 5, 0.8), "nz = 0 or 1"),
+    ((lbm.D3Q19, 8, 8, 8, 0.5), "tau"),
+    ((lbm.D3Q19, 8, 8, 8, float("nan")), "tau"),
+    ((lbm.D3Q27, 2048, 1024, 1024, 0.8), "2^31"),
+])
+def test_create_rejects(args, msg):
+    h = lbm.lib().lbm_create(*args, None)
+    assert not h
+    assert msg in lbm.last_error()
+
+
+def _bc(faces):
+    return ctypes.byref(lbm.make_bc(faces))
+
+
+@pytest.mark.parametrize("faces,msg", [
+    ([lbm.WALL, lbm.PERIODIC, 0, 0, 0, 0], "periodic must be set on both"),
+    ([(lbm.WALL, (0.1, 0, 0)), lbm.WALL, 0, 0, 0, 0], "tangential"),
+    ([(lbm.ZOUHE_VELOCITY, (0.1, 0, 0)), lbm.EQ_OUTFLOW, (lbm.ZOUHE_PRESSURE, (0, 0, 0), 1.0), lbm.WALL, 0, 0],
+     "one axis"),
+    ([(lbm.ZOUHE_PRESSURE, (0, 0, 0), 0.0), lbm.WALL, 0, 0, 0, 0], "density"),
+    ([(9,), lbm.WALL, 0, 0, 0, 0], "unknown boundary type"),
+    ([(lbm.ZOUHE_VELOCITY, (1.5, 0, 0)), lbm.WALL, 0, 0, 0, 0], "below 1"),
+])
+def test_create_rejects_faces(faces, msg):
+    h = lbm.lib().lbm_create(lbm.D3Q19, 8, 8, 8, 0.8, _bc(faces))
+    assert not h
+    assert msg in lbm.last_error()
+
+
+def test_open_axis_needs_two_cells():
+    faces = [(lbm.ZOUHE_VELOCITY, (0.01, 0, 0)), lbm.EQ_OUTFLOW, lbm.WALL, lbm.WALL, 0, 0]
+    assert not lbm.lib().lbm_create(lbm.D3Q19, 1, 8, 8, 0.8, _bc(faces))
+    assert ">= 2 cells" in lbm.last_error()
+
+
+def test_2d_rejects_z_velocity():
+    faces = [0, 0, lbm.WALL, (lbm.WALL, (0.05, 0, 0.01)), 0, 0]
+    assert not lbm.lib().lbm_create(lbm.D2Q9, 8, 8, 0, 0.8, _bc(faces))
+    assert "z velocity" in lbm.last_error()
+
+
+def test_create_and_options_without_device():
+    """lbm_create does no device work, so it succeeds on a host without a GPU;
+    option checks also run before any device call."""
+    L = lbm.lib()
+    faces = [lbm.WALL] * 5 + [(lbm.WALL, (0.05, 0, 0))]
+    h = L.lbm_create(lbm.D3Q19, 16, 16, 16, 0.55, _bc(faces))
+    assert h
+    h = ctypes.c_void_p(h)
+    bad = lbm.lbm_options(9, lbm.F32, lbm.INPLACE, 0, 1.0)
+    assert L.lbm_set_options(h, ctypes.byref(bad)) == lbm.LBM_EINVAL
+    bad = lbm.lbm_options(lbm.F16, lbm.F64, lbm.INPLACE, 0, 1.0)
+    assert L.lbm_set_options(h, ctypes.byref(bad)) == lbm.LBM_EUNSUPPORTED
+    bad = lbm.lbm_options(lbm.F32, lbm.F32, 5, 0, 1.0)
+    assert L.lbm_set_options(h, ctypes.byref(bad)) == lbm.LBM_EINVAL
+    bad = lbm.lbm_options(lbm.F32, lbm.F32, lbm.INPLACE, 0, -1.0)
+    assert L.lbm_set_options(h, ctypes.byref(bad)) == lbm.LBM_EINVAL
+    ok = lbm.lbm_options(lbm.BF16, lbm.F32, lbm.DOUBLE, 0, 1.0)
+    assert L.lbm_set_options(h, ctypes.byref(ok)) == lbm.LBM_OK
+    # state-dependent calls before init
+    assert L.lbm_step(h, 1) == lbm.LBM_ESTATE
+    assert L.lbm_step(h, -1) == lbm.LBM_EINVAL
+    assert L.lbm_moments(h, None, None, lbm.F32, None) == lbm.LBM_ESTATE
+    assert L.lbm_backward(h, None, None, lbm.F32, None, None, None) == lbm.LBM_ESTATE
+    assert L.lbm_capture_graph(h, 0) == lbm.LBM_EINVAL
+    assert L.lbm_graph_launch(h) == lbm.LBM_ESTATE
+    assert L.lbm_time(h) == 0
+    assert L.lbm_state_bytes(h) > 19 * 16 ** 3 * 2
+    L.lbm_destroy(h)
+
+
+def test_null_context_everywhere():
+    L = lbm.lib()
+    assert L.lbm_step(None, 1) == lbm.LBM_EINVAL
+    assert L.lbm_set_stream(None, None) == lbm.LBM_EINVAL
+    assert L.lbm_moments(None, None, None, lbm.F32, None) == lbm.LBM_EINVAL
+    assert L.lbm_sync(None) == lbm.LBM_EINVAL
+    assert L.lbm_tape_end(None) == lbm.LBM_EINVAL
+    assert L.lbm_time(None) == -1
+    L.lbm_destroy(None)
+
+
+def test_copy_probe_rejects_misaligned():
+    L = lbm.lib()
+    assert L.lbm_copy_probe(ctypes.c_void_p(16), ctypes.c_void_p(32), 17, None) == lbm.LBM_EINVAL
+    assert L.lbm_copy_probe(None, ctypes.c_void_p(32), 16, None) == lbm.LBM_EINVAL
+
+
+def test_binding_raises_on_bad_create():
+    with pytest.raises(lbm.LbmError):
+        lbm.Sim("D3Q19", (8, 8, 8), tau=0.4)
