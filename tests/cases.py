@@ -61,7 +61,8 @@ def oracle_run(case: Case, steps: Optional[int] = None):
     if case.q == 9:
         faces[4] = faces[5] = oracle.Face()
     sol = None if case.solid is None else case.solid.reshape(case.oshape).astype(np.uint8)
-    sv = None if case.s is None else case.s.reshape(case.oshape).astype(np.float64)
+    # the C-ABI takes the solid fraction as float32: both sides get the same rounded values
+    sv = None if case.s is None else case.s.reshape(case.oshape).astype(np.float32).astype(np.float64)
     S = oracle.Sim(q=case.q, nx=case.oshape[0], ny=case.oshape[1], nz=case.oshape[2], tau=case.tau,
                    faces=faces, solid=sol, s=sv)
     rho, u = case.init_fields()
