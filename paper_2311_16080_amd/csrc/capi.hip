@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -155,6 +156,7 @@ static void fill_params(Params<CT> &p, const lbm_ctx *c) {
         if (F.type == LBM_ZOUHE_VELOCITY || F.type == LBM_ZOUHE_PRESSURE) p.zhmask |= 1u << f;
     }
     p.zh_pending = c->t > 0 ? 1 : 0;
+    p.xcd_remap = c->xcd_remap;
     p.ft = face_table<CT>(c);
     p.flags = c->flags;
     p.nbm = c->nbm;
@@ -206,10 +208,14 @@ static void setup_shape(lbm_ctx *c, int lattice, int nx, int ny, int nz, double 
         c->nZ = ny;
     }
     c->N = (int64_t)c->nX * c->nY * c->nZ;
-    c->plane = (c->N + 127) / 128 * 128;
+    // plane stride: rounded to 1024 elements plus one extra 1024-element pad, so
+    // the Q planes of a large power-of-two grid do not sit at power-of-two
+    // distances from each other (measured: otherwise fewer HBM channels serve
+    // the Q concurrent streams of each lane)
+    c->plane = (c->N + 1023) / 1024 * 1024 + 1024;
     c->tau = tau;
     int blk = (c->nZ + 63) / 64 * 64;
-    if (blk > kMaxBlock) blk = kMaxBlock;
+    if (blk > c->block_req) blk = c->block_req;
     c->block = blk;
     c->zblocks = (c->nZ + blk - 1) / blk;
     c->grid = (int64_t)c->nX * c->nY * c->zblocks;
@@ -229,6 +235,18 @@ extern "C" lbm_ctx *lbm_create(int lattice, int nx, int ny, int nz, double tau, 
     if (!c) {
         fail(LBM_ENOMEM, "host allocation failed");
         return nullptr;
+    }
+    {
+        // launch-shape knobs (measurement sweeps); defaults are the tuned ones
+        const char *nt = std::getenv("LBM_NT");
+        if (nt && nt[0] >= '0' && nt[0] <= '4') c->nt = nt[0] - '0';
+        const char *xr = std::getenv("LBM_XCD_REMAP");
+        if (xr && (xr[0] == '0' || xr[0] == '1')) c->xcd_remap = xr[0] - '0';
+        const char *bl = std::getenv("LBM_BLOCK");
+        if (bl) {
+            const int v = std::atoi(bl);
+            if (v == 64 || v == 128 || v == 256) c->block_req = v;
+        }
     }
     setup_shape(c, lattice, nx, ny, nz, tau);
     map_faces(c, bc);
@@ -383,6 +401,7 @@ Launch lbm::make_launch(lbm_ctx *c) {
     g.grid = (unsigned)c->grid;
     g.block = (unsigned)c->block;
     g.stream = c->stream;
+    g.nt = c->nt;
     return g;
 }
 

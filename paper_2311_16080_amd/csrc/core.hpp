@@ -60,7 +60,7 @@ struct Params {
     CT omega;              // 1 / tau
     CT rho0;
     int zh_pending;        // the state read needs the Zou-He closure (t > 0)
-    int pad1;
+    int xcd_remap;         // give each XCD a contiguous range of rows
     const uint8_t *flags;  // N bytes or null: bit0 solid, bit1 a neighbour is solid
     const uint32_t *nbm;   // N words: bit k set when x - c_k is a solid cell
     const float *s;        // N or null: partial bounce-back solid fraction
@@ -75,12 +75,16 @@ struct bf16_t {
 template <class ST>
 struct Store;
 
+// ld / st: plain accesses; ldn / stn: non-temporal (streaming) accesses, for
+// state that is touched once per step and not reused before it leaves the caches
 template <>
 struct Store<double> {
     using CT = double;
     static constexpr bool scaled = false;
     __device__ static double ld(const double *p) { return *p; }
     __device__ static void st(double *p, double v) { *p = v; }
+    __device__ static double ldn(const double *p) { return __builtin_nontemporal_load(p); }
+    __device__ static void stn(double *p, double v) { __builtin_nontemporal_store(v, p); }
 };
 template <>
 struct Store<float> {
@@ -88,6 +92,8 @@ struct Store<float> {
     static constexpr bool scaled = false;
     __device__ static float ld(const float *p) { return *p; }
     __device__ static void st(float *p, float v) { *p = v; }
+    __device__ static float ldn(const float *p) { return __builtin_nontemporal_load(p); }
+    __device__ static void stn(float *p, float v) { __builtin_nontemporal_store(v, p); }
 };
 template <>
 struct Store<_Float16> {
@@ -95,34 +101,76 @@ struct Store<_Float16> {
     static constexpr bool scaled = true;
     __device__ static float ld(const _Float16 *p) { return (float)*p; }
     __device__ static void st(_Float16 *p, float v) { *p = (_Float16)v; }  // round to nearest even
+    __device__ static float ldn(const _Float16 *p) { return (float)__builtin_nontemporal_load(p); }
+    __device__ static void stn(_Float16 *p, float v) { __builtin_nontemporal_store((_Float16)v, p); }
 };
 template <>
 struct Store<bf16_t> {
     using CT = float;
     static constexpr bool scaled = true;
-    __device__ static float ld(const bf16_t *p) { return __uint_as_float(((uint32_t)p->bits) << 16); }
-    __device__ static void st(bf16_t *p, float v) {
+    __device__ static uint16_t round(float v) {
         uint32_t u = __float_as_uint(v);
-        uint16_t r;
-        if ((u & 0x7fffffffu) > 0x7f800000u) r = (uint16_t)((u >> 16) | 0x40u);     // quiet NaN
-        else r = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);                // nearest even
-        p->bits = r;
+        if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+        return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);                  // nearest even
     }
+    __device__ static float ld(const bf16_t *p) { return __uint_as_float(((uint32_t)p->bits) << 16); }
+    __device__ static void st(bf16_t *p, float v) { p->bits = round(v); }
+    __device__ static float ldn(const bf16_t *p) {
+        return __uint_as_float(((uint32_t)__builtin_nontemporal_load(&p->bits)) << 16);
+    }
+    __device__ static void stn(bf16_t *p, float v) { __builtin_nontemporal_store(round(v), &p->bits); }
 };
 
-// load / store of population i with the storage scale
-template <class L, class ST, int I>
-__device__ __forceinline__ typename Store<ST>::CT ldh(const ST *base, int64_t plane, int64_t cell) {
+// Address of population I of a cell.  Tiled layout (LBM_TILE=1): cells in
+// groups of 64 consecutive linear indices, each group storing its Q planes
+// back to back (Q x 64 elements); planar layout (0): one plane of `plane`
+// elements per direction.
+#ifndef LBM_TILE
+#define LBM_TILE 0
+#endif
+template <class L, int I, class ST>
+__device__ __forceinline__ const ST *pop_ptr(const ST *base, int64_t plane, int64_t cell) {
+    if constexpr (LBM_TILE) return base + (cell + (cell >> 6) * (int64_t)((L::Q - 1) * 64) + (int64_t)I * 64);
+    else return base + (int64_t)I * plane + cell;
+}
+template <class L, int I, class ST>
+__device__ __forceinline__ ST *pop_ptr(ST *base, int64_t plane, int64_t cell) {
+    if constexpr (LBM_TILE) return base + (cell + (cell >> 6) * (int64_t)((L::Q - 1) * 64) + (int64_t)I * 64);
+    else return base + (int64_t)I * plane + cell;
+}
+
+// load / store of population I through a pointer, with the storage scale
+template <class L, class ST, int I, bool NT = false>
+__device__ __forceinline__ typename Store<ST>::CT ldp(const ST *ptr) {
     using CT = typename Store<ST>::CT;
-    CT v = Store<ST>::ld(base + (int64_t)I * plane + cell);
+    CT v = NT ? Store<ST>::ldn(ptr) : Store<ST>::ld(ptr);
     if constexpr (Store<ST>::scaled) v *= (CT)weight<L>(I);
     return v;
 }
-template <class L, class ST, int I>
+template <class L, class ST, int I, bool NT = false>
+__device__ __forceinline__ void stp(ST *ptr, typename Store<ST>::CT v) {
+    using CT = typename Store<ST>::CT;
+    if constexpr (Store<ST>::scaled) v *= (CT)(1.0 / weight<L>(I));
+    if constexpr (NT) Store<ST>::stn(ptr, v);
+    else Store<ST>::st(ptr, v);
+}
+
+// load / store of population i with the storage scale
+template <class L, class ST, int I, bool NT = false>
+__device__ __forceinline__ typename Store<ST>::CT ldh(const ST *base, int64_t plane, int64_t cell) {
+    using CT = typename Store<ST>::CT;
+    const ST *ptr = pop_ptr<L, I>(base, plane, cell);
+    CT v = NT ? Store<ST>::ldn(ptr) : Store<ST>::ld(ptr);
+    if constexpr (Store<ST>::scaled) v *= (CT)weight<L>(I);
+    return v;
+}
+template <class L, class ST, int I, bool NT = false>
 __device__ __forceinline__ void sth(ST *base, int64_t plane, int64_t cell, typename Store<ST>::CT v) {
     using CT = typename Store<ST>::CT;
     if constexpr (Store<ST>::scaled) v *= (CT)(1.0 / weight<L>(I));
-    Store<ST>::st(base + (int64_t)I * plane + cell, v);
+    ST *ptr = pop_ptr<L, I>(base, plane, cell);
+    if constexpr (NT) Store<ST>::stn(ptr, v);
+    else Store<ST>::st(ptr, v);
 }
 
 // compile-time loop

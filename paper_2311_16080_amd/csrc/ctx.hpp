@@ -41,6 +41,9 @@ struct lbm_ctx {
     lbm_options opt{};
     int block = 256, zblocks = 1;
     int64_t grid = 1;
+    int nt = 1;                      // step kernel memory hints (LBM_NT = 0..4)
+    int xcd_remap = 0;               // LBM_XCD_REMAP = 0 / 1 (measured: off is faster)
+    int block_req = 256;             // LBM_BLOCK = 64 / 128 / 256 (threads per block, along Z)
 
     // device
     int device = -1;

@@ -23,6 +23,7 @@ struct Launch {
     unsigned grid;
     unsigned block;
     hipStream_t stream;
+    int nt;              // step kernel memory hints: 0 plain, 1 non-temporal, 2 non-temporal stores
 };
 
 hipError_t launch_step(const Launch &g, int mode, bool has_s);

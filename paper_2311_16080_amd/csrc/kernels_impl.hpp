@@ -32,7 +32,7 @@ template <class CT>
 __device__ __forceinline__ bool block_cell(const Params<CT> &p, int &X, int &Y, int &Z) {
     const int G = (int)gridDim.x;
     int b = (int)blockIdx.x;
-    if ((G & 7) == 0) b = (b & 7) * (G >> 3) + (b >> 3);
+    if (p.xcd_remap && (G & 7) == 0) b = (b & 7) * (G >> 3) + (b >> 3);
     const int zc = b % p.zblocks;
     const int r = b / p.zblocks;
     Y = r % p.nY;
@@ -41,9 +41,18 @@ __device__ __forceinline__ bool block_cell(const Params<CT> &p, int &X, int &Y, 
     return Z < p.nZ;
 }
 
-template <class L, class ST, int MODE, bool HAS_S>
+template <class L, class ST, int MODE, bool HAS_S, int NT>
 __global__ void __launch_bounds__(kMaxBlock) k_step(const Params<typename Store<ST>::CT> p, ST *__restrict__ A,
                                                     ST *__restrict__ B) {
+    // NT 0: plain accesses.  NT 1: non-temporal loads and stores wherever the
+    // access is aligned with the wavefront (the local even step; directions
+    // without a Z component in the odd / push steps); Z-shifted accesses stay
+    // cached, since neighbouring wavefronts share their boundary cache lines.
+    // NT 2: non-temporal everywhere.  NT 3: as 1 plus non-temporal Z-shifted
+    // stores.  NT 4: as 1 plus non-temporal Z-shifted loads.
+    constexpr bool NTA = (NT >= 1);
+    constexpr bool NTZL = (NT == 2) || (NT == 4);
+    constexpr bool NTZS = (NT == 2) || (NT == 3);
     using CT = typename Store<ST>::CT;
     constexpr int Q = L::Q;
     int X, Y, Z;
@@ -65,14 +74,14 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(const Params<typename Store<
             constexpr int O = opp<L>(I);
             if (!((irr >> I) & 1u)) {
                 const int64_t src = cell - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
-                h[I] = ldh<L, ST, O>(A, P, src);
+                h[I] = ldh<L, ST, O, (L::c[I][2] == 0) ? NTA : NTZL>(A, P, src);
             } else {
                 const Nb nb = classify_src<L>(p, X, Y, Z, I, nbm);
                 h[I] = (nb.kind == NB_FLUID) ? ldh<L, ST, O>(A, P, nb.cell) : ldh<L, ST, I>(A, P, cell);
             }
         });
     } else {
-        unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(A, P, cell); });
+        unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I, NTA>(A, P, cell); });
     }
 
     const int zf = zh_face_of(p, e);
@@ -90,10 +99,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(const Params<typename Store<
         constexpr int O = opp<L>(I);
         if (!((irr >> O) & 1u)) {
             if constexpr (MODE == 0) {
-                sth<L, ST, O>(W, P, cell, hp[I]);
+                sth<L, ST, O, NTA>(W, P, cell, hp[I]);
             } else {
                 const int64_t dst = cell + ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
-                sth<L, ST, I>(W, P, dst, hp[I]);
+                sth<L, ST, I, (L::c[I][2] == 0) ? NTA : NTZS>(W, P, dst, hp[I]);
             }
         } else {
             const Nb nb = classify_src<L>(p, X, Y, Z, O, nbm);   // the cell x + c_i
@@ -269,10 +278,16 @@ hipError_t step_t(const Launch &g, int mode, bool has_s) {
     const Params<CT> &p = *static_cast<const Params<CT> *>(g.params);
     ST *A = static_cast<ST *>(g.A);
     ST *B = static_cast<ST *>(g.B);
-#define LBM_STEP_CASE(M, S)                                                                   \
-    if (mode == M && has_s == S) {                                                            \
-        hipLaunchKernelGGL((k_step<L, ST, M, S>), dim3(g.grid), dim3(g.block), 0, g.stream, p, A, B); \
-        return hipGetLastError();                                                             \
+#define LBM_STEP_CASE(M, S)                                                                            \
+    if (mode == M && has_s == S) {                                                                     \
+        switch (g.nt) {                                                                                \
+            case 0: hipLaunchKernelGGL((k_step<L, ST, M, S, 0>), dim3(g.grid), dim3(g.block), 0, g.stream, p, A, B); break; \
+            case 2: hipLaunchKernelGGL((k_step<L, ST, M, S, 2>), dim3(g.grid), dim3(g.block), 0, g.stream, p, A, B); break; \
+            case 3: hipLaunchKernelGGL((k_step<L, ST, M, S, 3>), dim3(g.grid), dim3(g.block), 0, g.stream, p, A, B); break; \
+            case 4: hipLaunchKernelGGL((k_step<L, ST, M, S, 4>), dim3(g.grid), dim3(g.block), 0, g.stream, p, A, B); break; \
+            default: hipLaunchKernelGGL((k_step<L, ST, M, S, 1>), dim3(g.grid), dim3(g.block), 0, g.stream, p, A, B); break; \
+        }                                                                                              \
+        return hipGetLastError();                                                                      \
     }
     LBM_STEP_CASE(0, false)
     LBM_STEP_CASE(1, false)
@@ -315,22 +330,13 @@ hipError_t moments_t(const Launch &g, bool odd, void *rho, void *u, int out_f64,
     return hipGetLastError();
 }
 
-template <class L>
-hipError_t dispatch_storage(const Launch &g, int op, int a0, bool b0, const void *p0, const void *p1,
-                                   void *q0, void *q1, double *partial, int64_t N) {
-    switch (g.storage) {
-#define LBM_ST_CASE(TAG, ST)                                                                    \
-    case TAG:                                                                                   \
-        if (op == OP_STEP) return step_t<L, ST>(g, a0, b0);                                     \
-        if (op == OP_INIT) return init_t<L, ST>(g, p0, p1, a0, N);                              \
-        if (op == OP_MOMENTS) return moments_t<L, ST>(g, b0, q0, q1, a0, partial, N);           \
-        return hipErrorInvalidValue;
-        LBM_ST_CASE(ST_F64, double)
-        LBM_ST_CASE(ST_F32, float)
-        LBM_ST_CASE(ST_F16, _Float16)
-        LBM_ST_CASE(ST_BF16, bf16_t)
-#undef LBM_ST_CASE
-    }
+// Launches for one (lattice, storage) pair; instantiated in kernels_<lat>_<st>.hip.
+template <class L, class ST>
+hipError_t dispatch_one(const Launch &g, int op, int a0, bool b0, const void *p0, const void *p1, void *q0, void *q1,
+                        double *partial, int64_t N) {
+    if (op == OP_STEP) return step_t<L, ST>(g, a0, b0);
+    if (op == OP_INIT) return init_t<L, ST>(g, p0, p1, a0, N);
+    if (op == OP_MOMENTS) return moments_t<L, ST>(g, b0, q0, q1, a0, partial, N);
     return hipErrorInvalidValue;
 }
 

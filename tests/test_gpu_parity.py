@@ -179,3 +179,20 @@ def test_graph_replay_matches_eager():
     torch.cuda.synchronize()
     assert g.t == 30
     assert torch.equal(r_e, r_g) and torch.equal(u_e, u_g)
+
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+def test_memory_hints_do_not_change_results(storage, monkeypatch):
+    """Plain, non-temporal and non-temporal-store variants of the step kernel
+    differ only in cache hints: bitwise equal moments."""
+    _announce(f"memory hints {storage}")
+    faces = [(W,), (W,), (P,), (P,), (ZV, (0.01, 0, 0.03)), (OUT, (0, 0, 0), 1.0)]
+    ref = None
+    for nt in ("0", "1", "2"):
+        monkeypatch.setenv("LBM_NT", nt)
+        g = gpu_run(Case(19, (6, 5, 264), 0.62, faces, steps=7, storage=storage, init_seed=50))
+        if ref is None:
+            ref = g
+        else:
+            assert np.array_equal(ref[0], g[0]) and np.array_equal(ref[1], g[1]), nt
