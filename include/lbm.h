@@ -150,6 +150,14 @@ void lbm_destroy(lbm_ctx *ctx);
 /* opt: host pointer.  LBM_ESTATE after the state exists. */
 int lbm_set_options(lbm_ctx *ctx, const lbm_options *opt);
 
+/*
+ * Change tau and the faces' velocities / densities of a single-domain context
+ * (the face types must stay the same).  bc: host pointer or NULL (faces
+ * unchanged).  Invalidates a recorded tape and captured graphs.  Checked like
+ * lbm_create.
+ */
+int lbm_set_params(lbm_ctx *ctx, double tau, const lbm_bc *bc);
+
 /* hip_stream: a hipStream_t (NULL = the null stream). */
 int lbm_set_stream(lbm_ctx *ctx, void *hip_stream);
 

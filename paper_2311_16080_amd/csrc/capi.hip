@@ -276,6 +276,33 @@ extern "C" int lbm_set_options(lbm_ctx *c, const lbm_options *o) {
     return LBM_OK;
 }
 
+extern "C" int lbm_set_params(lbm_ctx *c, double tau, const lbm_bc *bc) {
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if (c->batch) return fail(LBM_EUNSUPPORTED, "batch contexts take per-domain parameters at creation");
+    const int nz_arg = (c->lattice == LBM_D2Q9) ? 1 : c->nz;
+    if (validate_domain(c->lattice, c->nx, c->ny, nz_arg, tau, bc) != LBM_OK) return LBM_EINVAL;
+    if (bc) {
+        const int nf = (c->D == 3) ? 6 : 4;
+        for (int f = 0; f < nf; ++f)
+            if (bc->face[f].type != c->bc.face[f].type && !(c->bc.face[f].type == 0 && bc->face[f].type == 0))
+                return fail(LBM_EINVAL, "face %d: the boundary type cannot change (%d -> %d)", f, c->bc.face[f].type,
+                            bc->face[f].type);
+    }
+    c->tau = tau;
+    if (bc) {
+        c->bc = *bc;
+        map_faces(c, bc);
+    }
+    drop_graph(c);
+    c->moved_since_tape = true;
+    if (c->A) {
+        int rc = upload_faces(c);
+        if (rc) return rc;
+    }
+    refresh_params(c);
+    return LBM_OK;
+}
+
 extern "C" int lbm_set_stream(lbm_ctx *c, void *s) {
     if (!c) return fail(LBM_EINVAL, "null context");
     c->stream = static_cast<hipStream_t>(s);

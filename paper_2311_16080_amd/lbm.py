@@ -55,6 +55,7 @@ SIGNATURES = {
     "lbm_batch_offsets": (_i, [_vp, ctypes.POINTER(ctypes.c_int64)]),
     "lbm_destroy": (None, [_vp]),
     "lbm_set_options": (_i, [_vp, ctypes.POINTER(lbm_options)]),
+    "lbm_set_params": (_i, [_vp, _d, ctypes.POINTER(lbm_bc)]),
     "lbm_set_stream": (_i, [_vp, _vp]),
     "lbm_set_solid": (_i, [_vp, _vp, _i]),
     "lbm_set_solid_fraction": (_i, [_vp, _vp, _i]),
@@ -176,6 +177,15 @@ class Sim:
             self.h = None
 
     # ---- setup ---------------------------------------------------------------
+    def set_params(self, tau: Optional[float] = None, faces=None):
+        """Change tau and/or the faces' velocities and densities (same types)."""
+        tau = self.tau if tau is None else float(tau)
+        bc = make_bc(faces) if faces is not None else None
+        check(lib().lbm_set_params(self.h, tau, ctypes.byref(bc) if bc is not None else None))
+        self.tau = tau
+        if bc is not None:
+            self._bc = bc
+
     def use_current_stream(self):
         torch = _torch()
         check(lib().lbm_set_stream(self.h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
@@ -301,3 +311,51 @@ def copy_probe(dst, src, nbytes: int):
     torch = _torch()
     check(lib().lbm_copy_probe(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), int(nbytes),
                                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+
+class _Rollout:
+    """torch.autograd.Function factory (built lazily so importing this module
+    does not import torch)."""
+    fn = None
+
+    @classmethod
+    def get(cls):
+        if cls.fn is None:
+            torch = _torch()
+
+            class LbmRollout(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, s, tau, sim, nsteps, K, rho0, u0):
+                    sim.set_params(tau=float(tau))
+                    if s is not None:
+                        sim.set_solid_fraction(s.detach())
+                    sim.init_equilibrium(rho0, u0)
+                    sim.tape_begin(K, max(int(nsteps), 1))
+                    sim.step(int(nsteps))
+                    sim.tape_end()
+                    rho, u = sim.moments(dtype=torch.float64 if sim.storage == "f64" else torch.float32)
+                    ctx.sim = sim
+                    ctx.has_s = s is not None
+                    ctx.tau_dtype = tau.dtype
+                    return rho, u
+
+                @staticmethod
+                def backward(ctx, g_rho, g_u):
+                    sim = ctx.sim
+                    ds, dtau, _ = sim.backward(g_rho, g_u, want_s=ctx.has_s)
+                    g_tau = torch.tensor(dtau[0], dtype=ctx.tau_dtype)
+                    return ds, g_tau, None, None, None, None, None
+
+            cls.fn = LbmRollout
+        return cls.fn
+
+
+def rollout(sim: "Sim", nsteps: int, K: int, s=None, tau=None, rho0=None, u0=None):
+    """Differentiable run: init at equilibrium(rho0, u0), `nsteps` steps with a
+    checkpoint every K steps, returns (rho, u) of the final state.  Gradients
+    flow to the solid fraction `s` (device tensor) and `tau` (0-d tensor)
+    through the library's adjoint (lbm_backward)."""
+    torch = _torch()
+    if tau is None:
+        tau = torch.tensor(sim.tau, dtype=torch.float64)
+    return _Rollout.get().apply(s, tau, sim, nsteps, K, rho0, u0)
