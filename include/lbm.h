@@ -144,6 +144,24 @@ lbm_ctx *lbm_create_batch(int lattice, int n, const int *nx, const int *ny, cons
 /* off: host array of n+1 int64; off[d] = first packed cell of domain d, off[n] = total cells. */
 int lbm_batch_offsets(const lbm_ctx *ctx, int64_t *off);
 
+/*
+ * Work decomposition of a batch.  A batch is stepped as a list of tiles of
+ * `tile` consecutive cells of one domain, one workgroup each; with
+ * persistent = 1, n steps run as one cooperative launch whose resident
+ * workgroups stride over the tiles with a grid barrier between steps, else
+ * one launch per step.  By default the first lbm_step / lbm_capture_graph
+ * times tile in {64, 128, 256} x both launch modes on a copy of the state
+ * (restored afterwards) and keeps the fastest, caching the choice in the file
+ * named by LBM_AUTOTUNE_CACHE (default ~/.cache/lbm_mi355x_autotune.txt);
+ * LBM_AUTOTUNE=0 skips the timing.  lbm_batch_tuning(ctx, tile, persistent)
+ * fixes the choice (tile 0 keeps the tile, persistent -1 keeps the mode;
+ * 0 and -1 together return to automatic).  lbm_batch_config reports it.
+ * Batch domains hold fewer than 2^24 cells each and use the in-place pattern;
+ * solid cells and partial bounce-back are single-domain features.
+ */
+int lbm_batch_tuning(lbm_ctx *ctx, int tile, int persistent);
+int lbm_batch_config(const lbm_ctx *ctx, int *tile, int *persistent);
+
 /* Free everything the context owns (synchronises its stream).  NULL is a no-op. */
 void lbm_destroy(lbm_ctx *ctx);
 

@@ -474,6 +474,7 @@ extern "C" int lbm_set_solid(lbm_ctx *c, const uint8_t *flags, int on_device) {
 
 extern "C" int lbm_set_solid_fraction(lbm_ctx *c, const float *s, int on_device) {
     if (!c) return fail(LBM_EINVAL, "null context");
+    if (c->batch) return fail(LBM_EUNSUPPORTED, "partial bounce-back is not supported on batch contexts");
     if (on_device != 0 && on_device != 1) return fail(LBM_EINVAL, "on_device must be 0 or 1");
     int rc = ensure_device(c);
     if (rc) return rc;
@@ -537,6 +538,17 @@ extern "C" int lbm_step(lbm_ctx *c, int n) {
     if (!c->A) return fail(LBM_ESTATE, "state not initialised (call lbm_init_equilibrium)");
     int rc = ensure_device(c);
     if (rc) return rc;
+    if (c->batch && n > 0) {
+        rc = batch_autotune(c);
+        if (rc) return rc;
+        if (!c->tape_recording && batch_uses_persistent(c)) {
+            hipError_t e = batch_persistent_steps(c, n);
+            if (e != hipSuccess) return hip_fail(e, "lbm_step (persistent batch)");
+            c->t += n;
+            c->moved_since_tape = true;
+            return LBM_OK;
+        }
+    }
     for (int k = 0; k < n; ++k) {
         hipError_t e = forward_step(c);
         if (e != hipSuccess) return hip_fail(e, "lbm_step");

@@ -80,6 +80,7 @@ struct lbm_ctx {
     int graph_steps = 0;
     int64_t graph_t0 = 0;
     void *graph_A = nullptr;
+    int graph_persistent = 0;
 };
 
 namespace lbm {
@@ -108,5 +109,8 @@ void batch_release(lbm_ctx *c);
 hipError_t batch_init(lbm_ctx *c, const void *rho, const void *u, bool f64);
 hipError_t batch_step(lbm_ctx *c);
 hipError_t batch_moments(lbm_ctx *c, bool odd, void *rho, void *u, bool f64, double *partial);
+hipError_t batch_persistent_steps(lbm_ctx *c, int n);
+bool batch_uses_persistent(const lbm_ctx *c);
+int batch_autotune(lbm_ctx *c);
 
 }  // namespace lbm

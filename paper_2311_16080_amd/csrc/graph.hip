@@ -24,14 +24,43 @@ extern "C" int lbm_capture_graph(lbm_ctx *c, int n) {
     if (c->tape_recording) return fail(LBM_ESTATE, "cannot capture while a tape is recording");
     (void)hipSetDevice(c->device);
     drop_graph(c);
+    if (c->batch) {
+        int rc = batch_autotune(c);
+        if (rc) return rc;
+    }
     const int64_t t0 = c->t;
     void *A0 = c->A, *B0 = c->B;
-    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    hipError_t le = hipSuccess;
-    for (int k = 0; k < n && le == hipSuccess; ++k) le = forward_step(c);
     hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(c->stream, &g);
+    hipError_t e = hipSuccess, le = hipSuccess;
+    bool captured = false;
+    if (c->batch && batch_uses_persistent(c)) {
+        // one persistent cooperative launch for all n steps, if the runtime can
+        // capture it; otherwise fall back to one node per step
+        e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            le = batch_persistent_steps(c, n);
+            e = hipStreamEndCapture(c->stream, &g);
+            if (le == hipSuccess && e == hipSuccess && g) {
+                captured = true;
+                c->graph_persistent = 1;
+            } else {
+                if (g) (void)hipGraphDestroy(g);
+                g = nullptr;
+                (void)hipGetLastError();
+                le = e = hipSuccess;
+            }
+        } else {
+            (void)hipGetLastError();
+            e = hipSuccess;
+        }
+    }
+    if (!captured) {
+        c->graph_persistent = 0;
+        e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        for (int k = 0; k < n && le == hipSuccess; ++k) le = forward_step(c);
+        e = hipStreamEndCapture(c->stream, &g);
+    }
     c->t = t0;
     c->A = A0;
     c->B = B0;

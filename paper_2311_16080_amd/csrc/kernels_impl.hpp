@@ -41,9 +41,11 @@ __device__ __forceinline__ bool block_cell(const Params<CT> &p, int &X, int &Y, 
     return Z < p.nZ;
 }
 
+// One cell of one step.  p: the domain's parameters; A (and B for the push
+// step) the domain's state; pending: the state read needs the Zou-He closure.
 template <class L, class ST, int MODE, bool HAS_S, int NT>
-__global__ void __launch_bounds__(kMaxBlock) k_step(const Params<typename Store<ST>::CT> p, ST *__restrict__ A,
-                                                    ST *__restrict__ B) {
+__device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &p, ST *__restrict__ A,
+                                          ST *__restrict__ B, int X, int Y, int Z, int pending) {
     // NT 0: plain accesses.  NT 1: non-temporal loads and stores wherever the
     // access is aligned with the wavefront (the local even step; directions
     // without a Z component in the odd / push steps); Z-shifted accesses stay
@@ -55,8 +57,6 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(const Params<typename Store<
     constexpr bool NTZS = (NT == 2) || (NT == 3);
     using CT = typename Store<ST>::CT;
     constexpr int Q = L::Q;
-    int X, Y, Z;
-    if (!block_cell(p, X, Y, Z)) return;
     const int64_t cell = ((int64_t)X * p.nY + Y) * p.nZ + Z;
     uint32_t nbm = 0;
     if (p.flags) {
@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(const Params<typename Store<
     }
 
     const int zf = zh_face_of(p, e);
-    if (zf >= 0 && (MODE == 1 || p.zh_pending)) zouhe<L>(h, p, zf);
+    if (zf >= 0 && (MODE == 1 || pending)) zouhe<L>(h, p, zf);
 
     CT hp[Q];
     CT rho, ux, uy, uz;
@@ -114,6 +114,14 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(const Params<typename Store<
             }
         }
     });
+}
+
+template <class L, class ST, int MODE, bool HAS_S, int NT>
+__global__ void __launch_bounds__(kMaxBlock) k_step(const Params<typename Store<ST>::CT> p, ST *__restrict__ A,
+                                                    ST *__restrict__ B) {
+    int X, Y, Z;
+    if (!block_cell(p, X, Y, Z)) return;
+    step_cell<L, ST, MODE, HAS_S, NT>(p, A, B, X, Y, Z, p.zh_pending);
 }
 
 // f = feq(rho, u) written in natural order.  rho: N, u: D planes of N in the
@@ -147,85 +155,63 @@ __global__ void __launch_bounds__(kMaxBlock) k_init(const Params<typename Store<
     });
 }
 
-// Moments of the current state.  ODD = the state is the AA buffer after an
-// even step (post-collision values in swapped slots): the populations are
-// gathered as the odd step would.  Writes rho, u (caller axes, OT) and one
-// row of FP64 partial sums per block: mass, P_X, P_Y, P_Z, kinetic energy.
-template <class L, class ST, class OT, bool ODD>
-__global__ void __launch_bounds__(kMaxBlock) k_moments(const Params<typename Store<ST>::CT> p,
-                                                       const ST *__restrict__ A, OT *__restrict__ rho_out,
-                                                       OT *__restrict__ u_out, double *__restrict__ partial,
-                                                       int64_t N) {
+// Moments of one cell of the current state.  ODD = the state is the AA buffer
+// after an even step (post-collision values in swapped slots): the
+// populations are gathered as the odd step would.  Returns false for a solid
+// cell (rho0, u = 0).
+template <class L, class ST, bool ODD>
+__device__ __forceinline__ bool moments_cell(const Params<typename Store<ST>::CT> &p, const ST *__restrict__ A,
+                                             int X, int Y, int Z, int pending, typename Store<ST>::CT &rho,
+                                             typename Store<ST>::CT &ux, typename Store<ST>::CT &uy,
+                                             typename Store<ST>::CT &uz) {
     using CT = typename Store<ST>::CT;
     constexpr int Q = L::Q;
-    __shared__ double red[5][kMaxBlock];
-    int X, Y, Z;
-    const bool inside = block_cell(p, X, Y, Z);
-    double m[5] = {0, 0, 0, 0, 0};
-    if (inside) {
-        const int64_t cell = ((int64_t)X * p.nY + Y) * p.nZ + Z;
-        uint32_t nbm = 0;
-        bool solid = false;
-        if (p.flags) {
-            const uint8_t fl = p.flags[cell];
-            solid = fl & 1;
-            if (fl & 2) nbm = p.nbm[cell];
-        }
-        CT rho = p.rho0, ux = 0, uy = 0, uz = 0;
-        if (!solid) {
-            const uint32_t e = edge_bits(p, X, Y, Z);
-            const uint32_t irr = irregular_mask<L>(e, nbm);
-            CT h[Q];
-            if constexpr (ODD) {
-                unroll<Q>([&](auto I) {
-                    constexpr int O = opp<L>(I);
-                    if (!((irr >> I) & 1u)) {
-                        const int64_t src =
-                            cell - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
-                        h[I] = ldh<L, ST, O>(A, p.plane, src);
-                    } else {
-                        const Nb nb = classify_src<L>(p, X, Y, Z, I, nbm);
-                        h[I] = (nb.kind == NB_FLUID) ? ldh<L, ST, O>(A, p.plane, nb.cell)
-                                                     : ldh<L, ST, I>(A, p.plane, cell);
-                    }
-                });
-            } else {
-                unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(A, p.plane, cell); });
-            }
-            const int zf = zh_face_of(p, e);
-            if (zf >= 0 && (ODD || p.zh_pending)) zouhe<L>(h, p, zf);
-            CT drho = 0, jx = 0, jy = 0, jz = 0;
-            unroll<Q>([&](auto I) {
-                drho += h[I];
-                if constexpr (L::c[I][0] != 0) jx += (CT)L::c[I][0] * h[I];
-                if constexpr (L::c[I][1] != 0) jy += (CT)L::c[I][1] * h[I];
-                if constexpr (L::c[I][2] != 0) jz += (CT)L::c[I][2] * h[I];
-            });
-            rho = p.rho0 + drho;
-            const CT inv = (CT)1 / rho;
-            ux = jx * inv;
-            uy = jy * inv;
-            uz = jz * inv;
-            const double r = (double)rho, vx = (double)ux, vy = (double)uy, vz = (double)uz;
-            m[0] = r;
-            m[1] = r * vx;
-            m[2] = r * vy;
-            m[3] = r * vz;
-            m[4] = 0.5 * r * (vx * vx + vy * vy + vz * vz);
-        }
-        if (rho_out) rho_out[cell] = (OT)rho;
-        if (u_out) {
-            if constexpr (L::D == 2) {
-                u_out[cell] = (OT)uy;
-                u_out[N + cell] = (OT)uz;
-            } else {
-                u_out[cell] = (OT)ux;
-                u_out[N + cell] = (OT)uy;
-                u_out[2 * N + cell] = (OT)uz;
-            }
-        }
+    const int64_t cell = ((int64_t)X * p.nY + Y) * p.nZ + Z;
+    uint32_t nbm = 0;
+    rho = p.rho0;
+    ux = uy = uz = 0;
+    if (p.flags) {
+        const uint8_t fl = p.flags[cell];
+        if (fl & 1) return false;
+        if (fl & 2) nbm = p.nbm[cell];
     }
-    if (!partial) return;
+    const uint32_t e = edge_bits(p, X, Y, Z);
+    const uint32_t irr = irregular_mask<L>(e, nbm);
+    CT h[Q];
+    if constexpr (ODD) {
+        unroll<Q>([&](auto I) {
+            constexpr int O = opp<L>(I);
+            if (!((irr >> I) & 1u)) {
+                const int64_t src = cell - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
+                h[I] = ldh<L, ST, O>(A, p.plane, src);
+            } else {
+                const Nb nb = classify_src<L>(p, X, Y, Z, I, nbm);
+                h[I] = (nb.kind == NB_FLUID) ? ldh<L, ST, O>(A, p.plane, nb.cell) : ldh<L, ST, I>(A, p.plane, cell);
+            }
+        });
+    } else {
+        unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(A, p.plane, cell); });
+    }
+    const int zf = zh_face_of(p, e);
+    if (zf >= 0 && (ODD || pending)) zouhe<L>(h, p, zf);
+    CT drho = 0, jx = 0, jy = 0, jz = 0;
+    unroll<Q>([&](auto I) {
+        drho += h[I];
+        if constexpr (L::c[I][0] != 0) jx += (CT)L::c[I][0] * h[I];
+        if constexpr (L::c[I][1] != 0) jy += (CT)L::c[I][1] * h[I];
+        if constexpr (L::c[I][2] != 0) jz += (CT)L::c[I][2] * h[I];
+    });
+    rho = p.rho0 + drho;
+    const CT inv = (CT)1 / rho;
+    ux = jx * inv;
+    uy = jy * inv;
+    uz = jz * inv;
+    return true;
+}
+
+// Block sum of the five moment sums into partial[row * 5 ..]
+__device__ __forceinline__ void block_sums(const double (&m)[5], double *partial, int64_t row) {
+    __shared__ double red[5][kMaxBlock];
     const int t = (int)threadIdx.x;
     unroll<5>([&](auto K) { red[K][t] = m[K]; });
     __syncthreads();
@@ -233,7 +219,49 @@ __global__ void __launch_bounds__(kMaxBlock) k_moments(const Params<typename Sto
         if (t < w) unroll<5>([&](auto K) { red[K][t] += red[K][t + w]; });
         __syncthreads();
     }
-    if (t == 0) unroll<5>([&](auto K) { partial[(int64_t)blockIdx.x * 5 + K] = red[K][0]; });
+    if (t == 0) unroll<5>([&](auto K) { partial[row * 5 + K] = red[K][0]; });
+}
+
+template <class L, class CT, class OT>
+__device__ __forceinline__ void store_moments(OT *rho_out, OT *u_out, int64_t gcell, int64_t N, CT rho, CT ux, CT uy,
+                                              CT uz) {
+    if (rho_out) rho_out[gcell] = (OT)rho;
+    if (u_out) {
+        if constexpr (L::D == 2) {
+            u_out[gcell] = (OT)uy;
+            u_out[N + gcell] = (OT)uz;
+        } else {
+            u_out[gcell] = (OT)ux;
+            u_out[N + gcell] = (OT)uy;
+            u_out[2 * N + gcell] = (OT)uz;
+        }
+    }
+}
+
+// rho, u of the current state in the caller's axes (OT) and one row of FP64
+// partial sums per block: mass, P_X, P_Y, P_Z, kinetic energy.
+template <class L, class ST, class OT, bool ODD>
+__global__ void __launch_bounds__(kMaxBlock) k_moments(const Params<typename Store<ST>::CT> p,
+                                                       const ST *__restrict__ A, OT *__restrict__ rho_out,
+                                                       OT *__restrict__ u_out, double *__restrict__ partial,
+                                                       int64_t N) {
+    using CT = typename Store<ST>::CT;
+    int X, Y, Z;
+    const bool inside = block_cell(p, X, Y, Z);
+    double m[5] = {0, 0, 0, 0, 0};
+    if (inside) {
+        CT rho, ux, uy, uz;
+        if (moments_cell<L, ST, ODD>(p, A, X, Y, Z, p.zh_pending, rho, ux, uy, uz)) {
+            const double r = (double)rho, vx = (double)ux, vy = (double)uy, vz = (double)uz;
+            m[0] = r;
+            m[1] = r * vx;
+            m[2] = r * vy;
+            m[3] = r * vz;
+            m[4] = 0.5 * r * (vx * vx + vy * vy + vz * vz);
+        }
+        store_moments<L>(rho_out, u_out, ((int64_t)X * p.nY + Y) * p.nZ + Z, N, rho, ux, uy, uz);
+    }
+    if (partial) block_sums(m, partial, blockIdx.x);
 }
 
 // Per-cell flag byte (bit0 solid, bit1 some source x - c_k is solid) and the

@@ -53,6 +53,8 @@ SIGNATURES = {
     "lbm_create": (_vp, [_i, _i, _i, _i, _d, ctypes.POINTER(lbm_bc)]),
     "lbm_create_batch": (_vp, [_i, _i, _ip, _ip, _ip, _dp, ctypes.POINTER(lbm_bc)]),
     "lbm_batch_offsets": (_i, [_vp, ctypes.POINTER(ctypes.c_int64)]),
+    "lbm_batch_tuning": (_i, [_vp, _i, _i]),
+    "lbm_batch_config": (_i, [_vp, _ip, _ip]),
     "lbm_destroy": (None, [_vp]),
     "lbm_set_options": (_i, [_vp, ctypes.POINTER(lbm_options)]),
     "lbm_set_params": (_i, [_vp, _d, ctypes.POINTER(lbm_bc)]),
@@ -92,6 +94,14 @@ def lib() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python paper_2311_16080_amd/build.py` "
                                "(or __graft_entry__.build())")
+        # PyTorch-ROCm carries its own HIP runtime.  Loading torch first makes
+        # liblbm.so bind to that same runtime (same soname), so the library and
+        # torch share one HIP/HSA instance, devices and streams; loading
+        # liblbm.so first would bring a second runtime into the process.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
@@ -359,3 +369,129 @@ def rollout(sim: "Sim", nsteps: int, K: int, s=None, tau=None, rho0=None, u0=Non
     if tau is None:
         tau = torch.tensor(sim.tau, dtype=torch.float64)
     return _Rollout.get().apply(s, tau, sim, nsteps, K, rho0, u0)
+
+
+class BatchSim:
+    """Many independent domains of one lattice advanced together (wraps a
+    batch lbm_ctx).  Fields are packed domain after domain: rho [Ntot],
+    u [D, Ntot]; `offsets[d]` is the first packed cell of domain d."""
+
+    def __init__(self, lattice, shapes, taus, faces_list=None, storage: str = "f32", rho0: float = 1.0):
+        self.lattice = LATTICES[lattice] if isinstance(lattice, str) else int(lattice)
+        self.Q = Q_OF[self.lattice]
+        self.D = D_OF[self.lattice]
+        n = len(shapes)
+        self.n = n
+        self.shapes = [tuple(int(v) for v in sh)[: self.D] for sh in shapes]
+        nx = (ctypes.c_int * n)(*[sh[0] for sh in self.shapes])
+        ny = (ctypes.c_int * n)(*[sh[1] for sh in self.shapes])
+        nz = (ctypes.c_int * n)(*[(sh[2] if self.D == 3 else 0) for sh in self.shapes])
+        self.taus = [float(t) for t in taus]
+        tau = (ctypes.c_double * n)(*self.taus)
+        bcs = None
+        if faces_list is not None:
+            bcs = (lbm_bc * n)(*[make_bc(f) for f in faces_list])
+        self.storage = storage
+        h = lib().lbm_create_batch(self.lattice, n, nx, ny, nz, tau, bcs)
+        if not h:
+            raise LbmError(LBM_EINVAL, last_error())
+        self.h = ctypes.c_void_p(h)
+        opt = lbm_options(STORAGE[storage], F64 if storage == "f64" else F32, INPLACE, 0, float(rho0))
+        check(lib().lbm_set_options(self.h, ctypes.byref(opt)))
+        off = (ctypes.c_int64 * (n + 1))()
+        check(lib().lbm_batch_offsets(self.h, off))
+        self.offsets = np.array(list(off), dtype=np.int64)
+        self.N = int(self.offsets[-1])
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            try:
+                lib().lbm_destroy(h)
+            except Exception:
+                pass
+            self.h = None
+
+    def use_current_stream(self):
+        torch = _torch()
+        check(lib().lbm_set_stream(self.h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    def tuning(self, tile: int = 0, persistent: int = -1):
+        check(lib().lbm_batch_tuning(self.h, int(tile), int(persistent)))
+
+    def config(self):
+        t, p = ctypes.c_int(), ctypes.c_int()
+        check(lib().lbm_batch_config(self.h, ctypes.byref(t), ctypes.byref(p)))
+        return t.value, p.value
+
+    def init_equilibrium(self, rho=None, u=None):
+        torch = _torch()
+        dt = F64
+        if u is not None:
+            u = u.contiguous()
+            dt = F64 if u.dtype == torch.float64 else F32
+        if rho is not None:
+            rho = rho.contiguous().to(u.dtype if u is not None else rho.dtype)
+            dt = F64 if rho.dtype == torch.float64 else F32
+        self._keep = [x for x in (rho, u) if x is not None]
+        check(lib().lbm_init_equilibrium(self.h, _ptr(rho), _ptr(u), dt))
+
+    def step(self, n: int = 1):
+        check(lib().lbm_step(self.h, int(n)))
+
+    @property
+    def t(self) -> int:
+        return int(lib().lbm_time(self.h))
+
+    def moments(self, dtype=None, sums: bool = False):
+        """packed rho [Ntot], u [D, Ntot] (+ per-domain sums [n, 5] if sums)."""
+        torch = _torch()
+        dtype = dtype or (torch.float64 if self.storage == "f64" else torch.float32)
+        rho = torch.empty((self.N,), dtype=dtype, device="cuda")
+        u = torch.empty((self.D, self.N), dtype=dtype, device="cuda")
+        out = (ctypes.c_double * (5 * self.n))()
+        check(lib().lbm_moments(self.h, _ptr(rho), _ptr(u), F64 if dtype == torch.float64 else F32,
+                                out if sums else None))
+        if sums:
+            return rho, u, np.array(list(out)).reshape(self.n, 5)
+        return rho, u
+
+    def sums(self) -> np.ndarray:
+        out = (ctypes.c_double * (5 * self.n))()
+        check(lib().lbm_moments(self.h, None, None, F64, out))
+        return np.array(list(out)).reshape(self.n, 5)
+
+    def domain(self, field, d: int):
+        """View of domain d in a packed field ([..., Ntot] -> [..., *shape_d])."""
+        a, b = int(self.offsets[d]), int(self.offsets[d + 1])
+        return field[..., a:b].reshape(field.shape[:-1] + self.shapes[d])
+
+    def capture_graph(self, n: int):
+        check(lib().lbm_capture_graph(self.h, int(n)))
+
+    def graph_launch(self):
+        check(lib().lbm_graph_launch(self.h))
+
+    def sync(self):
+        check(lib().lbm_sync(self.h))
+
+    def tape_begin(self, K: int, max_steps: int):
+        check(lib().lbm_tape_begin(self.h, int(K), int(max_steps)))
+
+    def tape_end(self):
+        check(lib().lbm_tape_end(self.h))
+
+    def backward(self, dL_drho=None, dL_du=None):
+        """Adjoint of the taped steps: (dL_dtau [n], dL_duw [n, 6, 3])."""
+        torch = _torch()
+        ref = dL_du if dL_du is not None else dL_drho
+        dt = F32 if (ref is not None and ref.dtype == torch.float32) else F64
+        tt = torch.float32 if dt == F32 else torch.float64
+        if dL_drho is not None:
+            dL_drho = dL_drho.to(tt).contiguous()
+        if dL_du is not None:
+            dL_du = dL_du.to(tt).contiguous()
+        dtau = (ctypes.c_double * self.n)()
+        duw = (ctypes.c_double * (self.n * 18))()
+        check(lib().lbm_backward(self.h, _ptr(dL_drho), _ptr(dL_du), dt, None, dtau, duw))
+        return np.array(list(dtau)), np.array(list(duw)).reshape(self.n, 6, 3)
