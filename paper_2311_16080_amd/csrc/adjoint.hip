@@ -106,21 +106,15 @@ __device__ __forceinline__ void zouhe_transpose(CT *a, const Params<CT> &p, int 
 // (CT planes); Ao: a(t).  ds: per-cell dL/ds accumulator (null without s).
 // acc: per-block accumulator rows of kAdjSlots doubles (dL/dtau, dL/du_w[6][3]).
 template <class L, class ST>
-__global__ void __launch_bounds__(kMaxBlock) k_adjoint(const Params<typename Store<ST>::CT> p, const ST *__restrict__ F,
-                                                       const typename Store<ST>::CT *__restrict__ An,
-                                                       typename Store<ST>::CT *__restrict__ Ao,
-                                                       typename Store<ST>::CT *__restrict__ ds, double *__restrict__ acc,
-                                                       double inv_tau2) {
+__device__ __forceinline__ void adjoint_cell(const Params<typename Store<ST>::CT> &p, const ST *__restrict__ F,
+                                             const typename Store<ST>::CT *__restrict__ An,
+                                             typename Store<ST>::CT *__restrict__ Ao,
+                                             typename Store<ST>::CT *__restrict__ ds, int X, int Y, int Z,
+                                             int pending, double inv_tau2, double (&part)[kAdjSlots]) {
     using CT = typename Store<ST>::CT;
     constexpr int Q = L::Q;
-    __shared__ double red[kAdjSlots][kMaxBlock / 64];
-    int X, Y, Z;
-    const bool inside = adj_block_cell(p, X, Y, Z);
-    double part[kAdjSlots];
-#pragma unroll
-    for (int k = 0; k < kAdjSlots; ++k) part[k] = 0.0;
     const int64_t P = p.plane;
-    if (inside) {
+    {
         const int64_t cell = ((int64_t)X * p.nY + Y) * p.nZ + Z;
         uint32_t nbm = 0;
         bool solid = false;
@@ -138,7 +132,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_adjoint(const Params<typename Sto
             CT h[Q];
             unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(F, P, cell); });
             const int zf = zh_face_of(p, e);
-            if (zf >= 0 && p.zh_pending) zouhe<L>(h, p, zf);
+            if (zf >= 0 && pending) zouhe<L>(h, p, zf);
             // forward quantities
             CT drho = 0, jx = 0, jy = 0, jz = 0;
             unroll<Q>([&](auto I) {
@@ -245,11 +239,15 @@ __global__ void __launch_bounds__(kMaxBlock) k_adjoint(const Params<typename Sto
                 if (has_s) v += s * b[O];
                 a[J] = v;
             });
-            if (zf >= 0 && p.zh_pending) zouhe_transpose<L>(a, p, zf);
+            if (zf >= 0 && pending) zouhe_transpose<L>(a, p, zf);
             unroll<Q>([&](auto I) { Ao[(int64_t)I * P + cell] = a[I]; });
         }
     }
-    // block partial sums -> the block's own accumulator row
+}
+
+// block partial sums -> the block's own accumulator row
+__device__ __forceinline__ void adj_block_reduce(const double (&part)[kAdjSlots], double *acc, int64_t row) {
+    __shared__ double red[kAdjSlots][kMaxBlock / 64];
     const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < kAdjSlots; ++k) {
@@ -263,21 +261,36 @@ __global__ void __launch_bounds__(kMaxBlock) k_adjoint(const Params<typename Sto
         for (int k = 0; k < kAdjSlots; ++k) {
             double v = 0.0;
             for (int w = 0; w < nw; ++w) v += red[k][w];
-            acc[(int64_t)blockIdx.x * kAdjSlots + k] += v;
+            acc[row * kAdjSlots + k] += v;
         }
     }
 }
 
+template <class L, class ST>
+__global__ void __launch_bounds__(kMaxBlock) k_adjoint(const Params<typename Store<ST>::CT> p, const ST *__restrict__ F,
+                                                       const typename Store<ST>::CT *__restrict__ An,
+                                                       typename Store<ST>::CT *__restrict__ Ao,
+                                                       typename Store<ST>::CT *__restrict__ ds, double *__restrict__ acc,
+                                                       double inv_tau2) {
+    int X, Y, Z;
+    const bool inside = adj_block_cell(p, X, Y, Z);
+    double part[kAdjSlots];
+#pragma unroll
+    for (int k = 0; k < kAdjSlots; ++k) part[k] = 0.0;
+    if (inside) adjoint_cell<L, ST>(p, F, An, Ao, ds, X, Y, Z, p.zh_pending, inv_tau2, part);
+    adj_block_reduce(part, acc, blockIdx.x);
+}
+
 // a(n) = dL/df(n) from dL/drho, dL/du of the final moments (caller axes), with
 // the Zou-He closure transpose on face cells.  IT = float or double.
+// gcell / N: the cell's index in, and the length of, the caller's fields
 template <class L, class ST, class IT>
-__global__ void __launch_bounds__(kMaxBlock) k_seed(const Params<typename Store<ST>::CT> p, const ST *__restrict__ F,
-                                                    const IT *__restrict__ grho, const IT *__restrict__ gu,
-                                                    typename Store<ST>::CT *__restrict__ Ao, int64_t N) {
+__device__ __forceinline__ void seed_cell(const Params<typename Store<ST>::CT> &p, const ST *__restrict__ F,
+                                          const IT *__restrict__ grho, const IT *__restrict__ gu,
+                                          typename Store<ST>::CT *__restrict__ Ao, int X, int Y, int Z, int pending,
+                                          int64_t gcell, int64_t N) {
     using CT = typename Store<ST>::CT;
     constexpr int Q = L::Q;
-    int X, Y, Z;
-    if (!adj_block_cell(p, X, Y, Z)) return;
     const int64_t cell = ((int64_t)X * p.nY + Y) * p.nZ + Z;
     const int64_t P = p.plane;
     if (p.flags && (p.flags[cell] & 1)) {
@@ -288,7 +301,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_seed(const Params<typename Store<
     CT h[Q];
     unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(F, P, cell); });
     const int zf = zh_face_of(p, e);
-    if (zf >= 0 && p.zh_pending) zouhe<L>(h, p, zf);
+    if (zf >= 0 && pending) zouhe<L>(h, p, zf);
     CT drho = 0, jx = 0, jy = 0, jz = 0;
     unroll<Q>([&](auto I) {
         drho += h[I];
@@ -299,16 +312,16 @@ __global__ void __launch_bounds__(kMaxBlock) k_seed(const Params<typename Store<
     const CT rho = p.rho0 + drho;
     const CT inv = (CT)1 / rho;
     const CT ux = jx * inv, uy = jy * inv, uz = jz * inv;
-    const CT gr = grho ? (CT)grho[cell] : (CT)0;
+    const CT gr = grho ? (CT)grho[gcell] : (CT)0;
     CT gx = 0, gy = 0, gz = 0;
     if (gu) {
         if constexpr (L::D == 2) {
-            gy = (CT)gu[cell];
-            gz = (CT)gu[N + cell];
+            gy = (CT)gu[gcell];
+            gz = (CT)gu[N + gcell];
         } else {
-            gx = (CT)gu[cell];
-            gy = (CT)gu[N + cell];
-            gz = (CT)gu[2 * N + cell];
+            gx = (CT)gu[gcell];
+            gy = (CT)gu[N + gcell];
+            gz = (CT)gu[2 * N + gcell];
         }
     }
     const CT gdotu = gx * ux + gy * uy + gz * uz;
@@ -317,19 +330,26 @@ __global__ void __launch_bounds__(kMaxBlock) k_seed(const Params<typename Store<
         const CT gc = (CT)L::c[I][0] * gx + (CT)L::c[I][1] * gy + (CT)L::c[I][2] * gz;
         a[I] = gr + (gc - gdotu) * inv;
     });
-    if (zf >= 0 && p.zh_pending) zouhe_transpose<L>(a, p, zf);
+    if (zf >= 0 && pending) zouhe_transpose<L>(a, p, zf);
     unroll<Q>([&](auto I) { Ao[(int64_t)I * P + cell] = a[I]; });
+}
+
+template <class L, class ST, class IT>
+__global__ void __launch_bounds__(kMaxBlock) k_seed(const Params<typename Store<ST>::CT> p, const ST *__restrict__ F,
+                                                    const IT *__restrict__ grho, const IT *__restrict__ gu,
+                                                    typename Store<ST>::CT *__restrict__ Ao, int64_t N) {
+    int X, Y, Z;
+    if (!adj_block_cell(p, X, Y, Z)) return;
+    seed_cell<L, ST, IT>(p, F, grho, gu, Ao, X, Y, Z, p.zh_pending, ((int64_t)X * p.nY + Y) * p.nZ + Z, N);
 }
 
 // Natural-order copy of the current in-place state: after an even step the
 // AA buffer holds post-collision values in swapped slots; gather them as the
 // odd step would (boundary slots from the cell itself), no closure.
 template <class L, class ST>
-__global__ void __launch_bounds__(kMaxBlock) k_materialize(const Params<typename Store<ST>::CT> p,
-                                                           const ST *__restrict__ A, ST *__restrict__ D) {
+__device__ __forceinline__ void materialize_cell(const Params<typename Store<ST>::CT> &p, const ST *__restrict__ A,
+                                                 ST *__restrict__ D, int X, int Y, int Z) {
     constexpr int Q = L::Q;
-    int X, Y, Z;
-    if (!adj_block_cell(p, X, Y, Z)) return;
     const int64_t cell = ((int64_t)X * p.nY + Y) * p.nZ + Z;
     const int64_t P = p.plane;
     uint32_t nbm = 0;
@@ -354,6 +374,14 @@ __global__ void __launch_bounds__(kMaxBlock) k_materialize(const Params<typename
     });
 }
 
+template <class L, class ST>
+__global__ void __launch_bounds__(kMaxBlock) k_materialize(const Params<typename Store<ST>::CT> p,
+                                                           const ST *__restrict__ A, ST *__restrict__ D) {
+    int X, Y, Z;
+    if (!adj_block_cell(p, X, Y, Z)) return;
+    materialize_cell<L, ST>(p, A, D, X, Y, Z);
+}
+
 // acc rows [0, rows) summed in a fixed order into out[kAdjSlots]
 __global__ void __launch_bounds__(256) k_adj_reduce(const double *__restrict__ acc, int64_t rows,
                                                     double *__restrict__ out) {
@@ -374,6 +402,135 @@ template <class CT>
 __global__ void __launch_bounds__(256) k_to_float(const CT *__restrict__ src, float *__restrict__ dst, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = (float)src[i];
+}
+
+// ---- batch variants ------------------------------------------------------------
+template <class L, class ST>
+__global__ void __launch_bounds__(kMaxBlock) k_adjoint_batch(const BatchDev b, const ST *__restrict__ F,
+                                                             const typename Store<ST>::CT *__restrict__ An,
+                                                             typename Store<ST>::CT *__restrict__ Ao,
+                                                             double *__restrict__ acc,
+                                                             const double *__restrict__ inv_tau2, int pending) {
+    using CT = typename Store<ST>::CT;
+    const int tile = (int)blockIdx.x;
+    const int d = b.tile_dom[tile];
+    const Params<CT> &p = dom_params<CT>(b, d);
+    const int c = b.tile_start[tile] + (int)threadIdx.x;
+    double part[kAdjSlots];
+#pragma unroll
+    for (int k = 0; k < kAdjSlots; ++k) part[k] = 0.0;
+    if (c < p.nX * p.nY * p.nZ) {
+        int X, Y, Z;
+        split_cell(c, p.nY, p.nZ, X, Y, Z);
+        const int64_t o = b.stoff[d];
+        adjoint_cell<L, ST>(p, F + o, An + o, Ao + o, nullptr, X, Y, Z, pending, inv_tau2[d], part);
+    }
+    adj_block_reduce(part, acc, tile);
+}
+
+template <class L, class ST, class IT>
+__global__ void __launch_bounds__(kMaxBlock) k_seed_batch(const BatchDev b, const ST *__restrict__ F,
+                                                          const IT *__restrict__ grho, const IT *__restrict__ gu,
+                                                          typename Store<ST>::CT *__restrict__ Ao, int pending) {
+    using CT = typename Store<ST>::CT;
+    const int tile = (int)blockIdx.x;
+    const int d = b.tile_dom[tile];
+    const Params<CT> &p = dom_params<CT>(b, d);
+    const int c = b.tile_start[tile] + (int)threadIdx.x;
+    if (c >= p.nX * p.nY * p.nZ) return;
+    int X, Y, Z;
+    split_cell(c, p.nY, p.nZ, X, Y, Z);
+    const int64_t o = b.stoff[d];
+    seed_cell<L, ST, IT>(p, F + o, grho, gu, Ao + o, X, Y, Z, pending, b.cell0[d] + c, b.ncells);
+}
+
+template <class L, class ST>
+__global__ void __launch_bounds__(kMaxBlock) k_materialize_batch(const BatchDev b, const ST *__restrict__ A,
+                                                                 ST *__restrict__ D) {
+    using CT = typename Store<ST>::CT;
+    const int tile = (int)blockIdx.x;
+    const int d = b.tile_dom[tile];
+    const Params<CT> &p = dom_params<CT>(b, d);
+    const int c = b.tile_start[tile] + (int)threadIdx.x;
+    if (c >= p.nX * p.nY * p.nZ) return;
+    int X, Y, Z;
+    split_cell(c, p.nY, p.nZ, X, Y, Z);
+    const int64_t o = b.stoff[d];
+    materialize_cell<L, ST>(p, A + o, D + o, X, Y, Z);
+}
+
+// one workgroup per domain; rows summed by a fixed thread/row assignment and
+// a fixed tree, so the result is deterministic
+__global__ void __launch_bounds__(256) k_adj_reduce_batch(const double *__restrict__ acc,
+                                                          const int64_t *__restrict__ rbeg,
+                                                          const int64_t *__restrict__ rend, double *__restrict__ out) {
+    __shared__ double red[256];
+    const int d = (int)blockIdx.x;
+    const int64_t r0 = rbeg[d], r1 = rend[d];
+    for (int k = 0; k < kAdjSlots; ++k) {
+        double v = 0.0;
+        for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) v += acc[r * kAdjSlots + k];
+        red[threadIdx.x] = v;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[(int64_t)d * kAdjSlots + k] = red[0];
+        __syncthreads();
+    }
+}
+
+template <class L, class ST>
+static hipError_t adj_batch_dispatch(const BatchAdjLaunch &g) {
+    using CT = typename Store<ST>::CT;
+    const dim3 grid(g.grid), block(g.block);
+    switch (g.op) {
+        case ADJ_STEP:
+            hipLaunchKernelGGL((k_adjoint_batch<L, ST>), grid, block, 0, g.stream, g.b, static_cast<const ST *>(g.F),
+                               static_cast<const CT *>(g.An), static_cast<CT *>(g.Ao), g.acc, g.inv_tau2, g.pending);
+            break;
+        case ADJ_SEED:
+            if (g.in_f64)
+                hipLaunchKernelGGL((k_seed_batch<L, ST, double>), grid, block, 0, g.stream, g.b,
+                                   static_cast<const ST *>(g.F), static_cast<const double *>(g.grho),
+                                   static_cast<const double *>(g.gu), static_cast<CT *>(g.Ao), g.pending);
+            else
+                hipLaunchKernelGGL((k_seed_batch<L, ST, float>), grid, block, 0, g.stream, g.b,
+                                   static_cast<const ST *>(g.F), static_cast<const float *>(g.grho),
+                                   static_cast<const float *>(g.gu), static_cast<CT *>(g.Ao), g.pending);
+            break;
+        case ADJ_MATERIALIZE:
+            hipLaunchKernelGGL((k_materialize_batch<L, ST>), grid, block, 0, g.stream, g.b,
+                               static_cast<const ST *>(g.F), static_cast<ST *>(g.D));
+            break;
+        case ADJ_REDUCE:
+            hipLaunchKernelGGL(k_adj_reduce_batch, dim3(g.b.ndom), dim3(256), 0, g.stream, g.acc, g.rbeg, g.rend,
+                               g.out);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <class L>
+static hipError_t adj_batch_storage(const BatchAdjLaunch &g) {
+    switch (g.storage) {
+        case ST_F64: return adj_batch_dispatch<L, double>(g);
+        case ST_F32: return adj_batch_dispatch<L, float>(g);
+        case ST_F16: return adj_batch_dispatch<L, _Float16>(g);
+        case ST_BF16: return adj_batch_dispatch<L, bf16_t>(g);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_adjoint_batch(const BatchAdjLaunch &g) {
+    switch (g.lattice) {
+        case LAT_D2Q9: return adj_batch_storage<D2Q9>(g);
+        case LAT_D3Q19: return adj_batch_storage<D3Q19>(g);
+        case LAT_D3Q27: return adj_batch_storage<D3Q27>(g);
+    }
+    return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,6 +1,6 @@
 // adjoint.hpp -- internal interface of the adjoint kernels (not public ABI).
 #pragma once
-#include "kernels.hpp"
+#include "batch.hpp"
 
 namespace lbm {
 
@@ -30,6 +30,34 @@ struct AdjLaunch {
 };
 
 hipError_t launch_adjoint(const AdjLaunch &g);
+
+// Batch variants: the same ops over a tile list (workgroup k = tile k); the
+// adjoint buffers use the state's per-domain offsets; acc holds one row per
+// tile.  ADJ_REDUCE sums the rows [rbeg[d], rend[d]) of each domain d into
+// out[d * kAdjSlots ...] in a fixed order.
+enum : int { ADJ_REDUCE = 4 };
+
+struct BatchAdjLaunch {
+    int op;
+    int lattice;
+    int storage;
+    BatchDev b;
+    const void *F;
+    const void *An;
+    void *Ao;
+    void *D;
+    double *acc;
+    const double *inv_tau2;   // [ndom] 1 / tau_d^2
+    const void *grho, *gu;
+    int in_f64;
+    int pending;
+    const int64_t *rbeg, *rend;
+    double *out;
+    unsigned grid, block;
+    hipStream_t stream;
+};
+
+hipError_t launch_adjoint_batch(const BatchAdjLaunch &g);
 hipError_t launch_adj_reduce(const double *acc, int64_t rows, double *out, hipStream_t s);
 
 }  // namespace lbm

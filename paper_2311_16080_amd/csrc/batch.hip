@@ -185,6 +185,8 @@ static BatchLaunch blaunch(lbm_ctx *c) {
     return g;
 }
 
+BatchLaunch lbm::batch_launch_of(lbm_ctx *c) { return blaunch(c); }
+
 hipError_t lbm::batch_init(lbm_ctx *c, const void *rho, const void *u, bool f64) {
     return batch_launch_init(blaunch(c), rho, u, f64 ? 1 : 0);
 }

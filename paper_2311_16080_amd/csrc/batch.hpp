@@ -32,7 +32,29 @@ struct BatchLaunch {
     hipStream_t stream;
 };
 
+// local cell c of a domain -> (X, Y, Z); c < 2^24 (small domains), so the
+// float reciprocal quotient is off by at most one and is corrected
+__device__ __forceinline__ void split_cell(int c, int nY, int nZ, int &X, int &Y, int &Z) {
+    const float rz = 1.0f / (float)nZ, ry = 1.0f / (float)nY;
+    int r = (int)((float)c * rz);
+    int z = c - r * nZ;
+    if (z < 0) { r -= 1; z += nZ; } else if (z >= nZ) { r += 1; z -= nZ; }
+    int x = (int)((float)r * ry);
+    int y = r - x * nY;
+    if (y < 0) { x -= 1; y += nY; } else if (y >= nY) { x += 1; y -= nY; }
+    X = x;
+    Y = y;
+    Z = z;
+}
+
+template <class CT>
+__device__ __forceinline__ const Params<CT> &dom_params(const BatchDev &b, int d) {
+    return static_cast<const Params<CT> *>(b.P)[d];
+}
+
 hipError_t batch_launch_step(const BatchLaunch &g, int mode, int pending);
+// natural-order push step A -> B (the recompute step of the backward pass)
+hipError_t batch_launch_push(const BatchLaunch &g, void *B, int pending);
 hipError_t batch_launch_persistent(const BatchLaunch &g, int nsteps, int64_t t0);
 hipError_t batch_launch_init(const BatchLaunch &g, const void *rho, const void *u, int in_f64);
 hipError_t batch_launch_moments(const BatchLaunch &g, bool odd, int pending, void *rho, void *u, int out_f64,

@@ -12,27 +12,8 @@
 
 namespace lbm {
 
-// local cell c of a domain -> (X, Y, Z); c < 2^24 (small domains)
-__device__ __forceinline__ void split_cell(int c, int nY, int nZ, int &X, int &Y, int &Z) {
-    const float rz = 1.0f / (float)nZ, ry = 1.0f / (float)nY;
-    int r = (int)((float)c * rz);
-    int z = c - r * nZ;
-    if (z < 0) { r -= 1; z += nZ; } else if (z >= nZ) { r += 1; z -= nZ; }
-    int x = (int)((float)r * ry);
-    int y = r - x * nY;
-    if (y < 0) { x -= 1; y += nY; } else if (y >= nY) { x += 1; y -= nY; }
-    X = x;
-    Y = y;
-    Z = z;
-}
-
-template <class CT>
-__device__ __forceinline__ const Params<CT> &dom_params(const BatchDev &b, int d) {
-    return static_cast<const Params<CT> *>(b.P)[d];
-}
-
 template <class L, class ST, int MODE, int NT>
-__device__ __forceinline__ void batch_tile(const BatchDev &b, ST *A, int tile, int pending) {
+__device__ __forceinline__ void batch_tile(const BatchDev &b, ST *A, int tile, int pending, ST *B = nullptr) {
     using CT = typename Store<ST>::CT;
     const int d = b.tile_dom[tile];
     const Params<CT> &p = dom_params<CT>(b, d);
@@ -41,12 +22,18 @@ __device__ __forceinline__ void batch_tile(const BatchDev &b, ST *A, int tile, i
     if (c >= n) return;
     int X, Y, Z;
     split_cell(c, p.nY, p.nZ, X, Y, Z);
-    step_cell<L, ST, MODE, false, NT>(p, A + b.stoff[d], nullptr, X, Y, Z, pending);
+    step_cell<L, ST, MODE, false, NT>(p, A + b.stoff[d], MODE == 2 ? B + b.stoff[d] : nullptr, X, Y, Z, pending);
 }
 
 template <class L, class ST, int MODE, int NT>
 __global__ void __launch_bounds__(kMaxBlock) k_step_batch(const BatchDev b, ST *__restrict__ A, int pending) {
     batch_tile<L, ST, MODE, NT>(b, A, (int)blockIdx.x, pending);
+}
+
+template <class L, class ST>
+__global__ void __launch_bounds__(kMaxBlock) k_push_batch(const BatchDev b, const ST *__restrict__ A,
+                                                          ST *__restrict__ B, int pending) {
+    batch_tile<L, ST, 2, 1>(b, const_cast<ST *>(A), (int)blockIdx.x, pending, B);
 }
 
 // n steps in one launch: resident workgroups stride over the tiles; a grid
@@ -136,6 +123,13 @@ static hipError_t b_step(const BatchLaunch &g, int mode, int pending) {
 }
 
 template <class L, class ST>
+static hipError_t b_push(const BatchLaunch &g, void *B, int pending) {
+    hipLaunchKernelGGL((k_push_batch<L, ST>), dim3(g.grid), dim3(g.block), 0, g.stream, g.b,
+                       static_cast<const ST *>(g.A), static_cast<ST *>(B), pending);
+    return hipGetLastError();
+}
+
+template <class L, class ST>
 static hipError_t b_persistent(const BatchLaunch &g, int nsteps, int64_t t0) {
     ST *A = static_cast<ST *>(g.A);
     long long tt = (long long)t0;
@@ -191,6 +185,7 @@ static hipError_t b_dispatch(const BatchLaunch &g, int op, int a, int c, int64_t
         case 2: return b_init<L, ST>(g, p0, p1, a);
         case 3: return b_moments<L, ST>(g, a != 0, c, q0, q1, (int)t0, partial);
         case 4: *occ = b_occupancy<L, ST>((int)g.block); return hipSuccess;
+        case 5: return b_push<L, ST>(g, q0, c);
     }
     return hipErrorInvalidValue;
 }
@@ -219,6 +214,10 @@ static hipError_t b_all(const BatchLaunch &g, int op, int a, int c, int64_t t0, 
 }
 
 hipError_t batch_launch_step(const BatchLaunch &g, int mode, int pending) { return b_all(g, 0, mode, pending, 0); }
+
+hipError_t batch_launch_push(const BatchLaunch &g, void *B, int pending) {
+    return b_all(g, 5, 0, pending, 0, nullptr, nullptr, B);
+}
 
 hipError_t batch_launch_persistent(const BatchLaunch &g, int nsteps, int64_t t0) { return b_all(g, 1, nsteps, 0, t0); }
 

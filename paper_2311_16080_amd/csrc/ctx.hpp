@@ -6,7 +6,7 @@
 #include <vector>
 
 #include "../../include/lbm.h"
-#include "kernels.hpp"
+#include "batch.hpp"
 
 namespace lbm {
 
@@ -111,6 +111,7 @@ hipError_t batch_step(lbm_ctx *c);
 hipError_t batch_moments(lbm_ctx *c, bool odd, void *rho, void *u, bool f64, double *partial);
 hipError_t batch_persistent_steps(lbm_ctx *c, int n);
 bool batch_uses_persistent(const lbm_ctx *c);
+BatchLaunch batch_launch_of(lbm_ctx *c);   // tile-list launch over the current state
 int batch_autotune(lbm_ctx *c);
 
 }  // namespace lbm

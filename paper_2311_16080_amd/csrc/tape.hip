@@ -30,7 +30,9 @@ struct TapeState {
     void *abuf[2] = {nullptr, nullptr};
     void *ds = nullptr;       // N compute-type accumulators
     double *acc = nullptr;    // grid x kAdjSlots
-    double *out = nullptr;    // kAdjSlots
+    double *out = nullptr;    // kAdjSlots per domain
+    double *itau2 = nullptr;  // batch: 1 / tau_d^2 per domain
+    int64_t rows = 0;         // accumulator rows
 };
 }  // namespace lbm
 
@@ -47,6 +49,7 @@ void lbm::tape_release(lbm_ctx *c) {
         dev_free(T->ds);
         dev_free((void *&)T->acc);
         dev_free((void *&)T->out);
+        dev_free((void *&)T->itau2);
         delete T;
     }
     c->tape = nullptr;
@@ -81,7 +84,6 @@ extern "C" int lbm_tape_begin(lbm_ctx *c, int K, int max_steps) {
     if (K < 1 || max_steps < 1) return fail(LBM_EINVAL, "K and max_steps must be >= 1");
     if (!c->A) return fail(LBM_ESTATE, "state not initialised");
     if (c->tape_recording) return fail(LBM_ESTATE, "a tape is already recording");
-    if (c->batch) return fail(LBM_EUNSUPPORTED, "tapes on batch contexts go through the batch backward");
     tape_release(c);
     (void)hipSetDevice(c->device);
     TapeState *T = new (std::nothrow) TapeState();
@@ -97,9 +99,20 @@ extern "C" int lbm_tape_begin(lbm_ctx *c, int K, int max_steps) {
     if (!rc) rc = dev_alloc(&T->ring, (size_t)K * T->sbytes, "tape recompute ring");
     if (!rc) rc = dev_alloc(&T->abuf[0], T->abytes, "adjoint state");
     if (!rc) rc = dev_alloc(&T->abuf[1], T->abytes, "adjoint state");
-    if (!rc) rc = dev_alloc(&T->ds, (size_t)c->N * compute_size(c), "dL/ds accumulator");
-    if (!rc) rc = dev_alloc((void **)&T->acc, (size_t)c->grid * kAdjSlots * sizeof(double), "adjoint sums");
-    if (!rc) rc = dev_alloc((void **)&T->out, kAdjSlots * sizeof(double), "adjoint sums");
+    // batch: one accumulator row per tile of the smallest tile size (any tuning fits)
+    T->rows = c->batch ? c->bgrid : c->grid;
+    if (!rc && !c->batch) rc = dev_alloc(&T->ds, (size_t)c->N * compute_size(c), "dL/ds accumulator");
+    if (!rc) rc = dev_alloc((void **)&T->acc, (size_t)T->rows * kAdjSlots * sizeof(double), "adjoint sums");
+    if (!rc) rc = dev_alloc((void **)&T->out, (size_t)c->ndomains * kAdjSlots * sizeof(double), "adjoint sums");
+    if (!rc && c->batch) {
+        rc = dev_alloc((void **)&T->itau2, (size_t)c->ndomains * sizeof(double), "batch 1/tau^2");
+        if (!rc) {
+            std::vector<double> v(c->ndomains);
+            for (int d = 0; d < c->ndomains; ++d) v[d] = 1.0 / (c->dom[d].tau * c->dom[d].tau);
+            if (hipMemcpy(T->itau2, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+                rc = fail(LBM_EDEVICE, "batch 1/tau^2 upload");
+        }
+    }
     if (rc) {
         tape_release(c);
         return fail(LBM_ENOMEM, "tape for K = %d, max_steps = %d does not fit in device memory (%s)", K, max_steps,
@@ -148,9 +161,32 @@ static AdjLaunch adj_launch(lbm_ctx *c, int op) {
 
 static void set_pending(lbm_ctx *c, int64_t t) { c->pd.zh_pending = c->pf.zh_pending = (t > 0) ? 1 : 0; }
 
+static BatchAdjLaunch badj_launch(lbm_ctx *c, int op, int64_t t) {
+    const BatchLaunch bl = batch_launch_of(c);
+    BatchAdjLaunch g;
+    std::memset(&g, 0, sizeof g);
+    g.op = op;
+    g.lattice = bl.lattice;
+    g.storage = bl.storage;
+    g.b = bl.b;
+    g.grid = bl.grid;
+    g.block = bl.block;
+    g.stream = bl.stream;
+    g.pending = (t > 0) ? 1 : 0;
+    return g;
+}
+
 // natural-order copy of a stored state image taken at time t into dst
 static hipError_t restore_natural(lbm_ctx *c, const void *img, int64_t t, void *dst) {
     TapeState *T = c->tape;
+    if (c->batch && (t & 1)) {
+        BatchAdjLaunch g = badj_launch(c, ADJ_MATERIALIZE, t);
+        g.F = img;
+        g.D = dst;
+        hipError_t e = hipMemsetAsync(dst, 0, T->sbytes, c->stream);  // padding slots stay defined
+        if (e != hipSuccess) return e;
+        return launch_adjoint_batch(g);
+    }
     if (c->opt.pattern == LBM_INPLACE && (t & 1)) {
         AdjLaunch g = adj_launch(c, ADJ_MATERIALIZE);
         g.F = img;
@@ -180,7 +216,15 @@ extern "C" int lbm_backward(lbm_ctx *c, const void *dL_drho, const void *dL_du, 
 
     // seed a(t_end) from the final state
     e = restore_natural(c, c->A, c->t, ring);
-    if (e == hipSuccess) {
+    if (e == hipSuccess && c->batch) {
+        BatchAdjLaunch g = badj_launch(c, ADJ_SEED, c->t);
+        g.F = ring;
+        g.grho = dL_drho;
+        g.gu = dL_du;
+        g.in_f64 = dtype == LBM_F64;
+        g.Ao = T->abuf[cur];
+        e = launch_adjoint_batch(g);
+    } else if (e == hipSuccess) {
         set_pending(c, c->t);
         AdjLaunch g = adj_launch(c, ADJ_SEED);
         g.F = ring;
@@ -190,8 +234,8 @@ extern "C" int lbm_backward(lbm_ctx *c, const void *dL_drho, const void *dL_du, 
         g.Ao = T->abuf[cur];
         e = launch_adjoint(g);
     }
-    if (e == hipSuccess) e = hipMemsetAsync(T->acc, 0, (size_t)c->grid * kAdjSlots * sizeof(double), c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(T->ds, 0, (size_t)c->N * compute_size(c), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(T->acc, 0, (size_t)T->rows * kAdjSlots * sizeof(double), c->stream);
+    if (e == hipSuccess && T->ds) e = hipMemsetAsync(T->ds, 0, (size_t)c->N * compute_size(c), c->stream);
 
     const int nseg = (int)((n + T->K - 1) / T->K);
     void *A0 = c->A, *B0 = c->B;
@@ -202,6 +246,12 @@ extern "C" int lbm_backward(lbm_ctx *c, const void *dL_drho, const void *dL_du, 
         e = restore_natural(c, static_cast<char *>(T->ck) + (size_t)seg * T->sbytes, t0, ring);
         // recompute f(t0 + 1) .. f(t1 - 1) into the ring with the push step
         for (int64_t k = 1; k < t1 - t0 && e == hipSuccess; ++k) {
+            if (c->batch) {
+                BatchLaunch g = batch_launch_of(c);
+                g.A = ring + (size_t)(k - 1) * T->sbytes;
+                e = batch_launch_push(g, ring + (size_t)k * T->sbytes, (t0 + k - 1 > 0) ? 1 : 0);
+                continue;
+            }
             set_pending(c, t0 + k - 1);
             Launch g = make_launch(c);
             g.A = ring + (size_t)(k - 1) * T->sbytes;
@@ -210,6 +260,17 @@ extern "C" int lbm_backward(lbm_ctx *c, const void *dL_drho, const void *dL_du, 
         }
         // adjoint steps backwards
         for (int64_t t = t1 - 1; t >= t0 && e == hipSuccess; --t) {
+            if (c->batch) {
+                BatchAdjLaunch g = badj_launch(c, ADJ_STEP, t);
+                g.F = ring + (size_t)(t - t0) * T->sbytes;
+                g.An = T->abuf[cur];
+                g.Ao = T->abuf[1 - cur];
+                g.acc = T->acc;
+                g.inv_tau2 = T->itau2;
+                e = launch_adjoint_batch(g);
+                cur = 1 - cur;
+                continue;
+            }
             set_pending(c, t);
             AdjLaunch g = adj_launch(c, ADJ_STEP);
             g.F = ring + (size_t)(t - t0) * T->sbytes;
@@ -237,21 +298,38 @@ extern "C" int lbm_backward(lbm_ctx *c, const void *dL_drho, const void *dL_du, 
             e = hipMemsetAsync(dL_ds, 0, (size_t)c->N * sizeof(float), c->stream);
         }
     }
-    double sums[kAdjSlots];
-    if (e == hipSuccess) e = launch_adj_reduce(T->acc, c->grid, T->out, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(sums, T->out, sizeof sums, hipMemcpyDeviceToHost, c->stream);
+    const int nd = c->ndomains;
+    std::vector<double> sums((size_t)nd * kAdjSlots);
+    if (e == hipSuccess) {
+        if (c->batch) {
+            BatchAdjLaunch g = badj_launch(c, ADJ_REDUCE, c->t);
+            g.acc = T->acc;
+            g.rbeg = c->rbeg;
+            g.rend = c->rend;
+            g.out = T->out;
+            e = launch_adjoint_batch(g);
+        } else {
+            e = launch_adj_reduce(T->acc, c->grid, T->out, c->stream);
+        }
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sums.data(), T->out, sums.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "lbm_backward");
-    if (dL_dtau) dL_dtau[0] = sums[0];
-    if (dL_duw) {
-        // internal faces / axes -> caller faces / axes
-        for (int k = 0; k < 18; ++k) dL_duw[k] = 0.0;
-        for (int f = 0; f < 6; ++f)
-            for (int a = 0; a < 3; ++a) {
-                const double v = sums[1 + 3 * f + a];
-                if (c->D == 3) dL_duw[3 * f + a] = v;
-                else if (f >= 2 && a >= 1) dL_duw[3 * (f - 2) + (a - 1)] = v;
-            }
+    for (int d = 0; d < nd; ++d) {
+        const double *S = sums.data() + (size_t)d * kAdjSlots;
+        if (dL_dtau) dL_dtau[d] = S[0];
+        if (dL_duw) {
+            // internal faces / axes -> caller faces / axes
+            double *o = dL_duw + (size_t)d * 18;
+            for (int k = 0; k < 18; ++k) o[k] = 0.0;
+            for (int f = 0; f < 6; ++f)
+                for (int a = 0; a < 3; ++a) {
+                    const double v = S[1 + 3 * f + a];
+                    if (c->D == 3) o[3 * f + a] = v;
+                    else if (f >= 2 && a >= 1) o[3 * (f - 2) + (a - 1)] = v;
+                }
+        }
     }
     return LBM_OK;
 }

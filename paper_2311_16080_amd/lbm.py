@@ -481,8 +481,12 @@ class BatchSim:
     def tape_end(self):
         check(lib().lbm_tape_end(self.h))
 
+    def tape_free(self):
+        check(lib().lbm_tape_free(self.h))
+
     def backward(self, dL_drho=None, dL_du=None):
-        """Adjoint of the taped steps: (dL_dtau [n], dL_duw [n, 6, 3])."""
+        """Adjoint of the taped steps: (dL_dtau [n], dL_duw [n, 6, 3]); dL_drho
+        [Ntot] and dL_du [D, Ntot] are packed like the moments."""
         torch = _torch()
         ref = dL_du if dL_du is not None else dL_drho
         dt = F32 if (ref is not None and ref.dtype == torch.float32) else F64

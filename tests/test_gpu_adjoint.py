@@ -157,7 +157,7 @@ def test_autograd_rollout_matches_finite_differences():
         hm = float(s0[i, j]) - float(sm[i, j])
         with torch.no_grad():
             fd = (float(loss_of(sp, tau.detach())) - float(loss_of(sm, tau.detach()))) / (hp + hm)
-        assert abs(fd - gs[i, j]) <= 1e-5 * max(abs(fd), 1e-6 * abs(float(L))), (i, j, fd, gs[i, j])
+        assert abs(fd - gs[i, j]) <= 1e-5 * max(abs(fd), 1e-6 * abs(float(L.detach()))), (i, j, fd, gs[i, j])
     ht = 1e-6
     with torch.no_grad():
         fd = (float(loss_of(s0, torch.tensor(0.6 + ht, dtype=torch.float64))) -
