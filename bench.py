@@ -77,6 +77,215 @@ def cpu_baseline(n: int, tau: float, target_s: float = 15.0):
             "sample": f"D3Q19 FP64 cavity {n}^3, {k} steps after 1 warm-up step ({dt:.1f} s)"}
 
 
+class Timer:
+    """HIP events on the torch current stream (the stream the library launches on)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.s = torch.cuda.current_stream()
+        self.e0 = torch.cuda.Event(enable_timing=True)
+        self.e1 = torch.cuda.Event(enable_timing=True)
+
+    def __enter__(self):
+        self.torch.cuda.synchronize()
+        self.e0.record(self.s)
+        return self
+
+    def __exit__(self, *exc):
+        self.e1.record(self.s)
+        self.torch.cuda.synchronize()
+        self.ms = self.e0.elapsed_time(self.e1)
+
+
+def storage_variants(torch, lbm, n, tau, steps):
+    """The same cavity with FP16 / BF16 deviation storage (FP32 arithmetic)."""
+    out = {}
+    for st, es in (("f16", 2), ("bf16", 2)):
+        sim = lbm.Sim("D3Q19", (n, n, n), tau, faces=cavity_faces(lbm), storage=st)
+        sim.use_current_stream()
+        sim.init_equilibrium()
+        sim.step(10)
+        with Timer(torch) as T:
+            sim.step(steps)
+        mlups = n ** 3 * steps / (T.ms / 1e3) / 1e6
+        gbps = mlups * 1e6 * 2 * 19 * es / 1e9
+        out[st] = {"MLUPS": round(mlups, 1), "GBps": round(gbps, 1), "frac": round(gbps / PEAK_HBM_GBPS, 4),
+                   "bytes_per_lattice_update": 2 * 19 * es, "steps": steps}
+        del sim
+    return out
+
+
+def _ke_seed(torch, rho, u, n_cells):
+    return 0.5 * (u * u).sum(0) / n_cells, rho * u / n_cells
+
+
+def adjoint_ratio(torch, lbm, name, make_sim, nsteps, K, loss):
+    """(time of lbm_backward over nsteps, checkpoint restores and recompute
+    included) / (time of lbm_step(nsteps) without a tape)."""
+    sim = make_sim()
+    sim.use_current_stream()
+    sim.init_equilibrium()
+    sim.step(2)
+    with Timer(torch) as F:
+        sim.step(nsteps)
+    sim.init_equilibrium()
+    sim.tape_begin(K, nsteps)
+    with Timer(torch) as R:
+        sim.step(nsteps)
+    sim.tape_end()
+    rho, u = sim.moments(dtype=torch.float32)
+    g_rho, g_u = loss(rho, u)
+    with Timer(torch) as B:
+        sim.backward(g_rho, g_u, want_s=getattr(sim, "_has_s", False))
+    sim.tape_free()
+    del sim
+    return {"workload": name, "steps": nsteps, "K": K, "forward_ms": round(F.ms, 3),
+            "forward_taped_ms": round(R.ms, 3), "backward_ms": round(B.ms, 3),
+            "ratio": round(B.ms / F.ms, 3)}
+
+
+def adjoint_figures(torch, lbm):
+    from paper_2311_16080_amd import inputs
+    res = []
+
+    def c4():
+        sim = lbm.Sim("D2Q9", (512, 256), 0.6, faces=[(lbm.ZOUHE_VELOCITY, (0.04, 0.0)),
+                                                     (lbm.EQ_OUTFLOW, (0.0, 0.0), 1.0), (lbm.WALL,), (lbm.WALL,),
+                                                     (lbm.PERIODIC,), (lbm.PERIODIC,)], storage="f32")
+        sim.set_solid_fraction(inputs.smooth_solid_fraction(512, 256, seed=4))
+        sim._has_s = True
+        return sim
+
+    def l2(rho, u):
+        tgt = torch.zeros_like(u)
+        return None, 2.0 * (u - tgt)
+
+    res.append(adjoint_ratio(torch, lbm, "D2Q9 FP32 512x256 channel, partial bounce-back s field, u-mismatch loss",
+                             c4, 500, 50, l2))
+
+    def cav3():
+        return lbm.Sim("D3Q19", (256, 256, 256), 0.55, faces=cavity_faces(lbm), storage="f32")
+
+    res.append(adjoint_ratio(torch, lbm, "D3Q19 FP32 256^3 cavity, mean kinetic energy loss", cav3, 100, 10,
+                             lambda r, u: _ke_seed(torch, r, u, 256.0 ** 3)))
+
+    def cav2():
+        return lbm.Sim("D2Q9", (8192, 8192), 0.6, faces=[(lbm.WALL,), (lbm.WALL,), (lbm.WALL,),
+                                                         (lbm.WALL, (0.05, 0.0)), (lbm.PERIODIC,), (lbm.PERIODIC,)],
+                       storage="f32")
+
+    res.append(adjoint_ratio(torch, lbm, "D2Q9 FP32 8192^2 cavity, mean kinetic energy loss", cav2, 50, 10,
+                             lambda r, u: _ke_seed(torch, r, u, 8192.0 ** 2)))
+    return res
+
+
+def batch_figures(torch, lbm, steps=2000):
+    """256 D2Q9 cavities (side lengths 64..256, tau in [0.52, 1), lid 0.05..0.1)
+    advanced by one captured graph; against one launch per domain and the
+    plain single-domain FP32 rate; then forward + adjoint of the summed
+    per-domain mean kinetic energy."""
+    from paper_2311_16080_amd import inputs
+    L, tau, U = inputs.batch_cavities(256, seed=5)
+    shapes = [(int(l), int(l)) for l in L]
+    faces = [[(lbm.WALL,), (lbm.WALL,), (lbm.WALL,), (lbm.WALL, (float(U[d]), 0.0)), (lbm.PERIODIC,),
+              (lbm.PERIODIC,)] for d in range(256)]
+    out = {"domains": 256, "cells": int(sum(l * l for l in L)), "steps": steps}
+    bs = lbm.BatchSim("D2Q9", shapes, tau, faces, storage="f32")
+    bs.use_current_stream()
+    bs.init_equilibrium()
+    bs.step(2)                       # runs the autotuner on a copy of the state
+    bs.capture_graph(steps)
+    bs.graph_launch()                # warm-up replay
+    with Timer(torch) as G:
+        bs.graph_launch()
+    N = out["cells"]
+    tile, pers = bs.config()
+    out["graph_MLUPS"] = round(N * steps / (G.ms / 1e3) / 1e6, 1)
+    out["graph_ms"] = round(G.ms, 2)
+    out["tile"] = tile
+    out["persistent"] = pers
+    out["effective_GBps"] = round(out["graph_MLUPS"] * 1e6 * 72 / 1e9, 1)
+    # unstable domains: non-finite or |u| above 0.3 anywhere
+    rho, u = bs.moments(dtype=torch.float32)
+    speed = torch.sqrt((u * u).sum(0))
+    bad = []
+    for d in range(256):
+        a, b = int(bs.offsets[d]), int(bs.offsets[d + 1])
+        m = float(speed[a:b].max())
+        if not np.isfinite(m) or m > 0.3:
+            bad.append(d)
+    out["unstable_domains"] = bad
+    # one launch per domain (separate contexts), fewer steps
+    sims = []
+    for d in range(256):
+        s = lbm.Sim("D2Q9", shapes[d], float(tau[d]), faces=faces[d], storage="f32")
+        s.use_current_stream()
+        s.init_equilibrium()
+        sims.append(s)
+    k = 50
+    for s in sims:
+        s.step(2)
+    with Timer(torch) as P:
+        for s in sims:
+            s.step(k)
+    out["per_domain_launch_MLUPS"] = round(N * k / (P.ms / 1e3) / 1e6, 1)
+    del sims
+    big = lbm.Sim("D2Q9", (4096, 4096), 0.6, faces=faces[0], storage="f32")
+    big.use_current_stream()
+    big.init_equilibrium()
+    big.step(10)
+    with Timer(torch) as S:
+        big.step(100)
+    out["single_domain_4096sq_MLUPS"] = round(4096 ** 2 * 100 / (S.ms / 1e3) / 1e6, 1)
+    del big
+    # forward + adjoint of sum_d mean KE_d over the same steps
+    K = 50
+    bs.init_equilibrium()
+    bs.tape_begin(K, steps)
+    with Timer(torch) as R:
+        bs.step(steps)
+    bs.tape_end()
+    rho, u = bs.moments(dtype=torch.float32)
+    ncell = torch.empty_like(rho)
+    for d in range(256):
+        ncell[int(bs.offsets[d]):int(bs.offsets[d + 1])] = float(L[d]) ** 2
+    g_rho, g_u = _ke_seed(torch, rho, u, ncell)
+    with Timer(torch) as B:
+        dtau, duw = bs.backward(g_rho, g_u)
+    out["adjoint"] = {"K": K, "forward_taped_ms": round(R.ms, 2), "backward_ms": round(B.ms, 2),
+                      "ratio_vs_graph_forward": round(B.ms / G.ms, 3),
+                      "dE_dtau_first4": [float(v) for v in dtau[:4]],
+                      "dE_dU_first4": [float(duw[d, 3, 0]) for d in range(4)]}
+    return out
+
+
+def channel_spheres_figures(torch, lbm, steps=50):
+    """D3Q27 1024x512x512 FP32 channel with random spheres (5% solid), Zou-He
+    inlet u = 0.04, equilibrium outflow, bounce-back walls, in place."""
+    from paper_2311_16080_amd import inputs
+    shape = (1024, 512, 512)
+    t0 = time.perf_counter()
+    solid = inputs.sphere_obstacles(*shape, seed=3)
+    gen_s = time.perf_counter() - t0
+    faces = [(lbm.ZOUHE_VELOCITY, (0.04, 0.0, 0.0)), (lbm.EQ_OUTFLOW, (0.0, 0.0, 0.0), 1.0), (lbm.WALL,),
+             (lbm.WALL,), (lbm.WALL,), (lbm.WALL,)]
+    sim = lbm.Sim("D3Q27", shape, 0.6, faces=faces, storage="f32", pattern="inplace")
+    sim.use_current_stream()
+    sim.set_solid(solid)
+    sim.init_equilibrium()
+    sim.step(10)
+    with Timer(torch) as T:
+        sim.step(steps)
+    N = int(np.prod(shape))
+    mlups = N * steps / (T.ms / 1e3) / 1e6
+    gbps = mlups * 1e6 * 216 / 1e9
+    res = {"cells": N, "solid_fraction": round(float(solid.mean()), 4), "steps": steps,
+           "MLUPS": round(mlups, 1), "GBps_at_216B": round(gbps, 1), "frac": round(gbps / PEAK_HBM_GBPS, 4),
+           "sphere_generation_s": round(gen_s, 1)}
+    del sim
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,7 +295,9 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f64"])
     ap.add_argument("--lattice", default="D3Q19", choices=["D2Q9", "D3Q19", "D3Q27"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extras", action="store_true", help="skip the copy probe and extra figures")
+    ap.add_argument("--no-copy", action="store_true", help="skip the HBM copy probe")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FP16/BF16, adjoint, batched and D3Q27 channel figures")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -147,7 +358,7 @@ def main():
                      "bytes_per_lattice_update": 2 * Q * esize},
     }
 
-    if not args.no_extras:
+    if not args.no_copy:
         # achievable HBM copy bandwidth (bandwidth probe), same stream
         nb = 2 * 1024 ** 3
         src = torch.empty(nb // 4, dtype=torch.float32, device="cuda")
@@ -166,6 +377,21 @@ def main():
         out["frac_of_copy"] = round(achieved / copy_gbps, 4)
         del src, dst
         torch.cuda.empty_cache()
+
+    if not args.no_extras:
+        del sim
+        extras = {}
+        for key, fn in (("storage_f16_bf16", lambda: storage_variants(torch, lbm, n, tau, args.steps)),
+                        ("adjoint_forward_ratio", lambda: adjoint_figures(torch, lbm)),
+                        ("batched_cavities", lambda: batch_figures(torch, lbm)),
+                        ("d3q27_channel_spheres", lambda: channel_spheres_figures(torch, lbm))):
+            t0 = time.perf_counter()
+            try:
+                extras[key] = fn()
+            except Exception as exc:  # reported, never hides the headline figure
+                extras[key] = {"error": f"{type(exc).__name__}: {exc}"}
+            print(f"[bench] {key} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        out["extras"] = extras
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n if lat == "D3Q19" else 128, tau)

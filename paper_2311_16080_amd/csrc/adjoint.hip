@@ -17,8 +17,11 @@
 //   Zou-He  : the unknowns are affine in the knowns at the same cell, so their
 //             adjoints are folded into the knowns' (closure transpose);
 //   walls   : dL/du_w += a_i(x) 6 w_i rho0 c_i for populations bounced off a moving wall.
-// Per-block FP64 partial sums of dL/dtau and dL/du_w are added into the
-// block's own slot (deterministic).
+// The step kernel adds the block's FP64 sum of sum_i lambda_i (f_i - feq_i)
+// into the block's own accumulator row (times 1/tau^2 on the host); a second,
+// small kernel over the cells of the moving-wall faces adds the wall-velocity
+// terms into one row of 3 per face tile.  Both are summed on the host in a
+// fixed order (deterministic).
 #include "adjoint.hpp"
 
 namespace lbm {
@@ -102,19 +105,175 @@ __device__ __forceinline__ void zouhe_transpose(CT *a, const Params<CT> &p, int 
     unroll<L::Q>([&](auto I) { a[I] = (cn[I] == 1) ? (CT)0 : add[I]; });
 }
 
-// Adjoint step at time t.  F: natural state f(t) (storage type ST); An: a(t+1)
-// (CT planes); Ao: a(t).  ds: per-cell dL/ds accumulator (null without s).
-// acc: per-block accumulator rows of kAdjSlots doubles (dL/dtau, dL/du_w[6][3]).
-template <class L, class ST>
-__device__ __forceinline__ void adjoint_cell(const Params<typename Store<ST>::CT> &p, const ST *__restrict__ F,
-                                             const typename Store<ST>::CT *__restrict__ An,
-                                             typename Store<ST>::CT *__restrict__ Ao,
-                                             typename Store<ST>::CT *__restrict__ ds, int X, int Y, int Z,
-                                             int pending, double inv_tau2, double (&part)[kAdjSlots]) {
+// Adjoint step at time t for one fluid cell.  F: natural state f(t) (storage
+// type ST); An: a(t+1) (CT planes); Ao: a(t).  ds: per-cell dL/ds accumulator
+// (HAS_S).  Returns sum_i lambda_i (f_i - feq_i), the cell's dL/dtau * tau^2.
+template <class L, class ST, bool HAS_S>
+__device__ __forceinline__ typename Store<ST>::CT adjoint_cell(const Params<typename Store<ST>::CT> &p,
+                                                               const ST *__restrict__ F,
+                                                               const typename Store<ST>::CT *__restrict__ An,
+                                                               typename Store<ST>::CT *__restrict__ Ao,
+                                                               typename Store<ST>::CT *__restrict__ ds, int X, int Y,
+                                                               int Z, int pending) {
     using CT = typename Store<ST>::CT;
     constexpr int Q = L::Q;
     const int64_t P = p.plane;
-    {
+    const int64_t cell = ((int64_t)X * p.nY + Y) * p.nZ + Z;
+    uint32_t nbm = 0;
+    if (p.flags) {
+        const uint8_t fl = p.flags[cell];
+        if (fl & 1) {
+            unroll<Q>([&](auto I) { Ao[(int64_t)I * P + cell] = (CT)0; });
+            return (CT)0;
+        }
+        if (fl & 2) nbm = p.nbm[cell];
+    }
+    const uint32_t e = edge_bits(p, X, Y, Z);
+    const uint32_t irr = irregular_mask<L>(e, nbm);
+    CT h[Q];
+    unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(F, P, cell); });
+    const int zf = zh_face_of(p, e);
+    if (zf >= 0 && pending) zouhe<L>(h, p, zf);
+    CT drho = 0, jx = 0, jy = 0, jz = 0;
+    unroll<Q>([&](auto I) {
+        drho += h[I];
+        if constexpr (L::c[I][0] != 0) jx += (CT)L::c[I][0] * h[I];
+        if constexpr (L::c[I][1] != 0) jy += (CT)L::c[I][1] * h[I];
+        if constexpr (L::c[I][2] != 0) jz += (CT)L::c[I][2] * h[I];
+    });
+    const CT rho = p.rho0 + drho;
+    const CT inv = (CT)1 / rho;
+    const CT ux = jx * inv, uy = jy * inv, uz = jz * inv;
+    const CT uu = ux * ux + uy * uy + uz * uz;
+    const CT usq15 = (CT)1.5 * uu;
+    const CT om = p.omega;
+
+    // b_k: adjoint of the post-collision value f°_k(x): a_k(x + c_k) for a
+    // fluid neighbour, a_opp(k)(x) off a wall or solid, 0 out of an open face
+    CT b[Q];
+    unroll<Q>([&](auto K) {
+        constexpr int O = opp<L>(K);
+        if (!((irr >> O) & 1u)) {
+            const int64_t dst = cell + ((int64_t)L::c[K][0] * p.sX + (int64_t)L::c[K][1] * p.sY + L::c[K][2]);
+            b[K] = An[(int64_t)K * P + dst];
+        } else {
+            const Nb nb = classify_src<L>(p, X, Y, Z, O, nbm);  // the cell x + c_k
+            const int64_t idx = (nb.kind == NB_FLUID) ? (int64_t)K * P + nb.cell : (int64_t)O * P + cell;
+            const CT v = An[idx];
+            b[K] = (nb.kind == NB_FLUID || nb.kind == NB_WALL) ? v : (CT)0;
+        }
+    });
+    // adjoint of u(x, t) through the equilibrium fills of incoming populations
+    CT ex = 0, ey = 0, ez = 0;
+    if (irr) {
+        const bool perim = (e & p.wallmask) != 0;
+        unroll<Q>([&](auto K) {
+            if ((irr >> K) & 1u) {
+                const Nb ns = classify_src<L>(p, X, Y, Z, K, nbm);
+                if (ns.kind == NB_OUT || (ns.kind == NB_ZH && perim && p.ft->type[ns.face] == F_ZH_PRES)) {
+                    const CT aK = An[(int64_t)K * P + cell];
+                    const CT rf = p.ft->rho[ns.face];
+                    const CT cu = (CT)L::c[K][0] * ux + (CT)L::c[K][1] * uy + (CT)L::c[K][2] * uz;
+                    const CT g = aK * (CT)weight<L>(K) * rf;
+                    ex += g * ((CT)3 * (CT)L::c[K][0] + (CT)9 * cu * (CT)L::c[K][0] - (CT)3 * ux);
+                    ey += g * ((CT)3 * (CT)L::c[K][1] + (CT)9 * cu * (CT)L::c[K][1] - (CT)3 * uy);
+                    ez += g * ((CT)3 * (CT)L::c[K][2] + (CT)9 * cu * (CT)L::c[K][2] - (CT)3 * uz);
+                }
+            }
+        });
+    }
+
+    CT s = 0;
+    if constexpr (HAS_S) s = (CT)p.s[cell];
+    // lambda = (1 - s) b (partial bounce-back), dL/ds, dL/dtau * tau^2, A, V
+    CT gs = 0, gt = 0, Aa = 0, Vx = 0, Vy = 0, Vz = 0, Sw = 0;
+    unroll<Q>([&](auto I) {
+        constexpr int O = opp<L>(I);
+        const CT lam = HAS_S ? ((CT)1 - s) * b[I] : b[I];
+        const CT neq = h[I] - heq<L, I>(drho, rho, ux, uy, uz, usq15);
+        if constexpr (HAS_S) gs += b[I] * (h[O] - (h[I] - om * neq));
+        gt += lam * neq;
+        const CT cu = (CT)L::c[I][0] * ux + (CT)L::c[I][1] * uy + (CT)L::c[I][2] * uz;
+        const CT wl = (CT)weight<L>(I) * lam;
+        Aa += wl * ((CT)1 - (CT)4.5 * cu * cu + (CT)1.5 * uu);
+        Sw += wl;
+        const CT t9 = (CT)3 + (CT)9 * cu;
+        if constexpr (L::c[I][0] != 0) Vx += wl * t9 * (CT)L::c[I][0];
+        if constexpr (L::c[I][1] != 0) Vy += wl * t9 * (CT)L::c[I][1];
+        if constexpr (L::c[I][2] != 0) Vz += wl * t9 * (CT)L::c[I][2];
+    });
+    if constexpr (HAS_S) {
+        if (ds) ds[cell] += gs;
+    }
+    Vx -= (CT)3 * ux * Sw;
+    Vy -= (CT)3 * uy * Sw;
+    Vz -= (CT)3 * uz * Sw;
+    const CT eu = ex * ux + ey * uy + ez * uz;
+    CT a[Q];
+    unroll<Q>([&](auto J) {
+        constexpr int O = opp<L>(J);
+        const CT lam = HAS_S ? ((CT)1 - s) * b[J] : b[J];
+        const CT cV = (CT)L::c[J][0] * Vx + (CT)L::c[J][1] * Vy + (CT)L::c[J][2] * Vz;
+        const CT ce = (CT)L::c[J][0] * ex + (CT)L::c[J][1] * ey + (CT)L::c[J][2] * ez;
+        CT v = ((CT)1 - om) * lam + om * (Aa + cV) + (ce - eu) * inv;
+        if constexpr (HAS_S) v += s * b[O];
+        a[J] = v;
+    });
+    if (zf >= 0 && pending) zouhe_transpose<L>(a, p, zf);
+    unroll<Q>([&](auto I) { Ao[(int64_t)I * P + cell] = a[I]; });
+    return gt;
+}
+
+// FP64 sum of v over the block, added to acc[row] (fixed order)
+__device__ __forceinline__ void block_add(double v, double *acc, int64_t row) {
+    __shared__ double red[kMaxBlock / 64];
+    const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = ((int)blockDim.x + 63) / 64;
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += red[w];
+        acc[row] += t;
+    }
+}
+
+template <class L, class ST, bool HAS_S>
+__global__ void __launch_bounds__(kMaxBlock) k_adjoint(const Params<typename Store<ST>::CT> p, const ST *__restrict__ F,
+                                                       const typename Store<ST>::CT *__restrict__ An,
+                                                       typename Store<ST>::CT *__restrict__ Ao,
+                                                       typename Store<ST>::CT *__restrict__ ds, double *__restrict__ acc) {
+    int X, Y, Z;
+    double g = 0.0;
+    if (adj_block_cell(p, X, Y, Z)) g = (double)adjoint_cell<L, ST, HAS_S>(p, F, An, Ao, ds, X, Y, Z, p.zh_pending);
+    block_add(g, acc, blockIdx.x);
+}
+
+// Wall-velocity gradient of one step: tile k covers `blockDim.x` cells of
+// moving-wall face wt.face[k] of domain wt.dom[k] (face-local index from
+// wt.start[k]); for each incoming population bounced off that face,
+// dL/du_w += a_K(x, t+1) 6 w_K rho0 c_K.  accw: 3 rows per tile (internal axes).
+template <class L, class CT, bool BATCH>
+__global__ void __launch_bounds__(kMaxBlock) k_adj_walls(const Params<CT> p1, const BatchDev b, const WallTiles wt,
+                                                         const CT *__restrict__ An, double *__restrict__ accw) {
+    constexpr int Q = L::Q;
+    __shared__ double red[3][kMaxBlock / 64];
+    const int tile = (int)blockIdx.x;
+    const int d = wt.dom[tile], f = wt.face[tile];
+    const Params<CT> &p = BATCH ? dom_params<CT>(b, d) : p1;
+    const CT *A = BATCH ? An + b.stoff[d] : An;
+    const int ax = f >> 1;
+    const int na = (ax == 0) ? p.nY : p.nX;
+    const int nb = (ax == 2) ? p.nY : p.nZ;
+    const int q = wt.start[tile] + (int)threadIdx.x;
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    if (q < na * nb) {
+        const int i = q / nb, j = q - (q / nb) * nb;
+        const int fixed = (f & 1) ? ((ax == 0) ? p.nX : ((ax == 1) ? p.nY : p.nZ)) - 1 : 0;
+        const int X = (ax == 0) ? fixed : i;
+        const int Y = (ax == 0) ? i : ((ax == 1) ? fixed : j);
+        const int Z = (ax == 2) ? fixed : j;
         const int64_t cell = ((int64_t)X * p.nY + Y) * p.nZ + Z;
         uint32_t nbm = 0;
         bool solid = false;
@@ -123,162 +282,39 @@ __device__ __forceinline__ void adjoint_cell(const Params<typename Store<ST>::CT
             solid = fl & 1;
             if (fl & 2) nbm = p.nbm[cell];
         }
-        if (solid) {
-            unroll<Q>([&](auto I) { Ao[(int64_t)I * P + cell] = (CT)0; });
-        } else {
-            const uint32_t e = edge_bits(p, X, Y, Z);
-            const uint32_t irr = irregular_mask<L>(e, nbm);
-            const bool perim = (e & p.wallmask) != 0;
-            CT h[Q];
-            unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(F, P, cell); });
-            const int zf = zh_face_of(p, e);
-            if (zf >= 0 && pending) zouhe<L>(h, p, zf);
-            // forward quantities
-            CT drho = 0, jx = 0, jy = 0, jz = 0;
-            unroll<Q>([&](auto I) {
-                drho += h[I];
-                if constexpr (L::c[I][0] != 0) jx += (CT)L::c[I][0] * h[I];
-                if constexpr (L::c[I][1] != 0) jy += (CT)L::c[I][1] * h[I];
-                if constexpr (L::c[I][2] != 0) jz += (CT)L::c[I][2] * h[I];
-            });
-            const CT rho = p.rho0 + drho;
-            const CT inv = (CT)1 / rho;
-            const CT ux = jx * inv, uy = jy * inv, uz = jz * inv;
-            const CT usq15 = (CT)1.5 * (ux * ux + uy * uy + uz * uz);
-            const CT om = p.omega;
-            CT neq[Q];  // f - feq
-            unroll<Q>([&](auto I) { neq[I] = h[I] - heq<L, I>(drho, rho, ux, uy, uz, usq15); });
-
-            // b_k: adjoint of the post-collision value f°_k(x)
-            CT b[Q];
-            CT ex = 0, ey = 0, ez = 0;  // adjoint of u(x, t) through equilibrium fills
+        if (!solid) {
+            const uint32_t irr = irregular_mask<L>(edge_bits(p, X, Y, Z), nbm);
             unroll<Q>([&](auto K) {
-                constexpr int O = opp<L>(K);
-                if (!((irr >> O) & 1u)) {
-                    const int64_t dst = cell + ((int64_t)L::c[K][0] * p.sX + (int64_t)L::c[K][1] * p.sY + L::c[K][2]);
-                    b[K] = An[(int64_t)K * P + dst];
-                } else {
-                    const Nb nb = classify_src<L>(p, X, Y, Z, O, nbm);  // the cell x + c_k
-                    if (nb.kind == NB_FLUID) b[K] = An[(int64_t)K * P + nb.cell];
-                    else if (nb.kind == NB_WALL) b[K] = An[(int64_t)O * P + cell];
-                    else b[K] = (CT)0;
-                }
-                // incoming population K at x from a non-fluid source: wall velocity /
-                // equilibrium-fill dependencies
                 if ((irr >> K) & 1u) {
                     const Nb ns = classify_src<L>(p, X, Y, Z, K, nbm);
-                    if (ns.kind != NB_FLUID) {
-                        const CT aK = An[(int64_t)K * P + cell];
-                        const FaceTab<CT> &FT = *p.ft;
-                        if (ns.kind == NB_WALL && ns.face >= 0) {
-                            const double g = (double)aK * 6.0 * weight<L>(K) * (double)p.rho0;
-                            unroll<3>([&](auto A3) {
-                                if constexpr (L::c[K][A3] != 0) {
-                                    const double v = g * (double)L::c[K][A3];
-                                    // slot 1 + face*3 + axis (internal axes)
-                                    for (int f = 0; f < 6; ++f)
-                                        if (ns.face == f) part[1 + f * 3 + A3] += v;
-                                }
-                            });
-                        } else if (ns.kind == NB_OUT ||
-                                   (ns.kind == NB_ZH && perim && FT.type[ns.face] == F_ZH_PRES)) {
-                            const CT rf = FT.rho[ns.face];
-                            const CT cu = (CT)L::c[K][0] * ux + (CT)L::c[K][1] * uy + (CT)L::c[K][2] * uz;
-                            const CT g = aK * (CT)weight<L>(K) * rf;
-                            ex += g * ((CT)3 * (CT)L::c[K][0] + (CT)9 * cu * (CT)L::c[K][0] - (CT)3 * ux);
-                            ey += g * ((CT)3 * (CT)L::c[K][1] + (CT)9 * cu * (CT)L::c[K][1] - (CT)3 * uy);
-                            ez += g * ((CT)3 * (CT)L::c[K][2] + (CT)9 * cu * (CT)L::c[K][2] - (CT)3 * uz);
-                        }
+                    if (ns.kind == NB_WALL && ns.face == f) {
+                        const double v = (double)A[(int64_t)K * p.plane + cell] * 6.0 * weight<L>(K) * (double)p.rho0;
+                        g0 += v * L::c[K][0];
+                        g1 += v * L::c[K][1];
+                        g2 += v * L::c[K][2];
                     }
                 }
             });
-
-            CT s = 0;
-            const bool has_s = p.s != nullptr;
-            if (has_s) s = (CT)p.s[cell];
-            CT lam[Q];
-            unroll<Q>([&](auto I) { lam[I] = has_s ? ((CT)1 - s) * b[I] : b[I]; });
-            if (has_s && ds) {
-                CT g = 0;
-                unroll<Q>([&](auto I) {
-                    constexpr int O = opp<L>(I);
-                    const CT fstar = h[I] - om * neq[I];
-                    g += b[I] * (h[O] - fstar);
-                });
-                ds[cell] += g;
-            }
-            // dL/dtau: d f*_i / d tau = (f_i - feq_i) / tau^2
-            {
-                CT g = 0;
-                unroll<Q>([&](auto I) { g += lam[I] * neq[I]; });
-                part[0] += (double)g * inv_tau2;
-            }
-            // A and V
-            CT Aa = 0, Vx = 0, Vy = 0, Vz = 0, Sw = 0;
-            const CT uu = ux * ux + uy * uy + uz * uz;
-            unroll<Q>([&](auto I) {
-                const CT cu = (CT)L::c[I][0] * ux + (CT)L::c[I][1] * uy + (CT)L::c[I][2] * uz;
-                const CT wl = (CT)weight<L>(I) * lam[I];
-                Aa += wl * ((CT)1 - (CT)4.5 * cu * cu + (CT)1.5 * uu);
-                Sw += wl;
-                const CT t9 = (CT)3 + (CT)9 * cu;
-                if constexpr (L::c[I][0] != 0) Vx += wl * t9 * (CT)L::c[I][0];
-                if constexpr (L::c[I][1] != 0) Vy += wl * t9 * (CT)L::c[I][1];
-                if constexpr (L::c[I][2] != 0) Vz += wl * t9 * (CT)L::c[I][2];
-            });
-            Vx -= (CT)3 * ux * Sw;
-            Vy -= (CT)3 * uy * Sw;
-            Vz -= (CT)3 * uz * Sw;
-            const CT eu = ex * ux + ey * uy + ez * uz;
-            CT a[Q];
-            unroll<Q>([&](auto J) {
-                constexpr int O = opp<L>(J);
-                const CT cV = (CT)L::c[J][0] * Vx + (CT)L::c[J][1] * Vy + (CT)L::c[J][2] * Vz;
-                const CT ce = (CT)L::c[J][0] * ex + (CT)L::c[J][1] * ey + (CT)L::c[J][2] * ez;
-                CT v = ((CT)1 - om) * lam[J] + om * (Aa + cV) + (ce - eu) * inv;
-                if (has_s) v += s * b[O];
-                a[J] = v;
-            });
-            if (zf >= 0 && pending) zouhe_transpose<L>(a, p, zf);
-            unroll<Q>([&](auto I) { Ao[(int64_t)I * P + cell] = a[I]; });
         }
     }
-}
-
-// block partial sums -> the block's own accumulator row
-__device__ __forceinline__ void adj_block_reduce(const double (&part)[kAdjSlots], double *acc, int64_t row) {
-    __shared__ double red[kAdjSlots][kMaxBlock / 64];
     const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < kAdjSlots; ++k) {
-        double v = part[k];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-        if (lane == 0) red[k][wv] = v;
+    for (int o = 32; o > 0; o >>= 1) {
+        g0 += __shfl_xor(g0, o);
+        g1 += __shfl_xor(g1, o);
+        g2 += __shfl_xor(g2, o);
+    }
+    if (lane == 0) {
+        red[0][wv] = g0;
+        red[1][wv] = g1;
+        red[2][wv] = g2;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 3) {
         const int nw = ((int)blockDim.x + 63) / 64;
-        for (int k = 0; k < kAdjSlots; ++k) {
-            double v = 0.0;
-            for (int w = 0; w < nw; ++w) v += red[k][w];
-            acc[row * kAdjSlots + k] += v;
-        }
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += red[threadIdx.x][w];
+        accw[(int64_t)tile * 3 + threadIdx.x] += t;
     }
-}
-
-template <class L, class ST>
-__global__ void __launch_bounds__(kMaxBlock) k_adjoint(const Params<typename Store<ST>::CT> p, const ST *__restrict__ F,
-                                                       const typename Store<ST>::CT *__restrict__ An,
-                                                       typename Store<ST>::CT *__restrict__ Ao,
-                                                       typename Store<ST>::CT *__restrict__ ds, double *__restrict__ acc,
-                                                       double inv_tau2) {
-    int X, Y, Z;
-    const bool inside = adj_block_cell(p, X, Y, Z);
-    double part[kAdjSlots];
-#pragma unroll
-    for (int k = 0; k < kAdjSlots; ++k) part[k] = 0.0;
-    if (inside) adjoint_cell<L, ST>(p, F, An, Ao, ds, X, Y, Z, p.zh_pending, inv_tau2, part);
-    adj_block_reduce(part, acc, blockIdx.x);
 }
 
 // a(n) = dL/df(n) from dL/drho, dL/du of the final moments (caller axes), with
@@ -382,22 +418,6 @@ __global__ void __launch_bounds__(kMaxBlock) k_materialize(const Params<typename
     materialize_cell<L, ST>(p, A, D, X, Y, Z);
 }
 
-// acc rows [0, rows) summed in a fixed order into out[kAdjSlots]
-__global__ void __launch_bounds__(256) k_adj_reduce(const double *__restrict__ acc, int64_t rows,
-                                                    double *__restrict__ out) {
-    __shared__ double red[256];
-    const int k = (int)blockIdx.x;  // slot
-    double v = 0.0;
-    for (int64_t r = threadIdx.x; r < rows; r += 256) v += acc[r * kAdjSlots + k];
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[k] = red[0];
-}
-
 template <class CT>
 __global__ void __launch_bounds__(256) k_to_float(const CT *__restrict__ src, float *__restrict__ dst, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -409,23 +429,20 @@ template <class L, class ST>
 __global__ void __launch_bounds__(kMaxBlock) k_adjoint_batch(const BatchDev b, const ST *__restrict__ F,
                                                              const typename Store<ST>::CT *__restrict__ An,
                                                              typename Store<ST>::CT *__restrict__ Ao,
-                                                             double *__restrict__ acc,
-                                                             const double *__restrict__ inv_tau2, int pending) {
+                                                             double *__restrict__ acc, int pending) {
     using CT = typename Store<ST>::CT;
     const int tile = (int)blockIdx.x;
     const int d = b.tile_dom[tile];
     const Params<CT> &p = dom_params<CT>(b, d);
     const int c = b.tile_start[tile] + (int)threadIdx.x;
-    double part[kAdjSlots];
-#pragma unroll
-    for (int k = 0; k < kAdjSlots; ++k) part[k] = 0.0;
+    double g = 0.0;
     if (c < p.nX * p.nY * p.nZ) {
         int X, Y, Z;
         split_cell(c, p.nY, p.nZ, X, Y, Z);
         const int64_t o = b.stoff[d];
-        adjoint_cell<L, ST>(p, F + o, An + o, Ao + o, nullptr, X, Y, Z, pending, inv_tau2[d], part);
+        g = (double)adjoint_cell<L, ST, false>(p, F + o, An + o, Ao + o, nullptr, X, Y, Z, pending);
     }
-    adj_block_reduce(part, acc, tile);
+    block_add(g, acc, tile);
 }
 
 template <class L, class ST, class IT>
@@ -459,105 +476,60 @@ __global__ void __launch_bounds__(kMaxBlock) k_materialize_batch(const BatchDev 
     materialize_cell<L, ST>(p, A + o, D + o, X, Y, Z);
 }
 
-// one workgroup per domain; rows summed by a fixed thread/row assignment and
-// a fixed tree, so the result is deterministic
-__global__ void __launch_bounds__(256) k_adj_reduce_batch(const double *__restrict__ acc,
-                                                          const int64_t *__restrict__ rbeg,
-                                                          const int64_t *__restrict__ rend, double *__restrict__ out) {
-    __shared__ double red[256];
-    const int d = (int)blockIdx.x;
-    const int64_t r0 = rbeg[d], r1 = rend[d];
-    for (int k = 0; k < kAdjSlots; ++k) {
-        double v = 0.0;
-        for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) v += acc[r * kAdjSlots + k];
-        red[threadIdx.x] = v;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[(int64_t)d * kAdjSlots + k] = red[0];
-        __syncthreads();
-    }
-}
-
-template <class L, class ST>
-static hipError_t adj_batch_dispatch(const BatchAdjLaunch &g) {
-    using CT = typename Store<ST>::CT;
-    const dim3 grid(g.grid), block(g.block);
-    switch (g.op) {
-        case ADJ_STEP:
-            hipLaunchKernelGGL((k_adjoint_batch<L, ST>), grid, block, 0, g.stream, g.b, static_cast<const ST *>(g.F),
-                               static_cast<const CT *>(g.An), static_cast<CT *>(g.Ao), g.acc, g.inv_tau2, g.pending);
-            break;
-        case ADJ_SEED:
-            if (g.in_f64)
-                hipLaunchKernelGGL((k_seed_batch<L, ST, double>), grid, block, 0, g.stream, g.b,
-                                   static_cast<const ST *>(g.F), static_cast<const double *>(g.grho),
-                                   static_cast<const double *>(g.gu), static_cast<CT *>(g.Ao), g.pending);
-            else
-                hipLaunchKernelGGL((k_seed_batch<L, ST, float>), grid, block, 0, g.stream, g.b,
-                                   static_cast<const ST *>(g.F), static_cast<const float *>(g.grho),
-                                   static_cast<const float *>(g.gu), static_cast<CT *>(g.Ao), g.pending);
-            break;
-        case ADJ_MATERIALIZE:
-            hipLaunchKernelGGL((k_materialize_batch<L, ST>), grid, block, 0, g.stream, g.b,
-                               static_cast<const ST *>(g.F), static_cast<ST *>(g.D));
-            break;
-        case ADJ_REDUCE:
-            hipLaunchKernelGGL(k_adj_reduce_batch, dim3(g.b.ndom), dim3(256), 0, g.stream, g.acc, g.rbeg, g.rend,
-                               g.out);
-            break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <class L>
-static hipError_t adj_batch_storage(const BatchAdjLaunch &g) {
-    switch (g.storage) {
-        case ST_F64: return adj_batch_dispatch<L, double>(g);
-        case ST_F32: return adj_batch_dispatch<L, float>(g);
-        case ST_F16: return adj_batch_dispatch<L, _Float16>(g);
-        case ST_BF16: return adj_batch_dispatch<L, bf16_t>(g);
-    }
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_adjoint_batch(const BatchAdjLaunch &g) {
-    switch (g.lattice) {
-        case LAT_D2Q9: return adj_batch_storage<D2Q9>(g);
-        case LAT_D3Q19: return adj_batch_storage<D3Q19>(g);
-        case LAT_D3Q27: return adj_batch_storage<D3Q27>(g);
-    }
-    return hipErrorInvalidValue;
-}
-
 // ---------------------------------------------------------------------------
 template <class L, class ST>
 static hipError_t adj_dispatch(const AdjLaunch &g) {
     using CT = typename Store<ST>::CT;
-    const Params<CT> &p = *static_cast<const Params<CT> *>(g.params);
+    const bool batch = g.batch != nullptr;
+    const Params<CT> p = batch ? Params<CT>{} : *static_cast<const Params<CT> *>(g.params);
+    const BatchDev bd = batch ? *g.batch : BatchDev{};
     const dim3 grid(g.grid), block(g.block);
     switch (g.op) {
         case ADJ_STEP:
-            hipLaunchKernelGGL((k_adjoint<L, ST>), grid, block, 0, g.stream, p, static_cast<const ST *>(g.F),
-                               static_cast<const CT *>(g.An), static_cast<CT *>(g.Ao), static_cast<CT *>(g.ds), g.acc,
-                               g.inv_tau2);
+            if (batch)
+                hipLaunchKernelGGL((k_adjoint_batch<L, ST>), grid, block, 0, g.stream, bd, static_cast<const ST *>(g.F),
+                                   static_cast<const CT *>(g.An), static_cast<CT *>(g.Ao), g.acc, g.pending);
+            else if (g.ds)
+                hipLaunchKernelGGL((k_adjoint<L, ST, true>), grid, block, 0, g.stream, p, static_cast<const ST *>(g.F),
+                                   static_cast<const CT *>(g.An), static_cast<CT *>(g.Ao), static_cast<CT *>(g.ds),
+                                   g.acc);
+            else
+                hipLaunchKernelGGL((k_adjoint<L, ST, false>), grid, block, 0, g.stream, p, static_cast<const ST *>(g.F),
+                                   static_cast<const CT *>(g.An), static_cast<CT *>(g.Ao), nullptr, g.acc);
+            break;
+        case ADJ_WALLS:
+            if (g.walls.n == 0) break;
+            if (batch)
+                hipLaunchKernelGGL((k_adj_walls<L, CT, true>), dim3(g.walls.n), dim3(g.walls.block), 0, g.stream, p,
+                                   bd, g.walls, static_cast<const CT *>(g.An), g.accw);
+            else
+                hipLaunchKernelGGL((k_adj_walls<L, CT, false>), dim3(g.walls.n), dim3(g.walls.block), 0, g.stream, p,
+                                   bd, g.walls, static_cast<const CT *>(g.An), g.accw);
             break;
         case ADJ_SEED:
-            if (g.in_f64)
-                hipLaunchKernelGGL((k_seed<L, ST, double>), grid, block, 0, g.stream, p, static_cast<const ST *>(g.F),
-                                   static_cast<const double *>(g.grho), static_cast<const double *>(g.gu),
-                                   static_cast<CT *>(g.Ao), g.N);
-            else
-                hipLaunchKernelGGL((k_seed<L, ST, float>), grid, block, 0, g.stream, p, static_cast<const ST *>(g.F),
-                                   static_cast<const float *>(g.grho), static_cast<const float *>(g.gu),
-                                   static_cast<CT *>(g.Ao), g.N);
+#define LBM_SEED(IT)                                                                                                \
+    if (batch)                                                                                                      \
+        hipLaunchKernelGGL((k_seed_batch<L, ST, IT>), grid, block, 0, g.stream, bd, static_cast<const ST *>(g.F),  \
+                           static_cast<const IT *>(g.grho), static_cast<const IT *>(g.gu), static_cast<CT *>(g.Ao), \
+                           g.pending);                                                                              \
+    else                                                                                                            \
+        hipLaunchKernelGGL((k_seed<L, ST, IT>), grid, block, 0, g.stream, p, static_cast<const ST *>(g.F),          \
+                           static_cast<const IT *>(g.grho), static_cast<const IT *>(g.gu), static_cast<CT *>(g.Ao), \
+                           g.N);
+            if (g.in_f64) {
+                LBM_SEED(double)
+            } else {
+                LBM_SEED(float)
+            }
+#undef LBM_SEED
             break;
         case ADJ_MATERIALIZE:
-            hipLaunchKernelGGL((k_materialize<L, ST>), grid, block, 0, g.stream, p, static_cast<const ST *>(g.F),
-                               static_cast<ST *>(g.D));
+            if (batch)
+                hipLaunchKernelGGL((k_materialize_batch<L, ST>), grid, block, 0, g.stream, bd,
+                                   static_cast<const ST *>(g.F), static_cast<ST *>(g.D));
+            else
+                hipLaunchKernelGGL((k_materialize<L, ST>), grid, block, 0, g.stream, p, static_cast<const ST *>(g.F),
+                                   static_cast<ST *>(g.D));
             break;
         case ADJ_DS_OUT: {
             const unsigned nb = (unsigned)((g.N + 255) / 256);
@@ -588,11 +560,6 @@ hipError_t launch_adjoint(const AdjLaunch &g) {
         case LAT_D3Q27: return adj_storage<D3Q27>(g);
     }
     return hipErrorInvalidValue;
-}
-
-hipError_t launch_adj_reduce(const double *acc, int64_t rows, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_reduce, dim3(kAdjSlots), dim3(256), 0, s, acc, rows, out);
-    return hipGetLastError();
 }
 
 }  // namespace lbm

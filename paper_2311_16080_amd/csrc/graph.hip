@@ -16,11 +16,12 @@ void lbm::drop_graph(lbm_ctx *c) {
     c->graph_steps = 0;
 }
 
+static int capture_steps(lbm_ctx *c, int n);
+
 extern "C" int lbm_capture_graph(lbm_ctx *c, int n) {
     if (!c) return fail(LBM_EINVAL, "null context");
     if (n < 1) return fail(LBM_EINVAL, "n_steps must be >= 1");
     if (!c->A) return fail(LBM_ESTATE, "state not initialised");
-    if (!c->stream) return fail(LBM_EINVAL, "graph capture needs a non-null stream (lbm_set_stream)");
     if (c->tape_recording) return fail(LBM_ESTATE, "cannot capture while a tape is recording");
     (void)hipSetDevice(c->device);
     drop_graph(c);
@@ -28,6 +29,21 @@ extern "C" int lbm_capture_graph(lbm_ctx *c, int n) {
         int rc = batch_autotune(c);
         if (rc) return rc;
     }
+    // the legacy null stream cannot be captured: capture on a stream of our own
+    // (the graph keeps no reference to it) and replay on the context's stream
+    hipStream_t user = c->stream, own = nullptr;
+    if (!user) {
+        hipError_t se = hipStreamCreateWithFlags(&own, hipStreamNonBlocking);
+        if (se != hipSuccess) return hip_fail(se, "capture stream");
+        c->stream = own;
+    }
+    const int rc = capture_steps(c, n);
+    c->stream = user;
+    if (own) (void)hipStreamDestroy(own);
+    return rc;
+}
+
+static int capture_steps(lbm_ctx *c, int n) {
     const int64_t t0 = c->t;
     void *A0 = c->A, *B0 = c->B;
     hipGraph_t g = nullptr;
@@ -90,7 +106,9 @@ extern "C" int lbm_graph_launch(lbm_ctx *c) {
     if (c->tape_recording) return fail(LBM_ESTATE, "cannot replay a graph while a tape is recording");
     const bool same_parity = ((c->t ^ c->graph_t0) & 1) == 0;
     const bool same_buffers = c->A == c->graph_A;
-    const bool zh = c->pf.zhmask != 0;
+    bool zh = c->pf.zhmask != 0;
+    for (const Domain &D : c->dom)
+        for (const lbm_face &F : D.iface) zh = zh || F.type == LBM_ZOUHE_VELOCITY || F.type == LBM_ZOUHE_PRESSURE;
     if (!same_buffers || (c->opt.pattern == LBM_INPLACE && !same_parity) || (zh && ((c->t > 0) != (c->graph_t0 > 0))))
         return fail(LBM_ESTATE, "the state's step parity / buffers differ from those at capture");
     (void)hipSetDevice(c->device);

@@ -29,12 +29,17 @@ struct TapeState {
     void *ring = nullptr;     // K natural states
     void *abuf[2] = {nullptr, nullptr};
     void *ds = nullptr;       // N compute-type accumulators
-    double *acc = nullptr;    // grid x kAdjSlots
-    double *out = nullptr;    // kAdjSlots per domain
-    double *itau2 = nullptr;  // batch: 1 / tau_d^2 per domain
-    int64_t rows = 0;         // accumulator rows
+    double *acc = nullptr;    // one row per workgroup of the adjoint step
+    int64_t rows = 0;
+    // moving-wall face tiles (dL/du_w)
+    std::vector<int> wdom, wface, wstart;
+    int *wt = nullptr;        // device: dom[nwt], face[nwt], start[nwt]
+    int nwt = 0;
+    double *accw = nullptr;   // 3 rows per wall tile
 };
 }  // namespace lbm
+
+static constexpr int kWallBlock = 256;
 
 static size_t state_bytes_of(const lbm_ctx *c) { return (size_t)c->Q * (size_t)c->plane * storage_size(c->opt.storage); }
 static size_t compute_size(const lbm_ctx *c) { return c->opt.storage == LBM_F64 ? 8 : 4; }
@@ -48,8 +53,8 @@ void lbm::tape_release(lbm_ctx *c) {
         dev_free(T->abuf[1]);
         dev_free(T->ds);
         dev_free((void *&)T->acc);
-        dev_free((void *&)T->out);
-        dev_free((void *&)T->itau2);
+        dev_free((void *&)T->wt);
+        dev_free((void *&)T->accw);
         delete T;
     }
     c->tape = nullptr;
@@ -79,6 +84,31 @@ int lbm::tape_after_step(lbm_ctx *c) {
     return LBM_OK;
 }
 
+// tiles over the cells of every moving-wall face (internal axes) of every domain
+static void build_wall_tiles(const lbm_ctx *c, TapeState *T) {
+    T->wdom.clear();
+    T->wface.clear();
+    T->wstart.clear();
+    for (int d = 0; d < c->ndomains; ++d) {
+        const int nX = c->batch ? c->dom[d].nX : c->nX;
+        const int nY = c->batch ? c->dom[d].nY : c->nY;
+        const int nZ = c->batch ? c->dom[d].nZ : c->nZ;
+        const lbm_face *fc = c->batch ? c->dom[d].iface : c->iface;
+        for (int f = 0; f < 6; ++f) {
+            const lbm_face &F = fc[f];
+            if (F.type != LBM_WALL || (F.u[0] == 0.0 && F.u[1] == 0.0 && F.u[2] == 0.0)) continue;
+            const int ax = f >> 1;
+            const int64_t cells = (int64_t)(ax == 0 ? nY : nX) * (ax == 2 ? nY : nZ);
+            for (int64_t s = 0; s < cells; s += kWallBlock) {
+                T->wdom.push_back(d);
+                T->wface.push_back(f);
+                T->wstart.push_back((int)s);
+            }
+        }
+    }
+    T->nwt = (int)T->wdom.size();
+}
+
 extern "C" int lbm_tape_begin(lbm_ctx *c, int K, int max_steps) {
     if (!c) return fail(LBM_EINVAL, "null context");
     if (K < 1 || max_steps < 1) return fail(LBM_EINVAL, "K and max_steps must be >= 1");
@@ -95,22 +125,26 @@ extern "C" int lbm_tape_begin(lbm_ctx *c, int K, int max_steps) {
     T->abytes = (size_t)c->Q * (size_t)c->plane * compute_size(c);
     T->nck = max_steps / K + 1;
     T->ck_t.assign(T->nck, -1);
-    int rc = dev_alloc(&T->ck, (size_t)T->nck * T->sbytes, "tape checkpoints");
-    if (!rc) rc = dev_alloc(&T->ring, (size_t)K * T->sbytes, "tape recompute ring");
-    if (!rc) rc = dev_alloc(&T->abuf[0], T->abytes, "adjoint state");
-    if (!rc) rc = dev_alloc(&T->abuf[1], T->abytes, "adjoint state");
+    build_wall_tiles(c, T);
     // batch: one accumulator row per tile of the smallest tile size (any tuning fits)
     T->rows = c->batch ? c->bgrid : c->grid;
-    if (!rc && !c->batch) rc = dev_alloc(&T->ds, (size_t)c->N * compute_size(c), "dL/ds accumulator");
-    if (!rc) rc = dev_alloc((void **)&T->acc, (size_t)T->rows * kAdjSlots * sizeof(double), "adjoint sums");
-    if (!rc) rc = dev_alloc((void **)&T->out, (size_t)c->ndomains * kAdjSlots * sizeof(double), "adjoint sums");
-    if (!rc && c->batch) {
-        rc = dev_alloc((void **)&T->itau2, (size_t)c->ndomains * sizeof(double), "batch 1/tau^2");
+    int rc = dev_alloc(&T->ck, (size_t)T->nck * T->sbytes, "tape checkpoints");
+    // the first state of a segment is read from its checkpoint when that is in natural order
+    if (!rc && K > 1) rc = dev_alloc(&T->ring, (size_t)K * T->sbytes, "tape recompute ring");
+    if (!rc && K == 1) rc = dev_alloc(&T->ring, T->sbytes, "tape recompute ring");
+    if (!rc) rc = dev_alloc(&T->abuf[0], T->abytes, "adjoint state");
+    if (!rc) rc = dev_alloc(&T->abuf[1], T->abytes, "adjoint state");
+    if (!rc && c->s) rc = dev_alloc(&T->ds, (size_t)c->N * compute_size(c), "dL/ds accumulator");
+    if (!rc) rc = dev_alloc((void **)&T->acc, (size_t)T->rows * sizeof(double), "adjoint sums");
+    if (!rc && T->nwt) {
+        rc = dev_alloc((void **)&T->wt, (size_t)3 * T->nwt * sizeof(int), "wall tiles");
+        if (!rc) rc = dev_alloc((void **)&T->accw, (size_t)3 * T->nwt * sizeof(double), "wall sums");
         if (!rc) {
-            std::vector<double> v(c->ndomains);
-            for (int d = 0; d < c->ndomains; ++d) v[d] = 1.0 / (c->dom[d].tau * c->dom[d].tau);
-            if (hipMemcpy(T->itau2, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
-                rc = fail(LBM_EDEVICE, "batch 1/tau^2 upload");
+            std::vector<int> all(T->wdom);
+            all.insert(all.end(), T->wface.begin(), T->wface.end());
+            all.insert(all.end(), T->wstart.begin(), T->wstart.end());
+            if (hipMemcpy(T->wt, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+                rc = fail(LBM_EDEVICE, "wall tile upload");
         }
     }
     if (rc) {
@@ -145,58 +179,70 @@ extern "C" int lbm_tape_free(lbm_ctx *c) {
     return LBM_OK;
 }
 
-static AdjLaunch adj_launch(lbm_ctx *c, int op) {
-    AdjLaunch g;
-    std::memset(&g, 0, sizeof g);
-    g.op = op;
-    g.lattice = c->lattice;
-    g.storage = c->opt.storage;
-    g.params = (c->opt.storage == LBM_F64) ? (const void *)&c->pd : (const void *)&c->pf;
-    g.N = c->N;
-    g.grid = (unsigned)c->grid;
-    g.block = (unsigned)c->block;
-    g.stream = c->stream;
-    return g;
-}
+namespace {
+struct Backward {
+    lbm_ctx *c;
+    TapeState *T;
+    BatchLaunch bl{};
 
-static void set_pending(lbm_ctx *c, int64_t t) { c->pd.zh_pending = c->pf.zh_pending = (t > 0) ? 1 : 0; }
-
-static BatchAdjLaunch badj_launch(lbm_ctx *c, int op, int64_t t) {
-    const BatchLaunch bl = batch_launch_of(c);
-    BatchAdjLaunch g;
-    std::memset(&g, 0, sizeof g);
-    g.op = op;
-    g.lattice = bl.lattice;
-    g.storage = bl.storage;
-    g.b = bl.b;
-    g.grid = bl.grid;
-    g.block = bl.block;
-    g.stream = bl.stream;
-    g.pending = (t > 0) ? 1 : 0;
-    return g;
-}
-
-// natural-order copy of a stored state image taken at time t into dst
-static hipError_t restore_natural(lbm_ctx *c, const void *img, int64_t t, void *dst) {
-    TapeState *T = c->tape;
-    if (c->batch && (t & 1)) {
-        BatchAdjLaunch g = badj_launch(c, ADJ_MATERIALIZE, t);
-        g.F = img;
-        g.D = dst;
-        hipError_t e = hipMemsetAsync(dst, 0, T->sbytes, c->stream);  // padding slots stay defined
-        if (e != hipSuccess) return e;
-        return launch_adjoint_batch(g);
+    AdjLaunch launch(int op, int64_t t) {
+        AdjLaunch g;
+        std::memset(&g, 0, sizeof g);
+        g.op = op;
+        g.lattice = c->lattice;
+        g.storage = c->opt.storage;
+        g.params = (c->opt.storage == LBM_F64) ? (const void *)&c->pd : (const void *)&c->pf;
+        g.N = c->N;
+        g.grid = (unsigned)c->grid;
+        g.block = (unsigned)c->block;
+        g.stream = c->stream;
+        g.pending = (t > 0) ? 1 : 0;
+        if (c->batch) {
+            g.batch = &bl.b;
+            g.grid = bl.grid;
+            g.block = bl.block;
+        } else {
+            c->pd.zh_pending = c->pf.zh_pending = g.pending;
+        }
+        g.walls.dom = T->wt;
+        g.walls.face = T->wt ? T->wt + T->nwt : nullptr;
+        g.walls.start = T->wt ? T->wt + 2 * T->nwt : nullptr;
+        g.walls.n = T->nwt;
+        g.walls.block = kWallBlock;
+        return g;
     }
-    if (c->opt.pattern == LBM_INPLACE && (t & 1)) {
-        AdjLaunch g = adj_launch(c, ADJ_MATERIALIZE);
-        g.F = img;
-        g.D = dst;
-        hipError_t e = hipMemsetAsync(dst, 0, T->sbytes, c->stream);  // solid slots stay defined
-        if (e != hipSuccess) return e;
-        return launch_adjoint(g);
+
+    // a natural-order view of a state image taken at time t: the image itself
+    // when it is in natural order, else materialized into dst
+    hipError_t natural(const void *img, int64_t t, void *dst, const void **out) {
+        if (c->opt.pattern == LBM_INPLACE && (t & 1)) {
+            AdjLaunch g = launch(ADJ_MATERIALIZE, t);
+            g.F = img;
+            g.D = dst;
+            hipError_t e = hipMemsetAsync(dst, 0, T->sbytes, c->stream);  // slots of solid cells stay defined
+            if (e != hipSuccess) return e;
+            *out = dst;
+            return launch_adjoint(g);
+        }
+        *out = img;
+        return hipSuccess;
     }
-    return hipMemcpyAsync(dst, img, T->sbytes, hipMemcpyDeviceToDevice, c->stream);
-}
+
+    // natural-order push step src -> dst from time t
+    hipError_t push(const void *src, void *dst, int64_t t) {
+        if (c->batch) {
+            BatchLaunch g = bl;
+            g.A = const_cast<void *>(src);
+            return batch_launch_push(g, dst, (t > 0) ? 1 : 0);
+        }
+        c->pd.zh_pending = c->pf.zh_pending = (t > 0) ? 1 : 0;
+        Launch g = make_launch(c);
+        g.A = const_cast<void *>(src);
+        g.B = dst;
+        return launch_step(g, 2, c->s != nullptr);
+    }
+};
+}  // namespace
 
 extern "C" int lbm_backward(lbm_ctx *c, const void *dL_drho, const void *dL_du, int dtype, float *dL_ds,
                             double *dL_dtau, double *dL_duw) {
@@ -209,88 +255,63 @@ extern "C" int lbm_backward(lbm_ctx *c, const void *dL_drho, const void *dL_du, 
     if (c->moved_since_tape || c->t != T->t_end) return fail(LBM_ESTATE, "the state moved since the tape ended");
     (void)hipSetDevice(c->device);
     refresh_params(c);
+    Backward bw{c, T};
+    if (c->batch) bw.bl = batch_launch_of(c);
     const int64_t n = T->t_end - T->t_begin;
     char *ring = static_cast<char *>(T->ring);
     hipError_t e = hipSuccess;
     int cur = 0;
 
     // seed a(t_end) from the final state
-    e = restore_natural(c, c->A, c->t, ring);
-    if (e == hipSuccess && c->batch) {
-        BatchAdjLaunch g = badj_launch(c, ADJ_SEED, c->t);
-        g.F = ring;
-        g.grho = dL_drho;
-        g.gu = dL_du;
-        g.in_f64 = dtype == LBM_F64;
-        g.Ao = T->abuf[cur];
-        e = launch_adjoint_batch(g);
-    } else if (e == hipSuccess) {
-        set_pending(c, c->t);
-        AdjLaunch g = adj_launch(c, ADJ_SEED);
-        g.F = ring;
+    const void *Fn = nullptr;
+    e = bw.natural(c->A, c->t, ring, &Fn);
+    if (e == hipSuccess) {
+        AdjLaunch g = bw.launch(ADJ_SEED, c->t);
+        g.F = Fn;
         g.grho = dL_drho;
         g.gu = dL_du;
         g.in_f64 = dtype == LBM_F64;
         g.Ao = T->abuf[cur];
         e = launch_adjoint(g);
     }
-    if (e == hipSuccess) e = hipMemsetAsync(T->acc, 0, (size_t)T->rows * kAdjSlots * sizeof(double), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(T->acc, 0, (size_t)T->rows * sizeof(double), c->stream);
+    if (e == hipSuccess && T->nwt) e = hipMemsetAsync(T->accw, 0, (size_t)3 * T->nwt * sizeof(double), c->stream);
     if (e == hipSuccess && T->ds) e = hipMemsetAsync(T->ds, 0, (size_t)c->N * compute_size(c), c->stream);
 
     const int nseg = (int)((n + T->K - 1) / T->K);
-    void *A0 = c->A, *B0 = c->B;
-    const int64_t t_now = c->t;
+    std::vector<const void *> S((size_t)T->K);
     for (int seg = nseg - 1; seg >= 0 && e == hipSuccess; --seg) {
         const int64_t t0 = T->t_begin + (int64_t)seg * T->K;
         const int64_t t1 = (t0 + T->K < T->t_end) ? t0 + T->K : T->t_end;
-        e = restore_natural(c, static_cast<char *>(T->ck) + (size_t)seg * T->sbytes, t0, ring);
-        // recompute f(t0 + 1) .. f(t1 - 1) into the ring with the push step
+        // f(t0) .. f(t1 - 1) in natural order: the checkpoint, then push steps into the ring
+        e = bw.natural(static_cast<char *>(T->ck) + (size_t)seg * T->sbytes, t0, ring, &S[0]);
         for (int64_t k = 1; k < t1 - t0 && e == hipSuccess; ++k) {
-            if (c->batch) {
-                BatchLaunch g = batch_launch_of(c);
-                g.A = ring + (size_t)(k - 1) * T->sbytes;
-                e = batch_launch_push(g, ring + (size_t)k * T->sbytes, (t0 + k - 1 > 0) ? 1 : 0);
-                continue;
-            }
-            set_pending(c, t0 + k - 1);
-            Launch g = make_launch(c);
-            g.A = ring + (size_t)(k - 1) * T->sbytes;
-            g.B = ring + (size_t)k * T->sbytes;
-            e = launch_step(g, 2, c->s != nullptr);
+            void *dst = ring + (size_t)k * T->sbytes;
+            e = bw.push(S[k - 1], dst, t0 + k - 1);
+            S[k] = dst;
         }
         // adjoint steps backwards
         for (int64_t t = t1 - 1; t >= t0 && e == hipSuccess; --t) {
-            if (c->batch) {
-                BatchAdjLaunch g = badj_launch(c, ADJ_STEP, t);
-                g.F = ring + (size_t)(t - t0) * T->sbytes;
-                g.An = T->abuf[cur];
-                g.Ao = T->abuf[1 - cur];
-                g.acc = T->acc;
-                g.inv_tau2 = T->itau2;
-                e = launch_adjoint_batch(g);
-                cur = 1 - cur;
-                continue;
-            }
-            set_pending(c, t);
-            AdjLaunch g = adj_launch(c, ADJ_STEP);
-            g.F = ring + (size_t)(t - t0) * T->sbytes;
+            AdjLaunch w = bw.launch(ADJ_WALLS, t);
+            w.An = T->abuf[cur];
+            w.accw = T->accw;
+            e = launch_adjoint(w);
+            if (e != hipSuccess) break;
+            AdjLaunch g = bw.launch(ADJ_STEP, t);
+            g.F = S[t - t0];
             g.An = T->abuf[cur];
             g.Ao = T->abuf[1 - cur];
-            g.ds = c->s ? T->ds : nullptr;
+            g.ds = T->ds;
             g.acc = T->acc;
-            g.inv_tau2 = 1.0 / (c->tau * c->tau);
             e = launch_adjoint(g);
             cur = 1 - cur;
         }
     }
-    c->A = A0;
-    c->B = B0;
-    c->t = t_now;
-    set_pending(c, c->t);
+    refresh_params(c);
 
     if (e == hipSuccess && dL_ds) {
-        if (c->s) {
-            AdjLaunch g = adj_launch(c, ADJ_DS_OUT);
+        if (T->ds) {
+            AdjLaunch g = bw.launch(ADJ_DS_OUT, c->t);
             g.ds = T->ds;
             g.ds_out = dL_ds;
             e = launch_adjoint(g);
@@ -298,34 +319,38 @@ extern "C" int lbm_backward(lbm_ctx *c, const void *dL_drho, const void *dL_du, 
             e = hipMemsetAsync(dL_ds, 0, (size_t)c->N * sizeof(float), c->stream);
         }
     }
-    const int nd = c->ndomains;
-    std::vector<double> sums((size_t)nd * kAdjSlots);
-    if (e == hipSuccess) {
-        if (c->batch) {
-            BatchAdjLaunch g = badj_launch(c, ADJ_REDUCE, c->t);
-            g.acc = T->acc;
-            g.rbeg = c->rbeg;
-            g.rend = c->rend;
-            g.out = T->out;
-            e = launch_adjoint_batch(g);
-        } else {
-            e = launch_adj_reduce(T->acc, c->grid, T->out, c->stream);
-        }
-    }
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(sums.data(), T->out, sums.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    // FP64 row sums, added on the host in a fixed order
+    std::vector<double> acc((size_t)T->rows), accw((size_t)3 * T->nwt);
+    if (e == hipSuccess) e = hipMemcpyAsync(acc.data(), T->acc, acc.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && T->nwt)
+        e = hipMemcpyAsync(accw.data(), T->accw, accw.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "lbm_backward");
+    const int nd = c->ndomains;
+    std::vector<double> dtau((size_t)nd, 0.0), duw((size_t)nd * 18, 0.0);   // duw in internal faces / axes
+    if (c->batch) {
+        for (int d = 0; d < nd; ++d) {
+            double sum = 0.0;
+            for (int64_t r = c->dom[d].block0; r < c->dom[d].block0 + c->dom[d].nblocks; ++r) sum += acc[(size_t)r];
+            dtau[d] = sum / (c->dom[d].tau * c->dom[d].tau);
+        }
+    } else {
+        double sum = 0.0;
+        for (int64_t r = 0; r < c->grid; ++r) sum += acc[(size_t)r];
+        dtau[0] = sum / (c->tau * c->tau);
+    }
+    for (int k = 0; k < T->nwt; ++k)
+        for (int a = 0; a < 3; ++a) duw[(size_t)T->wdom[k] * 18 + 3 * T->wface[k] + a] += accw[(size_t)3 * k + a];
     for (int d = 0; d < nd; ++d) {
-        const double *S = sums.data() + (size_t)d * kAdjSlots;
-        if (dL_dtau) dL_dtau[d] = S[0];
+        if (dL_dtau) dL_dtau[d] = dtau[d];
         if (dL_duw) {
             // internal faces / axes -> caller faces / axes
             double *o = dL_duw + (size_t)d * 18;
+            const double *S18 = duw.data() + (size_t)d * 18;
             for (int k = 0; k < 18; ++k) o[k] = 0.0;
             for (int f = 0; f < 6; ++f)
                 for (int a = 0; a < 3; ++a) {
-                    const double v = S[1 + 3 * f + a];
+                    const double v = S18[3 * f + a];
                     if (c->D == 3) o[3 * f + a] = v;
                     else if (f >= 2 && a >= 1) o[3 * (f - 2) + (a - 1)] = v;
                 }
