@@ -41,6 +41,47 @@ def random_velocity(shape, dim: int, seed: int, amp: float = 0.03) -> np.ndarray
     return amp * rng.standard_normal(tuple(shape) + (dim,))
 
 
+def wave_field(shape, seed: int, lo=None, sub=None, amp: float = 0.03, rho_amp: float = 0.01,
+               modes: int = 4, xp=None, device=None):
+    """Seeded smooth (rho, u) over the box [lo, lo + sub) of a grid of `shape`:
+    a sum of `modes` plane waves per component with integer wave numbers in
+    [1, 3] per axis (periodic on the full grid), random phases and amplitudes.
+    Values depend only on the global cell coordinates, so any sub-box of the
+    full field is reproduced exactly.  xp = numpy (default) or torch
+    (device tensors for the full-size GPU runs).  Returns rho `sub` and u
+    `sub + (D,)` in FP64."""
+    rng = np.random.default_rng(seed)
+    D = len(shape)
+    lo = [0] * D if lo is None else list(lo)
+    sub = list(shape) if sub is None else list(sub)
+    xp = np if xp is None else xp
+    kw = {} if xp is np else {"device": device}
+    coords = []
+    for a in range(D):
+        c = xp.arange(lo[a], lo[a] + sub[a], dtype=xp.float64, **kw)
+        coords.append(c.reshape([-1 if b == a else 1 for b in range(D)]))
+
+    def waves(scale):
+        out = None
+        for _ in range(modes):
+            k = rng.integers(1, 4, size=D)
+            ph = rng.uniform(0.0, 2.0 * np.pi)
+            a = scale * rng.uniform(0.3, 1.0) / modes
+            arg = ph
+            for d in range(D):
+                arg = arg + (2.0 * np.pi * float(k[d]) / shape[d]) * coords[d]
+            term = a * xp.sin(arg)
+            out = term if out is None else out + term
+        return out
+
+    rho = 1.0 + waves(rho_amp)
+    u = [waves(amp) for _ in range(D)]
+    full = tuple(sub)
+    rho = rho + xp.zeros(full, dtype=xp.float64, **kw)
+    u = xp.stack([c + xp.zeros(full, dtype=xp.float64, **kw) for c in u], -1)
+    return rho, u
+
+
 def random_density(shape, seed: int, amp: float = 0.01, rho0: float = 1.0) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return rho0 + amp * rng.standard_normal(tuple(shape))

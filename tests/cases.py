@@ -122,3 +122,48 @@ def compare(case: Case, g, o):
     """(u rel-L2, max |rho - rho_oracle|) over fluid cells."""
     m = fluid_mask(case)
     return rel_l2(g[1], o[1], m), float(np.max(np.abs(g[0] - o[0])[m]))
+
+
+def cone_oracle(q: int, shape, tau: float, faces, center, nsteps: int, init_seed: int, solid=None,
+                margin: int = 2, amp: float = 0.03):
+    """Oracle (rho, u[3]) at one cell after `nsteps` steps of a run on the full
+    grid `shape`, computed on the cell's light cone only: a step moves
+    information one cell, so a sub-box reaching nsteps + margin cells around
+    the cell gives the full-grid result at its centre.  The sub-box keeps the
+    grid's own faces where it reaches them, wraps around periodic axes, and
+    has static walls on its cut faces.  The initial state is the seeded wave
+    field (inputs.wave_field, periodic on the full grid) on the sub-box."""
+    D = 2 if q == 9 else 3
+    r = nsteps + margin
+    lo, sub, of = [], [], []
+    for a in range(D):
+        c, n = int(center[a]), int(shape[a])
+        periodic = int(faces[2 * a][0]) == lbm.PERIODIC
+        if periodic and 2 * r + 1 < n:
+            lo.append(c - r)
+            sub.append(2 * r + 1)
+            of += [oracle.Face(oracle.WALL), oracle.Face(oracle.WALL)]
+            continue
+        l, h = max(c - r, 0), min(c + r + 1, n)
+        if periodic:
+            l, h = 0, n
+        lo.append(l)
+        sub.append(h - l)
+        of.append(_oface(faces[2 * a]) if l == 0 else oracle.Face(oracle.WALL))
+        of.append(_oface(faces[2 * a + 1]) if h == n else oracle.Face(oracle.WALL))
+    if q == 9:
+        of += [oracle.Face(), oracle.Face()]
+    osub = tuple(sub) + ((1,) if q == 9 else ())
+    sol = None
+    if solid is not None:
+        sol = np.asarray(solid)
+        for a in range(D):
+            sol = np.take(sol, np.arange(lo[a], lo[a] + sub[a]), axis=a, mode="wrap")
+        sol = np.ascontiguousarray(sol).reshape(osub).astype(np.uint8)
+    S = oracle.Sim(q=q, nx=osub[0], ny=osub[1], nz=osub[2], tau=tau, faces=of, solid=sol)
+    rho, u = inputs.wave_field(tuple(shape), init_seed, lo=lo, sub=sub, amp=amp)
+    f = S.equilibrium_state(rho=rho.reshape(osub), u=u.reshape(osub + (D,)))
+    S.run(f, nsteps)
+    R, U = S.moments(f)
+    idx = tuple(int(c) - l for c, l in zip(center, lo)) + ((0,) if q == 9 else ())
+    return float(R[idx]), U[idx].copy()

@@ -1,0 +1,133 @@
+"""Writes the full-size expected fields used by tests/test_gpu_fullsize.py.
+
+Every value comes from the FP64 CPU oracle (oracle/), run on the seeded
+synthetic inputs of paper_2311_16080_amd.inputs; nothing here touches the GPU
+library.  Run once (about 15-25 minutes on 8 cores):
+
+    python tests/golden/make_golden.py [cavity256] [channel_spheres]
+
+cavity256       -- D3Q19 lid-driven cavity 256^3, tau = 0.55, five static
+                   halfway bounce-back walls, lid (+z) moving at u = (0.05, 0, 0),
+                   start at rest (f = w_i), 1000 steps.  Stored: u on the plane
+                   y = 128 at every other x and z, the field sums.
+c4_adjoint      -- D2Q9 channel 512 x 256, tau = 0.6, Zou-He inlet u = (0.04, 0),
+                   equilibrium outflow, walls on +-y, solid fraction s from
+                   seed 4 (float32-rounded, as the library takes it), start at
+                   rest, 500 steps; loss sum |u(500) - u_T|^2 with u_T = u(500)
+                   of the same run with s from seed 40.  Stored: the oracle
+                   adjoint's dL/ds (float32), dL/dtau and L.
+c5_gradients    -- the four smallest of the 256 batched cavities (L = 64),
+                   2000 steps: mean kinetic energy E_d and the oracle adjoint's
+                   dE_d/dtau_d, dE_d/dU_d.
+channel_spheres -- D3Q27 channel 256 x 128 x 128, tau = 0.6, Zou-He velocity
+                   inlet u = (0.04, 0, 0) on -x, equilibrium outflow on +x,
+                   bounce-back walls on +-y and +-z, seeded spheres (radii 2..8,
+                   centres x in [16, 240), 5% solid), 300 steps.  Stored: u and
+                   rho on the plane z = 64 at every other x and y, the sums.
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_2311_16080_amd import inputs  # noqa: E402
+
+
+def cavity256(steps=1000, n=256):
+    faces = [oracle.Face(oracle.WALL) for _ in range(6)]
+    faces[5] = oracle.Face(oracle.WALL, (0.05, 0.0, 0.0))
+    S = oracle.Sim(q=19, nx=n, ny=n, nz=n, tau=0.55, faces=faces)
+    f = S.equilibrium_state()
+    t0 = time.time()
+    for k in range(0, steps, 100):
+        S.run(f, min(100, steps - k))
+        print(f"cavity256: {k + 100} steps, {time.time() - t0:.0f} s", flush=True)
+    rho, u = S.moments(f)
+    np.savez_compressed(os.path.join(HERE, "cavity256_d3q19_1000.npz"),
+                        u_y128=u[::2, n // 2, ::2, :], rho_y128=rho[::2, n // 2, ::2], sums=S.sums(f),
+                        steps=steps, stride=2)
+
+
+def channel_spheres(steps=300, shape=(256, 128, 128)):
+    solid = inputs.sphere_obstacles(*shape, seed=3, rmin=2.0, rmax=8.0, xlo=16, xhi=240, fraction=0.05)
+    faces = [oracle.Face(oracle.ZOUHE_VEL, (0.04, 0.0, 0.0)), oracle.Face(oracle.OUTFLOW, (0.0, 0.0, 0.0), 1.0),
+             oracle.Face(oracle.WALL), oracle.Face(oracle.WALL), oracle.Face(oracle.WALL), oracle.Face(oracle.WALL)]
+    S = oracle.Sim(q=27, nx=shape[0], ny=shape[1], nz=shape[2], tau=0.6, faces=faces, solid=solid)
+    f = S.equilibrium_state()
+    t0 = time.time()
+    for k in range(0, steps, 50):
+        S.run(f, min(50, steps - k))
+        print(f"channel_spheres: {k + 50} steps, {time.time() - t0:.0f} s", flush=True)
+    rho, u = S.moments(f)
+    z = shape[2] // 2
+    np.savez_compressed(os.path.join(HERE, "channel_spheres_d3q27_300.npz"),
+                        u_z64=u[::2, ::2, z, :], rho_z64=rho[::2, ::2, z], solid_z64=solid[::2, ::2, z],
+                        sums=S.sums(f), steps=steps, stride=2)
+
+
+def c4_channel(s_seed):
+    faces = [oracle.Face(oracle.ZOUHE_VEL, (0.04, 0.0, 0.0)), oracle.Face(oracle.OUTFLOW, (0.0, 0.0, 0.0), 1.0),
+             oracle.Face(oracle.WALL), oracle.Face(oracle.WALL), oracle.Face(), oracle.Face()]
+    sv = inputs.smooth_solid_fraction(512, 256, seed=s_seed).astype(np.float32).astype(np.float64)
+    return oracle.Sim(q=9, nx=512, ny=256, nz=1, tau=0.6, faces=faces, s=sv.reshape(512, 256, 1))
+
+
+def c4_target():
+    """u_T = u(500) of the seed-40 run, (512, 256, 2)."""
+    S = c4_channel(40)
+    f = S.equilibrium_state()
+    S.run(f, 500)
+    return S.moments(f)[1][:, :, 0, :2]
+
+
+def c4_adjoint():
+    uT = c4_target()
+    S = c4_channel(4)
+    states = S.trajectory(S.equilibrium_state(), 500)
+    _, u = S.moments(states[-1])
+    r = u[:, :, 0, :2] - uT
+    seed = S.seed_from_velocity_grad(states[-1], 2.0 * r[:, :, None, :])
+    t0 = time.time()
+    _, dlds, dtau, _ = S.adjoint(states, seed)
+    print(f"c4_adjoint: adjoint {time.time() - t0:.0f} s", flush=True)
+    np.savez_compressed(os.path.join(HERE, "c4_adjoint_d2q9_512x256.npz"), dlds=dlds[:, :, 0].astype(np.float32),
+                        dtau=dtau, loss=float(np.sum(r * r)), steps=500, K=50)
+
+
+C5_PICK = [16, 63, 225, 177]   # the four smallest domains of the seed-5 batch (L = 64)
+
+
+def c5_gradients(steps=2000):
+    L, tau, U = inputs.batch_cavities(256, seed=5)
+    E, dtau, dU = [], [], []
+    for d in C5_PICK:
+        faces = [oracle.Face(oracle.WALL), oracle.Face(oracle.WALL), oracle.Face(oracle.WALL),
+                 oracle.Face(oracle.WALL, (float(U[d]), 0.0, 0.0)), oracle.Face(), oracle.Face()]
+        S = oracle.Sim(q=9, nx=int(L[d]), ny=int(L[d]), nz=1, tau=float(tau[d]), faces=faces)
+        states = S.trajectory(S.equilibrium_state(), steps)
+        rho, u = S.moments(states[-1])
+        N = float(L[d]) ** 2
+        E.append(float(np.sum(0.5 * rho * np.sum(u * u, -1)) / N))
+        seed = S.seed_from_velocity_grad(states[-1], rho[..., None] * u[..., :2] / N,
+                                         0.5 * np.sum(u[..., :2] ** 2, -1) / N)
+        _, _, dt, duw = S.adjoint(states, seed)
+        dtau.append(dt)
+        dU.append(duw[3, 0])
+        print(f"c5_gradients: domain {d} done", flush=True)
+    np.savez_compressed(os.path.join(HERE, "c5_gradients_d2q9.npz"), domains=np.array(C5_PICK), E=np.array(E),
+                        dtau=np.array(dtau), dU=np.array(dU), steps=steps)
+
+
+if __name__ == "__main__":
+    which = sys.argv[1:] or ["cavity256", "channel_spheres", "c4_adjoint", "c5_gradients"]
+    oracle.build(force=False)
+    print(f"oracle threads: {oracle.num_threads()}", flush=True)
+    for w in which:
+        {"cavity256": cavity256, "channel_spheres": channel_spheres, "c4_adjoint": c4_adjoint,
+         "c5_gradients": c5_gradients}[w]()

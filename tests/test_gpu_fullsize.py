@@ -1,0 +1,368 @@
+"""Parity at the benchmark workloads' full sizes, in the launch configuration
+bench.py times (in-place streaming, default block shape):
+
+* Taylor-Green vortex, D2Q9 128^2 FP64, tau 0.8, 1000 steps: whole field vs
+  the oracle (<= 1e-12), kinetic-energy decay rate vs 2 nu k^2 (<= 1e-2).
+* D3Q19 cavity 256^3, 1000 steps: u on the plane y = 128 vs the oracle's
+  stored run (tests/golden/make_golden.py): FP32 <= 1e-5, FP16 <= 1e-3 rel-L2,
+  BF16 reported (gated at 2e-2).
+* D3Q27 channel with spheres: the reduced 256 x 128 x 128 run (300 steps) vs
+  the stored oracle plane (FP64 <= 1e-12, FP32 <= 1e-5); the full
+  1024 x 512 x 512 grid from a seeded wave field, sampled cells after 6 steps
+  vs the oracle on each cell's light cone.
+* D2Q9 512 x 256 partial-bounce-back channel, 500 steps, K = 50: GPU FP32 dL/ds
+  vs the FP64 oracle adjoint (<= 1e-4 rel-L2), GPU FP64 dL/ds vs central
+  differences of the FP64 forward at 16 cells from default_rng(41).
+* 256 batched D2Q9 cavities, 2000 steps: sampled domains bitwise equal to
+  their single-domain runs; per-domain mean-KE gradients vs central
+  differences (FP64) and vs the oracle adjoint on the smallest domains.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from cases import Case, cone_oracle, fluid_mask, gpu_run, oracle_run, rel_l2
+from paper_2311_16080_amd import inputs, lbm
+
+pytestmark = pytest.mark.gpu
+W, P, ZV, OUT = lbm.WALL, lbm.PERIODIC, lbm.ZOUHE_VELOCITY, lbm.EQ_OUTFLOW
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _announce(name):
+    print(f"\n[case] {name}", flush=True)
+    sys.stdout.flush()
+
+
+# ---- C1: Taylor-Green vortex ---------------------------------------------------------
+def test_tgv_128_fp64_1000_steps():
+    _announce("TGV 128^2 FP64 1000 steps")
+    import torch
+    case = Case(9, (128, 128), 0.8, steps=1000, init_u=inputs.taylor_green_velocity(128, 128, 0.01))
+    sim = lbm.Sim("D2Q9", case.shape, case.tau, faces=case.faces, storage="f64")
+    u0 = torch.tensor(np.moveaxis(case.init_u, -1, 0).copy(), device="cuda")
+    sim.init_equilibrium(None, u0)
+    ke = []
+    for k in range(10):
+        sim.step(100)
+        ke.append(sim.sums()[4])
+    rho, u = sim.moments(dtype=torch.float64)
+    o = oracle_run(case)
+    g = (rho.cpu().numpy().reshape(case.oshape),
+         np.stack([u[0].cpu().numpy(), u[1].cpu().numpy(), np.zeros(case.shape)], -1).reshape(case.oshape + (3,)))
+    m = fluid_mask(case)
+    eu = rel_l2(g[1], o[1], m)
+    er = float(np.max(np.abs(g[0] - o[0])))
+    print(f"[case] TGV: u rel-L2 {eu:.3e}, max |drho| {er:.3e}", flush=True)
+    assert eu <= 1e-12 and er <= 1e-13
+    # KE decay over t in [100, 1000] vs the Navier-Stokes rate 2 nu (kx^2 + ky^2)
+    t = np.arange(100, 1001, 100)
+    rate = -np.polyfit(t, np.log(ke), 1)[0]
+    nu = (0.8 - 0.5) / 3.0
+    exact = 2.0 * nu * 2.0 * (2.0 * np.pi / 128) ** 2
+    print(f"[case] TGV: KE decay rate {rate:.6e} vs {exact:.6e}", flush=True)
+    assert abs(rate - exact) <= 1e-2 * exact
+
+
+# ---- C2: 256^3 cavity, 1000 steps --------------------------------------------------------
+def _cavity_u_plane(storage):
+    import torch
+    n = 256
+    sim = lbm.Sim("D3Q19", (n, n, n), 0.55, faces=[(W,)] * 5 + [(W, (0.05, 0.0, 0.0))], storage=storage)
+    sim.init_equilibrium()
+    sim.step(1000)
+    rho, u = sim.moments(dtype=torch.float32)
+    plane = torch.stack([u[a, ::2, n // 2, ::2] for a in range(3)], -1).double().cpu().numpy()
+    sums = sim.sums()
+    del sim
+    return plane, sums
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f16", 1e-3), ("bf16", 2e-2)])
+def test_cavity256_1000_steps_vs_oracle(storage, tol):
+    path = os.path.join(GOLDEN, "cavity256_d3q19_1000.npz")
+    if not os.path.exists(path):
+        pytest.skip("run tests/golden/make_golden.py cavity256 first")
+    _announce(f"cavity 256^3 {storage} 1000 steps")
+    ref = np.load(path)
+    plane, sums = _cavity_u_plane(storage)
+    e = float(np.linalg.norm(plane - ref["u_y128"]) / np.linalg.norm(ref["u_y128"]))
+    print(f"[case] cavity256 {storage}: u rel-L2 on y = 128 {e:.3e}; KE {sums[4]:.6e} vs {ref['sums'][4]:.6e}",
+          flush=True)
+    assert e <= tol
+    assert abs(sums[0] - ref["sums"][0]) <= 1e-6 * ref["sums"][0]
+
+
+# ---- C3: channel with spheres ----------------------------------------------------------------
+def _channel_faces():
+    return [(ZV, (0.04, 0.0, 0.0)), (OUT, (0.0, 0.0, 0.0), 1.0), (W,), (W,), (W,), (W,)]
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_channel_spheres_reduced_300_steps_vs_oracle(storage, tol):
+    path = os.path.join(GOLDEN, "channel_spheres_d3q27_300.npz")
+    if not os.path.exists(path):
+        pytest.skip("run tests/golden/make_golden.py channel_spheres first")
+    _announce(f"channel spheres 256x128x128 {storage} 300 steps")
+    import torch
+    ref = np.load(path)
+    shape = (256, 128, 128)
+    solid = inputs.sphere_obstacles(*shape, seed=3, rmin=2.0, rmax=8.0, xlo=16, xhi=240, fraction=0.05)
+    assert np.array_equal(solid[::2, ::2, 64], ref["solid_z64"])
+    sim = lbm.Sim("D3Q27", shape, 0.6, faces=_channel_faces(), storage=storage)
+    sim.set_solid(solid)
+    sim.init_equilibrium()
+    sim.step(300)
+    rho, u = sim.moments(dtype=torch.float64)
+    plane = torch.stack([u[a, ::2, ::2, 64] for a in range(3)], -1).cpu().numpy()
+    m = ~ref["solid_z64"].astype(bool)
+    e = float(np.linalg.norm((plane - ref["u_z64"])[m]) / np.linalg.norm(ref["u_z64"][m]))
+    er = float(np.max(np.abs(rho[::2, ::2, 64].cpu().numpy() - ref["rho_z64"])[m]))
+    print(f"[case] channel {storage}: u rel-L2 {e:.3e}, max |drho| {er:.3e}", flush=True)
+    assert e <= tol and er <= tol
+
+
+def test_channel_spheres_full_size_light_cone_samples():
+    """1024 x 512 x 512 D3Q27 FP32, the benchmarked grid and launch: sampled
+    cells after 6 steps from a seeded wave field vs the oracle on their light
+    cones (inlet, outlet, walls, edges, cells next to spheres, random)."""
+    _announce("channel spheres 1024x512x512 f32 light-cone samples")
+    import torch
+    shape = (1024, 512, 512)
+    steps, seed, amp = 6, 31, 0.03
+    solid = inputs.sphere_obstacles(*shape, seed=3)
+    sim = lbm.Sim("D3Q27", shape, 0.6, faces=_channel_faces(), storage="f32", pattern="inplace")
+    sim.set_solid(solid)
+    rho0, u0 = inputs.wave_field(shape, seed, amp=amp, xp=torch, device="cuda")
+    sim.init_equilibrium(rho0, u0.permute(3, 0, 1, 2).contiguous())
+    del rho0, u0
+    torch.cuda.empty_cache()
+    sim.step(steps)
+    rho, u = sim.moments(dtype=torch.float32)
+    rng = np.random.default_rng(17)
+    cells = [(0, 0, 0), (0, 255, 300), (1, 511, 511), (1023, 0, 511), (1023, 200, 3), (500, 0, 0),
+             (700, 511, 250), (2, 3, 4)]
+    # fluid cells next to spheres: step in +x out of a few solid cells
+    for a, b, c in np.argwhere(solid[64:960:37, ::41, ::43] != 0)[:6]:
+        x, y, z = 64 + 37 * int(a), 41 * int(b), 43 * int(c)
+        while x < shape[0] - 1 and solid[x, y, z]:
+            x += 1
+        cells.append((x, y, z))
+    cells += [tuple(int(rng.integers(0, n)) for n in shape) for _ in range(8)]
+    worst_u, worst_r = 0.0, 0.0
+    for c in cells:
+        if solid[c]:
+            continue
+        r_o, u_o = cone_oracle(27, shape, 0.6, _channel_faces(), c, steps, seed, solid=solid, amp=amp)
+        r_g = float(rho[c])
+        u_g = np.array([float(u[a][c]) for a in range(3)])
+        worst_u = max(worst_u, float(np.max(np.abs(u_g - u_o))))
+        worst_r = max(worst_r, abs(r_g - r_o))
+    print(f"[case] full-size channel: max |du| {worst_u:.3e} (u scale {amp}), max |drho| {worst_r:.3e}", flush=True)
+    assert worst_u <= 1e-5 * amp * 10 and worst_r <= 1e-6
+
+
+# ---- C4: differentiable channel -----------------------------------------------------------------
+def _c4_setup(storage):
+    faces = [(ZV, (0.04, 0.0)), (OUT, (0.0, 0.0, 0.0), 1.0), (W,), (W,), (P,), (P,)]
+    s = inputs.smooth_solid_fraction(512, 256, seed=4)
+    sim = lbm.Sim("D2Q9", (512, 256), 0.6, faces=faces, storage=storage)
+    return sim, s, faces
+
+
+def _c4_target():
+    """u_T = u(500) of the oracle run with the solid fraction from seed 40."""
+    import oracle
+    from cases import _oface
+    faces = [(ZV, (0.04, 0.0)), (OUT, (0.0, 0.0, 0.0), 1.0), (W,), (W,), (P,), (P,)]
+    of = [_oface(F) for F in faces]
+    of[4] = of[5] = oracle.Face()
+    sT = inputs.smooth_solid_fraction(512, 256, seed=40).astype(np.float32).astype(np.float64)
+    S = oracle.Sim(q=9, nx=512, ny=256, nz=1, tau=0.6, faces=of, s=sT.reshape(512, 256, 1))
+    f = S.equilibrium_state()
+    S.run(f, 500)
+    _, u = S.moments(f)
+    return u[:, :, 0, :2], S, of
+
+
+def _gpu_dlds(storage, s, uT, K=50, steps=500):
+    import torch
+    sim, _, _ = _c4_setup(storage)
+    dt = torch.float64 if storage == "f64" else torch.float32
+    sim.set_solid_fraction(torch.tensor(s, dtype=torch.float32, device="cuda"))
+    sim.init_equilibrium()
+    sim.tape_begin(K, steps)
+    sim.step(steps)
+    sim.tape_end()
+    rho, u = sim.moments(dtype=torch.float64)
+    tgt = torch.tensor(np.moveaxis(uT, -1, 0).copy(), device="cuda")
+    L = float(torch.sum((u - tgt) ** 2))
+    ds, dtau, _ = sim.backward(None, 2.0 * (u - tgt), want_s=True)
+    return L, ds.double().cpu().numpy(), dtau[0]
+
+
+def test_c4_full_adjoint_vs_oracle():
+    path = os.path.join(GOLDEN, "c4_adjoint_d2q9_512x256.npz")
+    if not os.path.exists(path):
+        pytest.skip("run tests/golden/make_golden.py c4_adjoint first")
+    _announce("C4 512x256 500 steps K=50 adjoint vs oracle")
+    ref = np.load(path)
+    uT, _, _ = _c4_target()
+    s = inputs.smooth_solid_fraction(512, 256, seed=4)
+    L, g32, dtau32 = _gpu_dlds("f32", s, uT)
+    dlds = ref["dlds"].astype(np.float64)
+    e = float(np.linalg.norm(g32 - dlds) / np.linalg.norm(dlds))
+    print(f"[case] C4: L {L:.6e} vs {float(ref['loss']):.6e}; dL/ds rel-L2 {e:.3e}; "
+          f"dL/dtau {dtau32:.6e} vs {float(ref['dtau']):.6e}", flush=True)
+    assert abs(L - float(ref["loss"])) <= 1e-4 * float(ref["loss"])
+    assert e <= 1e-4
+    assert abs(dtau32 - float(ref["dtau"])) <= 1e-4 * abs(float(ref["dtau"]))
+
+
+def test_c4_full_adjoint_vs_finite_differences():
+    """FP64 GPU gradient vs central differences of the FP64 GPU forward (which
+    matches the oracle to 1e-12) at 16 cells drawn by default_rng(41)."""
+    _announce("C4 FP64 adjoint vs central differences")
+    import torch
+    uT, _, _ = _c4_target()
+    s = inputs.smooth_solid_fraction(512, 256, seed=4)
+    L, g64, _ = _gpu_dlds("f64", s, uT)
+    sim, _, _ = _c4_setup("f64")
+    tgt = torch.tensor(np.moveaxis(uT, -1, 0).copy(), device="cuda")
+    s32 = torch.tensor(s, dtype=torch.float32, device="cuda")
+
+    def loss(sv):
+        sim.set_solid_fraction(sv)
+        sim.init_equilibrium()
+        sim.step(500)
+        _, u = sim.moments(dtype=torch.float64)
+        return float(torch.sum((u - tgt) ** 2))
+
+    rng = np.random.default_rng(41)
+    fluid = np.flatnonzero(s.ravel() > 0.05)
+    h = 1e-6
+    worst = 0.0
+    for idx in rng.choice(fluid, size=16, replace=False):
+        i, j = np.unravel_index(idx, s.shape)
+        sp, sm = s32.clone(), s32.clone()
+        sp[i, j] += h
+        sm[i, j] -= h
+        step = float(sp[i, j]) - float(sm[i, j])
+        fd = (loss(sp) - loss(sm)) / step
+        err = abs(fd - g64[i, j]) / max(abs(fd), 1e-3 * float(np.max(np.abs(g64))))
+        worst = max(worst, err)
+    print(f"[case] C4 FD: worst relative error {worst:.3e}", flush=True)
+    assert worst <= 1e-4
+
+
+# ---- C5: batched cavities --------------------------------------------------------------------------
+def _c5_domains():
+    L, tau, U = inputs.batch_cavities(256, seed=5)
+    shapes = [(int(l), int(l)) for l in L]
+    faces = [[(W,), (W,), (W,), (W, (float(U[d]), 0.0)), (P,), (P,)] for d in range(256)]
+    return shapes, [float(t) for t in tau], faces, L, U
+
+
+def test_c5_full_batch_matches_single_domain_runs():
+    _announce("C5 256 cavities 2000 steps (graph) vs single-domain runs")
+    import torch
+    shapes, taus, faces, L, U = _c5_domains()
+    bs = lbm.BatchSim("D2Q9", shapes, taus, faces, storage="f32")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        bs.use_current_stream()
+        bs.init_equilibrium()
+        bs.capture_graph(2000)
+        bs.graph_launch()
+        rho, u = bs.moments(dtype=torch.float32)
+    torch.cuda.synchronize()
+    for d in [0, 1, 77, 128, 200, 255, int(np.argmin(L)), int(np.argmax(L))]:
+        sim = lbm.Sim("D2Q9", shapes[d], taus[d], faces=faces[d], storage="f32")
+        sim.init_equilibrium()
+        sim.step(2000)
+        r1, u1 = sim.moments(dtype=torch.float32)
+        assert torch.equal(bs.domain(rho, d), r1), d
+        assert torch.equal(bs.domain(u, d), u1), d
+
+
+def _c5_grads(shapes, taus, faces, steps, K, storage="f64"):
+    import torch
+    bs = lbm.BatchSim("D2Q9", shapes, taus, faces, storage=storage)
+    bs.init_equilibrium()
+    bs.tape_begin(K, steps)
+    bs.step(steps)
+    bs.tape_end()
+    rho, u = bs.moments(dtype=torch.float64)
+    n = torch.empty_like(rho)
+    for d in range(bs.n):
+        n[int(bs.offsets[d]):int(bs.offsets[d + 1])] = float(np.prod(shapes[d]))
+    E = [float(v) for v in _mean_ke(bs, rho, u)]
+    dtau, duw = bs.backward(0.5 * (u * u).sum(0) / n, rho * u / n)
+    return E, dtau, duw[:, 3, 0]
+
+
+def _mean_ke(bs, rho, u):
+    ke = 0.5 * rho * (u * u).sum(0)
+    return [float(bs.domain(ke, d).mean()) for d in range(bs.n)]
+
+
+def _c5_energy(shapes, taus, faces, steps):
+    import torch
+    bs = lbm.BatchSim("D2Q9", shapes, taus, faces, storage="f64")
+    bs.init_equilibrium()
+    bs.step(steps)
+    rho, u = bs.moments(dtype=torch.float64)
+    return _mean_ke(bs, rho, u)
+
+
+# the four smallest domains (L = 64, tau 0.60 .. 0.77): cheap for the oracle
+C5_PICK = [16, 63, 225, 177]
+
+
+def test_c5_gradients_vs_finite_differences():
+    """dE_d/dU_d and dE_d/dtau_d (E_d: mean KE of domain d at step 2000) from
+    the batch adjoint (FP64, K = 50) vs central differences of the batch
+    forward (FP64)."""
+    _announce("C5 gradients vs central differences")
+    shapes, taus, faces, L, U = _c5_domains()
+    sh = [shapes[d] for d in C5_PICK]
+    ta = [taus[d] for d in C5_PICK]
+    fa = [faces[d] for d in C5_PICK]
+    E, dtau, dU = _c5_grads(sh, ta, fa, 2000, 50)
+    hU, ht = 1e-6, 1e-6
+    for k, d in enumerate(C5_PICK):
+        up = [list(f) for f in fa]
+        um = [list(f) for f in fa]
+        up[k][3] = (W, (float(U[d]) + hU, 0.0))
+        um[k][3] = (W, (float(U[d]) - hU, 0.0))
+        fdU = (_c5_energy(sh, ta, up, 2000)[k] - _c5_energy(sh, ta, um, 2000)[k]) / (2 * hU)
+        tp, tm = list(ta), list(ta)
+        tp[k] += ht
+        tm[k] -= ht
+        fdt = (_c5_energy(sh, tp, fa, 2000)[k] - _c5_energy(sh, tm, fa, 2000)[k]) / (2 * ht)
+        print(f"[case] C5 domain {d} (L={shapes[d][0]}): dE/dU {dU[k]:.8e} fd {fdU:.8e}; "
+              f"dE/dtau {dtau[k]:.8e} fd {fdt:.8e}", flush=True)
+        assert abs(dU[k] - fdU) <= 1e-6 * abs(fdU)
+        assert abs(dtau[k] - fdt) <= 1e-5 * abs(fdt)
+
+
+def test_c5_gradients_vs_oracle():
+    """The same gradients (FP32 batch, as benchmarked) vs the FP64 oracle
+    adjoint of each domain run alone (stored by tests/golden/make_golden.py)."""
+    path = os.path.join(GOLDEN, "c5_gradients_d2q9.npz")
+    if not os.path.exists(path):
+        pytest.skip("run tests/golden/make_golden.py c5_gradients first")
+    _announce("C5 gradients vs oracle")
+    ref = np.load(path)
+    assert list(ref["domains"]) == C5_PICK
+    shapes, taus, faces, L, U = _c5_domains()
+    E, dtau, dU = _c5_grads([shapes[d] for d in C5_PICK], [taus[d] for d in C5_PICK], [faces[d] for d in C5_PICK],
+                            2000, 50, storage="f32")
+    for k, d in enumerate(C5_PICK):
+        print(f"[case] C5 domain {d}: E {E[k]:.8e} oracle {ref['E'][k]:.8e}; dE/dU {dU[k]:.8e} oracle "
+              f"{ref['dU'][k]:.8e}; dE/dtau {dtau[k]:.8e} oracle {ref['dtau'][k]:.8e}", flush=True)
+        assert abs(E[k] - ref["E"][k]) <= 1e-5 * abs(ref["E"][k])
+        assert abs(dU[k] - ref["dU"][k]) <= 1e-4 * abs(ref["dU"][k])
+        assert abs(dtau[k] - ref["dtau"][k]) <= 1e-4 * abs(ref["dtau"][k])
