@@ -80,8 +80,10 @@ def _cavity_u_plane(storage):
     return plane, sums
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f16", 1e-3), ("bf16", 2e-2)])
-def test_cavity256_1000_steps_vs_oracle(storage, tol):
+@pytest.mark.parametrize("storage,tol,mass_tol", [("f32", 1e-5, 1e-6), ("f16", 1e-3, 1e-6), ("bf16", 2e-2, 1e-4)])
+def test_cavity256_1000_steps_vs_oracle(storage, tol, mass_tol):
+    """Mass: the walls conserve it exactly; what remains is the rounding of
+    the stored deviations (BF16: 8-bit mantissa, so only a loose gate)."""
     path = os.path.join(GOLDEN, "cavity256_d3q19_1000.npz")
     if not os.path.exists(path):
         pytest.skip("run tests/golden/make_golden.py cavity256 first")
@@ -92,7 +94,7 @@ def test_cavity256_1000_steps_vs_oracle(storage, tol):
     print(f"[case] cavity256 {storage}: u rel-L2 on y = 128 {e:.3e}; KE {sums[4]:.6e} vs {ref['sums'][4]:.6e}",
           flush=True)
     assert e <= tol
-    assert abs(sums[0] - ref["sums"][0]) <= 1e-6 * ref["sums"][0]
+    assert abs(sums[0] - ref["sums"][0]) <= mass_tol * ref["sums"][0]
 
 
 # ---- C3: channel with spheres ----------------------------------------------------------------
@@ -363,6 +365,7 @@ def test_c5_gradients_vs_oracle():
     for k, d in enumerate(C5_PICK):
         print(f"[case] C5 domain {d}: E {E[k]:.8e} oracle {ref['E'][k]:.8e}; dE/dU {dU[k]:.8e} oracle "
               f"{ref['dU'][k]:.8e}; dE/dtau {dtau[k]:.8e} oracle {ref['dtau'][k]:.8e}", flush=True)
-        assert abs(E[k] - ref["E"][k]) <= 1e-5 * abs(ref["E"][k])
+        # E is quadratic in u, whose FP32-storage error is up to 1e-5 relative
+        assert abs(E[k] - ref["E"][k]) <= 3e-5 * abs(ref["E"][k])
         assert abs(dU[k] - ref["dU"][k]) <= 1e-4 * abs(ref["dU"][k])
         assert abs(dtau[k] - ref["dtau"][k]) <= 1e-4 * abs(ref["dtau"][k])
