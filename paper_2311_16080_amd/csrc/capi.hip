@@ -157,6 +157,7 @@ static void fill_params(Params<CT> &p, const lbm_ctx *c) {
     }
     p.zh_pending = c->t > 0 ? 1 : 0;
     p.xcd_remap = c->xcd_remap;
+    p.zrot = (c->zrot && c->nZ >= 64) ? 32 : 0;
     p.ft = face_table<CT>(c);
     p.flags = c->flags;
     p.nbm = c->nbm;
@@ -242,6 +243,8 @@ extern "C" lbm_ctx *lbm_create(int lattice, int nx, int ny, int nz, double tau, 
         if (nt && nt[0] >= '0' && nt[0] <= '4') c->nt = nt[0] - '0';
         const char *xr = std::getenv("LBM_XCD_REMAP");
         if (xr && (xr[0] == '0' || xr[0] == '1')) c->xcd_remap = xr[0] - '0';
+        const char *zr = std::getenv("LBM_ZROT");
+        if (zr && (zr[0] == '0' || zr[0] == '1')) c->zrot = zr[0] - '0';
         const char *bl = std::getenv("LBM_BLOCK");
         if (bl) {
             const int v = std::atoi(bl);

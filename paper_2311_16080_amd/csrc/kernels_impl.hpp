@@ -28,6 +28,10 @@ namespace lbm {
 // Block -> (X, Y, Z-chunk).  Workgroups are handed to the 8 XCDs round robin;
 // remapping makes each XCD process one contiguous range of rows, so the rows
 // a block's neighbours touch mostly sit in the same XCD's L2.
+// Within a row, lanes are rotated by p.zrot (32 when the row has >= 64
+// cells): the row's two end cells, Z = 0 and Z = nZ - 1, then share one
+// wavefront, so the other wavefronts of the row hold interior cells only and
+// take the boundary-free path of step_cell.
 template <class CT>
 __device__ __forceinline__ bool block_cell(const Params<CT> &p, int &X, int &Y, int &Z) {
     const int G = (int)gridDim.x;
@@ -37,8 +41,9 @@ __device__ __forceinline__ bool block_cell(const Params<CT> &p, int &X, int &Y, 
     const int r = b / p.zblocks;
     Y = r % p.nY;
     X = r / p.nY;
-    Z = zc * (int)blockDim.x + (int)threadIdx.x;
-    return Z < p.nZ;
+    const int lin = zc * (int)blockDim.x + (int)threadIdx.x;
+    Z = (lin >= p.zrot) ? lin - p.zrot : lin - p.zrot + p.nZ;
+    return lin < p.nZ;
 }
 
 // One cell of one step.  p: the domain's parameters; A (and B for the push
@@ -68,17 +73,52 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
     const uint32_t irr = irregular_mask<L>(e, nbm);
     const int64_t P = p.plane;
 
+    // Wavefronts of interior cells only (no face, no solid neighbour): plain
+    // loads and stores, no per-direction boundary tests.
+    if (__all(irr == 0)) {
+        CT h[Q];
+        if constexpr (MODE == 1) {
+            unroll<Q>([&](auto I) {
+                constexpr int O = opp<L>(I);
+                const int64_t src = cell - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
+                h[I] = ldh<L, ST, O, (L::c[I][2] == 0) ? NTA : NTZL>(A, P, src);
+            });
+        } else {
+            unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I, NTA>(A, P, cell); });
+        }
+        CT hp[Q];
+        CT rho, ux, uy, uz;
+        CT s = 0;
+        if constexpr (HAS_S) s = (CT)p.s[cell];
+        collide<L>(h, hp, p, s, HAS_S, rho, ux, uy, uz);
+        ST *W = (MODE == 2) ? B : A;
+        unroll<Q>([&](auto I) {
+            constexpr int O = opp<L>(I);
+            if constexpr (MODE == 0) {
+                sth<L, ST, O, NTA>(W, P, cell, hp[I]);
+            } else {
+                const int64_t dst = cell + ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
+                sth<L, ST, I, (L::c[I][2] == 0) ? NTA : NTZS>(W, P, dst, hp[I]);
+            }
+        });
+        return;
+    }
+
+    // Every direction issues exactly one load and one store: the address (and,
+    // for a boundary fill, the value) is chosen per lane, so wavefronts that
+    // hold a few boundary cells do not run extra memory instructions.
     CT h[Q];
     if constexpr (MODE == 1) {
         unroll<Q>([&](auto I) {
             constexpr int O = opp<L>(I);
+            const ST *ptr;
             if (!((irr >> I) & 1u)) {
-                const int64_t src = cell - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
-                h[I] = ldh<L, ST, O, (L::c[I][2] == 0) ? NTA : NTZL>(A, P, src);
+                ptr = pop_ptr<L, O>(A, P, cell - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]));
             } else {
                 const Nb nb = classify_src<L>(p, X, Y, Z, I, nbm);
-                h[I] = (nb.kind == NB_FLUID) ? ldh<L, ST, O>(A, P, nb.cell) : ldh<L, ST, I>(A, P, cell);
+                ptr = (nb.kind == NB_FLUID) ? pop_ptr<L, O>(A, P, nb.cell) : pop_ptr<L, I>(A, P, cell);
             }
+            h[I] = ldp<L, ST, O, (L::c[I][2] == 0) ? NTA : NTZL>(ptr);  // w_O = w_I
         });
     } else {
         unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I, NTA>(A, P, cell); });
@@ -97,22 +137,23 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
     ST *W = (MODE == 2) ? B : A;
     unroll<Q>([&](auto I) {
         constexpr int O = opp<L>(I);
+        constexpr bool NTW = (MODE == 0 || L::c[I][2] == 0) ? NTA : NTZS;
+        ST *ptr;
+        CT v = hp[I];
         if (!((irr >> O) & 1u)) {
-            if constexpr (MODE == 0) {
-                sth<L, ST, O, NTA>(W, P, cell, hp[I]);
-            } else {
-                const int64_t dst = cell + ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
-                sth<L, ST, I, (L::c[I][2] == 0) ? NTA : NTZS>(W, P, dst, hp[I]);
-            }
+            if constexpr (MODE == 0) ptr = pop_ptr<L, O>(W, P, cell);
+            else ptr = pop_ptr<L, I>(W, P, cell + ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]));
         } else {
             const Nb nb = classify_src<L>(p, X, Y, Z, O, nbm);   // the cell x + c_i
             if (nb.kind == NB_FLUID) {
-                if constexpr (MODE == 0) sth<L, ST, O>(W, P, cell, hp[I]);
-                else sth<L, ST, I>(W, P, nb.cell, hp[I]);
+                if constexpr (MODE == 0) ptr = pop_ptr<L, O>(W, P, cell);
+                else ptr = pop_ptr<L, I>(W, P, nb.cell);
             } else {
-                sth<L, ST, O>(W, P, cell, fill_value<L, I>(p, nb, hp[I], perim, rho, ux, uy, uz));
+                ptr = pop_ptr<L, O>(W, P, cell);
+                v = fill_value<L, I>(p, nb, hp[I], perim, rho, ux, uy, uz);
             }
         }
+        stp<L, ST, I, NTW>(ptr, v);  // w_O = w_I
     });
 }
 
