@@ -104,6 +104,63 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
         return;
     }
 
+    // Wavefronts whose only non-regular directions meet wall faces (no solid
+    // neighbour, no open or periodic face): halfway bounce-back with the
+    // moving-wall term, chosen per lane by selects.  Same values as the
+    // general path below (fill_value), without the per-direction classification.
+    // (Not for D3Q27: there the extra path pushes the kernel into spills.)
+    constexpr uint32_t kFaces = all_face_bits<L>();
+    if (L::Q <= 19 && __all(nbm == 0 && (e & kFaces & ~p.wallmask) == 0)) {
+        CT h[Q];
+        if constexpr (MODE == 1) {
+            unroll<Q>([&](auto I) {
+                constexpr int O = opp<L>(I);
+                const bool wall = (e & src_face_bits<L>(I)) != 0;   // x - c_i is across a wall
+                const ST *nb = pop_ptr<L, O>(A, P, cell - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]));
+                const ST *ptr = wall ? pop_ptr<L, I>(A, P, cell) : nb;
+                h[I] = ldp<L, ST, O, (L::c[I][2] == 0) ? NTA : NTZL>(ptr);  // w_O = w_I
+            });
+        } else {
+            unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I, NTA>(A, P, cell); });
+        }
+        CT hp[Q];
+        CT rho, ux, uy, uz;
+        CT s = 0;
+        if constexpr (HAS_S) s = (CT)p.s[cell];
+        collide<L>(h, hp, p, s, HAS_S, rho, ux, uy, uz);
+        ST *W = (MODE == 2) ? B : A;
+        unroll<Q>([&](auto I) {
+            constexpr int O = opp<L>(I);
+            constexpr uint32_t fb = src_face_bits<L>(O);     // faces x + c_i can lie across
+            constexpr bool NTW = (MODE == 0 || L::c[I][2] == 0) ? NTA : NTZS;
+            const uint32_t cr = e & fb;
+            ST *own = pop_ptr<L, O>(W, P, cell);
+            ST *ptr = own;
+            if constexpr (MODE != 0)
+                ptr = cr ? own : pop_ptr<L, I>(W, P, cell + ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]));
+            CT v = hp[I];
+            if (cr && !(cr & p.staticmask)) {
+                // moving wall: the lowest-index face crossed (static walls win)
+                CT wx = 0, wy = 0, wz = 0;
+                bool found = false;
+                unroll<6>([&](auto F) {
+                    if constexpr ((fb >> F) & 1u) {
+                        if (!found && ((cr >> F) & 1u)) {
+                            wx = p.uw[F][0];
+                            wy = p.uw[F][1];
+                            wz = p.uw[F][2];
+                            found = true;
+                        }
+                    }
+                });
+                const CT cu = (CT)L::c[O][0] * wx + (CT)L::c[O][1] * wy + (CT)L::c[O][2] * wz;
+                v = hp[I] + (CT)(6.0 * weight<L>(O)) * p.rho0 * cu;
+            }
+            stp<L, ST, I, NTW>(ptr, v);  // w_O = w_I
+        });
+        return;
+    }
+
     // Every direction issues exactly one load and one store: the address (and,
     // for a boundary fill, the value) is chosen per lane, so wavefronts that
     // hold a few boundary cells do not run extra memory instructions.

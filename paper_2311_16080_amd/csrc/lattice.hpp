@@ -85,4 +85,12 @@ __host__ __device__ constexpr uint32_t src_face_bits(int i) {
     return m;
 }
 
+// Faces any direction's source can cross (the lattice's axes).
+template <class L>
+__host__ __device__ constexpr uint32_t all_face_bits() {
+    uint32_t m = 0;
+    for (int i = 0; i < L::Q; ++i) m |= src_face_bits<L>(i);
+    return m;
+}
+
 }  // namespace lbm
