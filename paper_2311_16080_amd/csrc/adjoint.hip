@@ -149,38 +149,54 @@ __device__ __forceinline__ typename Store<ST>::CT adjoint_cell(const Params<type
     const CT om = p.omega;
 
     // b_k: adjoint of the post-collision value f°_k(x): a_k(x + c_k) for a
-    // fluid neighbour, a_opp(k)(x) off a wall or solid, 0 out of an open face
+    // fluid neighbour, a_opp(k)(x) off a wall or solid, 0 out of an open face.
+    // Wavefronts of interior cells gather without tests; wavefronts whose
+    // boundary cells only meet wall faces choose the address per lane.
     CT b[Q];
-    unroll<Q>([&](auto K) {
-        constexpr int O = opp<L>(K);
-        if (!((irr >> O) & 1u)) {
+    CT ex = 0, ey = 0, ez = 0;  // adjoint of u(x, t) through the equilibrium fills
+    constexpr uint32_t kFaces = all_face_bits<L>();
+    if (__all(irr == 0)) {
+        unroll<Q>([&](auto K) {
             const int64_t dst = cell + ((int64_t)L::c[K][0] * p.sX + (int64_t)L::c[K][1] * p.sY + L::c[K][2]);
             b[K] = An[(int64_t)K * P + dst];
-        } else {
-            const Nb nb = classify_src<L>(p, X, Y, Z, O, nbm);  // the cell x + c_k
-            const int64_t idx = (nb.kind == NB_FLUID) ? (int64_t)K * P + nb.cell : (int64_t)O * P + cell;
-            const CT v = An[idx];
-            b[K] = (nb.kind == NB_FLUID || nb.kind == NB_WALL) ? v : (CT)0;
-        }
-    });
-    // adjoint of u(x, t) through the equilibrium fills of incoming populations
-    CT ex = 0, ey = 0, ez = 0;
-    if (irr) {
-        const bool perim = (e & p.wallmask) != 0;
+        });
+    } else if (__all(nbm == 0 && (e & kFaces & ~p.wallmask) == 0)) {
         unroll<Q>([&](auto K) {
-            if ((irr >> K) & 1u) {
-                const Nb ns = classify_src<L>(p, X, Y, Z, K, nbm);
-                if (ns.kind == NB_OUT || (ns.kind == NB_ZH && perim && p.ft->type[ns.face] == F_ZH_PRES)) {
-                    const CT aK = An[(int64_t)K * P + cell];
-                    const CT rf = p.ft->rho[ns.face];
-                    const CT cu = (CT)L::c[K][0] * ux + (CT)L::c[K][1] * uy + (CT)L::c[K][2] * uz;
-                    const CT g = aK * (CT)weight<L>(K) * rf;
-                    ex += g * ((CT)3 * (CT)L::c[K][0] + (CT)9 * cu * (CT)L::c[K][0] - (CT)3 * ux);
-                    ey += g * ((CT)3 * (CT)L::c[K][1] + (CT)9 * cu * (CT)L::c[K][1] - (CT)3 * uy);
-                    ez += g * ((CT)3 * (CT)L::c[K][2] + (CT)9 * cu * (CT)L::c[K][2] - (CT)3 * uz);
-                }
+            constexpr int O = opp<L>(K);
+            const bool wall = (e & src_face_bits<L>(O)) != 0;   // x + c_k is across a wall
+            const int64_t dst = cell + ((int64_t)L::c[K][0] * p.sX + (int64_t)L::c[K][1] * p.sY + L::c[K][2]);
+            b[K] = An[wall ? (int64_t)O * P + cell : (int64_t)K * P + dst];
+        });
+    } else {
+        unroll<Q>([&](auto K) {
+            constexpr int O = opp<L>(K);
+            if (!((irr >> O) & 1u)) {
+                const int64_t dst = cell + ((int64_t)L::c[K][0] * p.sX + (int64_t)L::c[K][1] * p.sY + L::c[K][2]);
+                b[K] = An[(int64_t)K * P + dst];
+            } else {
+                const Nb nb = classify_src<L>(p, X, Y, Z, O, nbm);  // the cell x + c_k
+                const int64_t idx = (nb.kind == NB_FLUID) ? (int64_t)K * P + nb.cell : (int64_t)O * P + cell;
+                const CT v = An[idx];
+                b[K] = (nb.kind == NB_FLUID || nb.kind == NB_WALL) ? v : (CT)0;
             }
         });
+        if (irr) {
+            const bool perim = (e & p.wallmask) != 0;
+            unroll<Q>([&](auto K) {
+                if ((irr >> K) & 1u) {
+                    const Nb ns = classify_src<L>(p, X, Y, Z, K, nbm);
+                    if (ns.kind == NB_OUT || (ns.kind == NB_ZH && perim && p.ft->type[ns.face] == F_ZH_PRES)) {
+                        const CT aK = An[(int64_t)K * P + cell];
+                        const CT rf = p.ft->rho[ns.face];
+                        const CT cu = (CT)L::c[K][0] * ux + (CT)L::c[K][1] * uy + (CT)L::c[K][2] * uz;
+                        const CT g = aK * (CT)weight<L>(K) * rf;
+                        ex += g * ((CT)3 * (CT)L::c[K][0] + (CT)9 * cu * (CT)L::c[K][0] - (CT)3 * ux);
+                        ey += g * ((CT)3 * (CT)L::c[K][1] + (CT)9 * cu * (CT)L::c[K][1] - (CT)3 * uy);
+                        ez += g * ((CT)3 * (CT)L::c[K][2] + (CT)9 * cu * (CT)L::c[K][2] - (CT)3 * uz);
+                    }
+                }
+            });
+        }
     }
 
     CT s = 0;
