@@ -157,10 +157,9 @@ static void fill_params(Params<CT> &p, const lbm_ctx *c) {
     }
     p.zh_pending = c->t > 0 ? 1 : 0;
     p.xcd_remap = c->xcd_remap;
-    // rotation pays where boundary wavefronts take the general path: measured
-    // on D3Q27 (+6%); with the wall path of D2Q9 / D3Q19 aligned rows win
-    const bool rot = c->zrot > 0 || (c->zrot < 0 && c->lattice == LBM_D3Q27);
-    p.zrot = (rot && c->nZ >= 64) ? 32 : 0;
+    // measured: with the wall path, aligned rows (no rotation) are as fast or
+    // faster on every lattice; the rotation stays available for measurement
+    p.zrot = (c->zrot > 0 && c->nZ >= 64) ? 32 : 0;
     p.ft = face_table<CT>(c);
     p.flags = c->flags;
     p.nbm = c->nbm;

@@ -43,7 +43,7 @@ struct lbm_ctx {
     int64_t grid = 1;
     int nt = 1;                      // step kernel memory hints (LBM_NT = 0..4)
     int xcd_remap = 0;               // LBM_XCD_REMAP = 0 / 1 (measured: off is faster)
-    int zrot = -1;                   // LBM_ZROT = 0 / 1: rotate lanes within a Z row by 32 (-1: per lattice)
+    int zrot = 0;                    // LBM_ZROT = 0 / 1: rotate lanes within a Z row by 32
     int block_req = 256;             // LBM_BLOCK = 64 / 128 / 256 (threads per block, along Z)
 
     // device

@@ -22,16 +22,21 @@
 // 2 Q values per cell.
 #include "kernels.hpp"
 
+// Lattices up to this Q take the wall path of step_cell (all by default;
+// the knob exists for measurement).
+#ifndef LBM_WALL_PATH_MAXQ
+#define LBM_WALL_PATH_MAXQ 27
+#endif
+
 
 namespace lbm {
 
 // Block -> (X, Y, Z-chunk).  Workgroups are handed to the 8 XCDs round robin;
 // remapping makes each XCD process one contiguous range of rows, so the rows
 // a block's neighbours touch mostly sit in the same XCD's L2.
-// Within a row, lanes are rotated by p.zrot (32 when the row has >= 64
-// cells): the row's two end cells, Z = 0 and Z = nZ - 1, then share one
-// wavefront, so the other wavefronts of the row hold interior cells only and
-// take the boundary-free path of step_cell.
+// Optionally (LBM_ZROT=1) lanes are rotated by p.zrot = 32 within a row of
+// >= 64 cells, so the row's two end cells share one wavefront; since the wall
+// path made boundary wavefronts cheap, aligned rows measure as fast or faster.
 template <class CT>
 __device__ __forceinline__ bool block_cell(const Params<CT> &p, int &X, int &Y, int &Z) {
     const int G = (int)gridDim.x;
@@ -108,9 +113,8 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
     // neighbour, no open or periodic face): halfway bounce-back with the
     // moving-wall term, chosen per lane by selects.  Same values as the
     // general path below (fill_value), without the per-direction classification.
-    // (Not for D3Q27: there the extra path pushes the kernel into spills.)
     constexpr uint32_t kFaces = all_face_bits<L>();
-    if (L::Q <= 19 && __all(nbm == 0 && (e & kFaces & ~p.wallmask) == 0)) {
+    if (L::Q <= LBM_WALL_PATH_MAXQ && __all(nbm == 0 && (e & kFaces & ~p.wallmask) == 0)) {
         CT h[Q];
         if constexpr (MODE == 1) {
             unroll<Q>([&](auto I) {
@@ -140,20 +144,11 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
                 ptr = cr ? own : pop_ptr<L, I>(W, P, cell + ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]));
             CT v = hp[I];
             if (cr && !(cr & p.staticmask)) {
-                // moving wall: the lowest-index face crossed (static walls win)
-                CT wx = 0, wy = 0, wz = 0;
-                bool found = false;
-                unroll<6>([&](auto F) {
-                    if constexpr ((fb >> F) & 1u) {
-                        if (!found && ((cr >> F) & 1u)) {
-                            wx = p.uw[F][0];
-                            wy = p.uw[F][1];
-                            wz = p.uw[F][2];
-                            found = true;
-                        }
-                    }
-                });
-                const CT cu = (CT)L::c[O][0] * wx + (CT)L::c[O][1] * wy + (CT)L::c[O][2] * wz;
+                // moving wall: the lowest-index face crossed (static walls win);
+                // its velocity from the device face table, as in fill_value
+                const int f = (int)__builtin_ctz(cr);
+                const FaceTab<CT> &F = *p.ft;
+                const CT cu = (CT)L::c[O][0] * F.uw[f][0] + (CT)L::c[O][1] * F.uw[f][1] + (CT)L::c[O][2] * F.uw[f][2];
                 v = hp[I] + (CT)(6.0 * weight<L>(O)) * p.rho0 * cu;
             }
             stp<L, ST, I, NTW>(ptr, v);  // w_O = w_I
@@ -214,8 +209,18 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
     });
 }
 
+// Waves per SIMD that the D3Q27 step kernels' registers must leave room for
+// (0: the compiler's choice).
+#ifndef LBM_STEP_WAVES_Q27
+#define LBM_STEP_WAVES_Q27 0
+#endif
+template <class L>
+struct StepWaves {
+    static constexpr int value = (L::Q == 27 && LBM_STEP_WAVES_Q27 > 0) ? LBM_STEP_WAVES_Q27 : 1;
+};
+
 template <class L, class ST, int MODE, bool HAS_S, int NT>
-__global__ void __launch_bounds__(kMaxBlock) k_step(const Params<typename Store<ST>::CT> p, ST *__restrict__ A,
+__global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(StepWaves<L>::value))) k_step(const Params<typename Store<ST>::CT> p, ST *__restrict__ A,
                                                     ST *__restrict__ B) {
     int X, Y, Z;
     if (!block_cell(p, X, Y, Z)) return;
