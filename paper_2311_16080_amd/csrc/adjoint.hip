@@ -151,7 +151,7 @@ __device__ __forceinline__ typename Store<ST>::CT adjoint_cell(const Params<type
     // b_k: adjoint of the post-collision value f°_k(x): a_k(x + c_k) for a
     // fluid neighbour, a_opp(k)(x) off a wall or solid, 0 out of an open face.
     // Wavefronts of interior cells gather without tests; wavefronts whose
-    // boundary cells only meet wall faces choose the address per lane.
+    // boundary cells only meet wall faces or solids choose the address per lane.
     CT b[Q];
     CT ex = 0, ey = 0, ez = 0;  // adjoint of u(x, t) through the equilibrium fills
     constexpr uint32_t kFaces = all_face_bits<L>();
@@ -160,10 +160,11 @@ __device__ __forceinline__ typename Store<ST>::CT adjoint_cell(const Params<type
             const int64_t dst = cell + ((int64_t)L::c[K][0] * p.sX + (int64_t)L::c[K][1] * p.sY + L::c[K][2]);
             b[K] = An[(int64_t)K * P + dst];
         });
-    } else if (__all(nbm == 0 && (e & kFaces & ~p.wallmask) == 0)) {
+    } else if (__all((e & kFaces & ~p.wallmask) == 0)) {
         unroll<Q>([&](auto K) {
             constexpr int O = opp<L>(K);
-            const bool wall = (e & src_face_bits<L>(O)) != 0;   // x + c_k is across a wall
+            // x + c_k is across a wall or solid
+            const bool wall = ((e & src_face_bits<L>(O)) | (nbm & (1u << O))) != 0;
             const int64_t dst = cell + ((int64_t)L::c[K][0] * p.sX + (int64_t)L::c[K][1] * p.sY + L::c[K][2]);
             b[K] = An[wall ? (int64_t)O * P + cell : (int64_t)K * P + dst];
         });

@@ -109,17 +109,18 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
         return;
     }
 
-    // Wavefronts whose only non-regular directions meet wall faces (no solid
-    // neighbour, no open or periodic face): halfway bounce-back with the
+    // Wavefronts whose only non-regular directions meet wall faces or solid
+    // cells (no open or periodic face): halfway bounce-back with the
     // moving-wall term, chosen per lane by selects.  Same values as the
     // general path below (fill_value), without the per-direction classification.
     constexpr uint32_t kFaces = all_face_bits<L>();
-    if (L::Q <= LBM_WALL_PATH_MAXQ && __all(nbm == 0 && (e & kFaces & ~p.wallmask) == 0)) {
+    if (L::Q <= LBM_WALL_PATH_MAXQ && __all((e & kFaces & ~p.wallmask) == 0)) {
         CT h[Q];
         if constexpr (MODE == 1) {
             unroll<Q>([&](auto I) {
                 constexpr int O = opp<L>(I);
-                const bool wall = (e & src_face_bits<L>(I)) != 0;   // x - c_i is across a wall
+                // x - c_i is across a wall or solid
+                const bool wall = ((e & src_face_bits<L>(I)) | (nbm & (1u << I))) != 0;
                 const ST *nb = pop_ptr<L, O>(A, P, cell - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]));
                 const ST *ptr = wall ? pop_ptr<L, I>(A, P, cell) : nb;
                 h[I] = ldp<L, ST, O, (L::c[I][2] == 0) ? NTA : NTZL>(ptr);  // w_O = w_I
@@ -138,10 +139,11 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
             constexpr uint32_t fb = src_face_bits<L>(O);     // faces x + c_i can lie across
             constexpr bool NTW = (MODE == 0 || L::c[I][2] == 0) ? NTA : NTZS;
             const uint32_t cr = e & fb;
+            const bool wall = (cr | (nbm & (1u << O))) != 0;  // x + c_i is across a wall or solid
             ST *own = pop_ptr<L, O>(W, P, cell);
             ST *ptr = own;
             if constexpr (MODE != 0)
-                ptr = cr ? own : pop_ptr<L, I>(W, P, cell + ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]));
+                ptr = wall ? own : pop_ptr<L, I>(W, P, cell + ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]));
             CT v = hp[I];
             if (cr && !(cr & p.staticmask)) {
                 // moving wall: the lowest-index face crossed (static walls win);
