@@ -216,13 +216,19 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
 #ifndef LBM_STEP_WAVES_Q27
 #define LBM_STEP_WAVES_Q27 0
 #endif
-template <class L>
+// ... and of the kernels with 2-byte storage.
+#ifndef LBM_STEP_WAVES_H
+#define LBM_STEP_WAVES_H 0
+#endif
+template <class L, class ST>
 struct StepWaves {
-    static constexpr int value = (L::Q == 27 && LBM_STEP_WAVES_Q27 > 0) ? LBM_STEP_WAVES_Q27 : 1;
+    static constexpr int value = (sizeof(ST) == 2 && LBM_STEP_WAVES_H > 0)
+                                     ? LBM_STEP_WAVES_H
+                                     : ((L::Q == 27 && LBM_STEP_WAVES_Q27 > 0) ? LBM_STEP_WAVES_Q27 : 1);
 };
 
 template <class L, class ST, int MODE, bool HAS_S, int NT>
-__global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(StepWaves<L>::value))) k_step(const Params<typename Store<ST>::CT> p, ST *__restrict__ A,
+__global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(StepWaves<L, ST>::value))) k_step(const Params<typename Store<ST>::CT> p, ST *__restrict__ A,
                                                     ST *__restrict__ B) {
     int X, Y, Z;
     if (!block_cell(p, X, Y, Z)) return;
