@@ -245,6 +245,8 @@ extern "C" lbm_ctx *lbm_create(int lattice, int nx, int ny, int nz, double tau, 
         if (nt && nt[0] >= '0' && nt[0] <= '4') c->nt = nt[0] - '0';
         const char *xr = std::getenv("LBM_XCD_REMAP");
         if (xr && (xr[0] == '0' || xr[0] == '1')) c->xcd_remap = xr[0] - '0';
+        const char *pr = std::getenv("LBM_PAIR");
+        if (pr && pr[0] >= '0' && pr[0] <= '2') c->pair = pr[0] - '0';
         const char *zr = std::getenv("LBM_ZROT");
         if (zr && (zr[0] == '0' || zr[0] == '1')) c->zrot = zr[0] - '0';
         const char *bl = std::getenv("LBM_BLOCK");
@@ -434,6 +436,19 @@ Launch lbm::make_launch(lbm_ctx *c) {
     g.block = (unsigned)c->block;
     g.stream = c->stream;
     g.nt = c->nt;
+    g.pair = 0;
+    g.pgrid = g.pblock = 0;
+    // two cells per lane for 2-byte storage: rows of nZ % 128 == 0 cells, no
+    // lane rotation or XCD remap (the pair kernel's row mapping is fixed)
+    if ((c->opt.storage == LBM_F16 || c->opt.storage == LBM_BF16) && c->pair && !c->batch && c->nZ % 128 == 0 &&
+        c->zrot == 0 && c->xcd_remap == 0) {
+        const int pairs = c->nZ / 2;
+        int blk = 256;
+        while (pairs % blk) blk -= 64;
+        g.pair = c->pair;
+        g.pblock = (unsigned)blk;
+        g.pgrid = (unsigned)((int64_t)c->nX * c->nY * (pairs / blk));
+    }
     return g;
 }
 

@@ -24,6 +24,9 @@ struct Launch {
     unsigned block;
     hipStream_t stream;
     int nt;              // step kernel memory hints: 0 plain, 1 non-temporal, 2 non-temporal stores
+    int pair;            // 2-byte storage: two cells per lane (k_step_pair) for 1: even steps, 2: all in-place steps
+    unsigned pgrid;      // launch shape of k_step_pair
+    unsigned pblock;
 };
 
 hipError_t launch_step(const Launch &g, int mode, bool has_s);

@@ -235,6 +235,12 @@ __global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(
     step_cell<L, ST, MODE, HAS_S, NT>(p, A, B, X, Y, Z, p.zh_pending);
 }
 
+}  // namespace lbm
+
+#include "pair_impl.hpp"
+
+namespace lbm {
+
 // f = feq(rho, u) written in natural order.  rho: N, u: D planes of N in the
 // caller's axes; IT = float or double.
 template <class L, class ST, class IT>
@@ -417,6 +423,18 @@ hipError_t step_t(const Launch &g, int mode, bool has_s) {
     const Params<CT> &p = *static_cast<const Params<CT> *>(g.params);
     ST *A = static_cast<ST *>(g.A);
     ST *B = static_cast<ST *>(g.B);
+    if constexpr (sizeof(ST) == 2) {
+        if ((g.pair == 1 && mode == 0) || (g.pair == 2 && mode != 2)) {
+#define LBM_PAIR_CASE(M, S) \
+    if (mode == M && has_s == S) hipLaunchKernelGGL((k_step_pair<L, ST, M, S>), dim3(g.pgrid), dim3(g.pblock), 0, g.stream, p, A);
+            LBM_PAIR_CASE(0, false)
+            LBM_PAIR_CASE(1, false)
+            LBM_PAIR_CASE(0, true)
+            LBM_PAIR_CASE(1, true)
+#undef LBM_PAIR_CASE
+            return hipGetLastError();
+        }
+    }
 #define LBM_STEP_CASE(M, S)                                                                            \
     if (mode == M && has_s == S) {                                                                     \
         switch (g.nt) {                                                                                \

@@ -1,0 +1,232 @@
+// pair_impl.hpp -- in-place step for 2-byte storage (FP16 / BF16) with two
+// cells per lane.
+//
+// With one cell per lane a 2-byte population moves 128 B per wavefront
+// instruction, and the kernel runs out of memory instructions long before it
+// runs out of bandwidth.  Here lane t of a Z row owns the cell pair
+// (z0, z0 + 1) = (2t, 2t + 1): every population plane is read and written as
+// aligned 32-bit pairs.  Z-shifted planes (the odd step) are realigned across
+// lanes with wavefront-wide DPP shifts; the one element that crosses into the
+// neighbouring wavefront, or into a Z wall, goes through a single-lane 2-byte
+// access.  Rows of nZ % 128 == 0 cells only, so no wavefront straddles two
+// rows: lane 0 of a row's first wavefront holds z = 0, lane 63 of its last
+// wavefront holds z = nZ - 1.
+//
+// Wavefronts whose cells meet only wall faces take this path; anything else
+// (solid cells, periodic / open faces) runs step_cell once per cell of the
+// pair.  Per cell the arithmetic is step_cell's (same collide, same rounding
+// to storage), so both paths give bitwise-equal states.
+//
+// Measured on the D3Q19 FP16 256^3 cavity: the even (local) step drops from
+// 305 to 224 us; the odd step, which holds both cells' populations and the
+// realigned pairs at once, needs ~150 VGPRs and runs slower than one cell per
+// lane (400-470 vs 288 us).  By default only even steps use this kernel
+// (LBM_PAIR=2 selects it for odd steps too, for measurement).
+#pragma once
+
+namespace lbm {
+
+template <class ST>
+struct HalfBits;
+template <>
+struct HalfBits<_Float16> {
+    __device__ static float val(uint32_t b) { return (float)__builtin_bit_cast(_Float16, (uint16_t)b); }
+    __device__ static uint32_t bits(float v) { return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)v); }
+};
+template <>
+struct HalfBits<bf16_t> {
+    __device__ static float val(uint32_t b) { return __uint_as_float((b & 0xffffu) << 16); }
+    __device__ static uint32_t bits(float v) { return (uint32_t)Store<bf16_t>::round(v); }
+};
+
+// population value of direction I (storage scale undone) from 16 stored bits
+template <class L, class ST, int I>
+__device__ __forceinline__ float hval(uint32_t b) {
+    return HalfBits<ST>::val(b) * (float)weight<L>(I);
+}
+template <class L, class ST, int I>
+__device__ __forceinline__ uint32_t hbits(float v) {
+    return HalfBits<ST>::bits(v * (float)(1.0 / weight<L>(I)));
+}
+
+template <bool NT>
+__device__ __forceinline__ uint32_t ld32(const uint32_t *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT>
+__device__ __forceinline__ void st32(uint32_t *p, uint32_t v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+// wavefront-wide shifts: lane t receives lane t - 1 (shr) / t + 1 (shl); the
+// lane without a source receives `edge`
+__device__ __forceinline__ uint32_t wave_shr1(uint32_t v, uint32_t edge) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ uint32_t wave_shl1(uint32_t v, uint32_t edge) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x130, 0xf, 0xf, false);
+}
+
+// moving-wall term of the population bounced into slot O (= opp(I)) of a
+// cell whose destination x + c_i lies across the faces cr (static walls win)
+template <class L, int O>
+__device__ __forceinline__ float wall_term(const Params<float> &p, uint32_t cr, float hpi) {
+    if (cr && !(cr & p.staticmask)) {
+        const int f = (int)__builtin_ctz(cr);
+        const FaceTab<float> &F = *p.ft;
+        const float cu = (float)L::c[O][0] * F.uw[f][0] + (float)L::c[O][1] * F.uw[f][1] + (float)L::c[O][2] * F.uw[f][2];
+        return hpi + (float)(6.0 * weight<L>(O)) * p.rho0 * cu;
+    }
+    return hpi;
+}
+
+template <class L, class ST, int MODE, bool HAS_S>
+__device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict__ A, int X, int Y, int z0,
+                                          int pending) {
+    constexpr int Q = L::Q;
+    constexpr uint32_t kFaces = all_face_bits<L>();
+    constexpr uint32_t kXY = 0xFu;  // faces of the X and Y axes
+    const int64_t P = p.plane;
+    const int64_t row = ((int64_t)X * p.nY + Y) * p.nZ;
+    const int64_t cell0 = row + z0;
+    bool plain = true;
+    if (p.flags) plain = (p.flags[cell0] | p.flags[cell0 + 1]) == 0;
+    const uint32_t e0 = edge_bits(p, X, Y, z0);
+    const uint32_t e1 = edge_bits(p, X, Y, z0 + 1);
+    if (!__all(plain && ((e0 | e1) & kFaces & ~p.wallmask) == 0)) {
+        step_cell<L, ST, MODE, HAS_S, 1>(p, A, nullptr, X, Y, z0, pending);
+        step_cell<L, ST, MODE, HAS_S, 1>(p, A, nullptr, X, Y, z0 + 1, pending);
+        return;
+    }
+    const int lane = (int)threadIdx.x & 63;
+    uint32_t *W = reinterpret_cast<uint32_t *>(A);            // pairs: element index / 2
+    uint16_t *H = reinterpret_cast<uint16_t *>(A);
+    const uint32_t exy = e0 & kXY;                              // X / Y faces: the same for the whole row
+    // ---- read: pairs of h_i(z0), h_i(z0 + 1) -------------------------------------
+    float h0[Q], h1[Q];
+    unroll<Q>([&](auto I) {
+        constexpr int O = opp<L>(I);
+        constexpr int cz = L::c[I][2];
+        uint32_t u;
+        if constexpr (MODE == 0) {
+            u = ld32<true>(W + (((int64_t)I * P + cell0) >> 1));
+        } else {
+            // Addresses are selected, not branched on, so the loads of all
+            // directions stay in flight together.  A source row across an X / Y
+            // wall means both cells bounce back (own slot I).
+            const bool wxy = (exy & src_face_bits<L>(I)) != 0;
+            const int64_t rs = row - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY);
+            const int64_t own = (int64_t)I * P + cell0;
+            const int64_t src = (int64_t)O * P + rs + z0;
+            const uint32_t a = ld32<cz == 0>(W + ((wxy ? own : src) >> 1));
+            if constexpr (cz == 1) {
+                // cell z0 needs element z0 - 1: the previous lane's high half; lane 0
+                // loads it (previous wavefront, or own slot I at the z = 0 wall), the
+                // other lanes reload an element of their own pair
+                const int64_t ea = (lane != 0 || wxy) ? own : (z0 == 0 ? own : src - 1);
+                const uint32_t ex = (uint32_t)H[ea] << 16;
+                const uint32_t sh = __builtin_amdgcn_alignbit(a, wave_shr1(a, ex), 16);
+                u = wxy ? a : sh;
+            } else if constexpr (cz == -1) {
+                // cell z0 + 1 needs element z0 + 2: the next lane's low half; lane 63
+                // loads it (next wavefront, or own slot I at the z = nZ - 1 wall)
+                const int64_t ea = (lane != 63 || wxy) ? own : (z0 + 2 == p.nZ ? own + 1 : src + 2);
+                const uint32_t ex = (uint32_t)H[ea];
+                const uint32_t sh = __builtin_amdgcn_alignbit(wave_shl1(a, ex), a, 16);
+                u = wxy ? a : sh;
+            } else {
+                u = a;
+            }
+        }
+        h0[I] = hval<L, ST, I>(u);
+        h1[I] = hval<L, ST, I>(u >> 16);
+    });
+    // ---- collide both cells (step_cell's arithmetic) ------------------------------------
+    float hp0[Q], hp1[Q];
+    float r0, ux0, uy0, uz0, r1, ux1, uy1, uz1;
+    float s0 = 0.f, s1 = 0.f;
+    if constexpr (HAS_S) {
+        s0 = p.s[cell0];
+        s1 = p.s[cell0 + 1];
+    }
+    collide<L>(h0, hp0, p, s0, HAS_S, r0, ux0, uy0, uz0);
+    collide<L>(h1, hp1, p, s1, HAS_S, r1, ux1, uy1, uz1);
+    // ---- write ------------------------------------------------------------------------
+    unroll<Q>([&](auto I) {
+        constexpr int O = opp<L>(I);
+        constexpr int cz = L::c[I][2];
+        constexpr uint32_t fb = src_face_bits<L>(O);  // faces x + c_i can lie across
+        if constexpr (MODE == 0) {
+            const uint32_t v = hbits<L, ST, I>(wall_term<L, O>(p, e0 & fb, hp0[I])) |
+                               (hbits<L, ST, I>(wall_term<L, O>(p, e1 & fb, hp1[I])) << 16);
+            st32<true>(W + (((int64_t)O * P + cell0) >> 1), v);
+        } else if (exy & fb) {
+            // destination row across an X / Y wall: both values bounce into own slot O
+            const uint32_t v = hbits<L, ST, I>(wall_term<L, O>(p, e0 & fb, hp0[I])) |
+                               (hbits<L, ST, I>(wall_term<L, O>(p, e1 & fb, hp1[I])) << 16);
+            st32<true>(W + (((int64_t)O * P + cell0) >> 1), v);
+        } else {
+            const int64_t rd = row + ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY);
+            const uint32_t v = hbits<L, ST, I>(hp0[I]) | (hbits<L, ST, I>(hp1[I]) << 16);
+            if constexpr (cz == 0) {
+                st32<true>(W + (((int64_t)I * P + rd + z0) >> 1), v);
+            } else if constexpr (cz == 1) {
+                // values go to z0 + 1, z0 + 2: the pair (z0, z0 + 1) takes the previous
+                // lane's second value and this lane's first
+                const uint32_t pv = __builtin_amdgcn_alignbit(v, wave_shr1(v, 0u), 16);
+                if (lane != 0) st32<false>(W + (((int64_t)I * P + rd + z0) >> 1), pv);
+                if (lane == 0 || lane == 63) {
+                    int64_t at;
+                    uint32_t b;
+                    if (lane == 0) {
+                        at = (int64_t)I * P + rd + z0 + 1;
+                        b = v & 0xffffu;
+                    } else if (z0 + 2 == p.nZ) {
+                        // z = nZ - 1 bounces off the z = nZ - 1 wall into its own slot O
+                        at = (int64_t)O * P + cell0 + 1;
+                        b = hbits<L, ST, I>(wall_term<L, O>(p, e1 & fb, hp1[I]));
+                    } else {
+                        at = (int64_t)I * P + rd + z0 + 2;
+                        b = v >> 16;
+                    }
+                    H[at] = (uint16_t)b;
+                }
+            } else {
+                // values go to z0 - 1, z0: the pair (z0, z0 + 1) takes this lane's second
+                // value and the next lane's first
+                const uint32_t pv = __builtin_amdgcn_alignbit(wave_shl1(v, 0u), v, 16);
+                if (lane != 63) st32<false>(W + (((int64_t)I * P + rd + z0) >> 1), pv);
+                if (lane == 0 || lane == 63) {
+                    int64_t at;
+                    uint32_t b;
+                    if (lane == 63) {
+                        at = (int64_t)I * P + rd + z0;
+                        b = v >> 16;
+                    } else if (z0 == 0) {
+                        // z = 0 bounces off the z = 0 wall into its own slot O
+                        at = (int64_t)O * P + cell0;
+                        b = hbits<L, ST, I>(wall_term<L, O>(p, e0 & fb, hp0[I]));
+                    } else {
+                        at = (int64_t)I * P + rd + z0 - 1;
+                        b = v & 0xffffu;
+                    }
+                    H[at] = (uint16_t)b;
+                }
+            }
+        }
+    });
+}
+
+// one lane per cell pair; grid: rows x (nZ / 2 / blockDim.x)
+template <class L, class ST, int MODE, bool HAS_S>
+__global__ void __launch_bounds__(kMaxBlock) k_step_pair(const Params<float> p, ST *__restrict__ A) {
+    const int per_row = (p.nZ >> 1) / (int)blockDim.x;
+    const int b = (int)blockIdx.x;
+    const int r = b / per_row;
+    const int z0 = 2 * ((b - r * per_row) * (int)blockDim.x + (int)threadIdx.x);
+    step_pair<L, ST, MODE, HAS_S>(p, A, r / p.nY, r % p.nY, z0, p.zh_pending);
+}
+
+}  // namespace lbm

@@ -196,3 +196,35 @@ def test_memory_hints_do_not_change_results(storage, monkeypatch):
             ref = g
         else:
             assert np.array_equal(ref[0], g[0]) and np.array_equal(ref[1], g[1]), nt
+
+
+PAIR_CASES = {
+    "cavity_d3q19": (19, (8, 9, 256), [(W,)] * 5 + [(W, (0.05, 0.01, 0))]),
+    "moving_walls_d3q19": (19, (6, 7, 384), [(W,), (W, (0, 0.02, 0.01)), (W,), (W, (0.03, 0, -0.02)),
+                                             (W, (0.02, 0.01, 0)), (W, (0.05, 0.01, 0))]),
+    "periodic_z_d3q19": (19, (6, 5, 128), [(W,), (W, (0, 0.01, 0.02)), (W,), (W,), (P,), (P,)]),
+    "periodic_xy_d3q27": (27, (4, 5, 256), [(P,), (P,), (P,), (P,), (W,), (W, (0.04, 0, 0))]),
+    "channel_zouhe_d3q19": (19, (20, 6, 128), [(ZV, (0.03, 0, 0)), (OUT, (0, 0, 0), 1.0), (W,), (W,), (W,), (W,)]),
+    "cavity_d2q9": (9, (40, 256), [(W,), (W,), (W,), (W, (0.08, 0.0)), (P,), (P,)]),
+    "spheres_d3q27": (27, (24, 12, 128), [(ZV, (0.03, 0, 0)), (OUT, (0, 0, 0), 1.0), (W,), (W,), (W,), (W,)]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PAIR_CASES))
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_pair_kernel_matches_one_cell_per_lane_bitwise(name, storage, monkeypatch):
+    """2-byte storage runs two cells per lane where rows allow it; the result
+    is bitwise that of the one-cell-per-lane kernel (same per-cell arithmetic)."""
+    _announce(f"pair kernel {name} {storage}")
+    q, shape, faces = PAIR_CASES[name]
+    solid = spheres(shape) if name.startswith("spheres") else None
+    res = {}
+    for pair in ("0", "1", "2"):       # never / even steps / even and odd steps
+        monkeypatch.setenv("LBM_PAIR", pair)
+        for steps in (7, 8):
+            res[(pair, steps)] = gpu_run(Case(q, shape, 0.6, faces, steps=steps, storage=storage, init_seed=55,
+                                              solid=solid))
+    for pair in ("1", "2"):
+        for steps in (7, 8):
+            a, b = res[("0", steps)], res[(pair, steps)]
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), (pair, steps)
