@@ -18,10 +18,10 @@
 // to storage), so both paths give bitwise-equal states.
 //
 // Measured on the D3Q19 FP16 256^3 cavity: the even (local) step drops from
-// 305 to 224 us; the odd step, which holds both cells' populations and the
-// realigned pairs at once, needs ~150 VGPRs and runs slower than one cell per
-// lane (400-470 vs 288 us).  By default only even steps use this kernel
-// (LBM_PAIR=2 selects it for odd steps too, for measurement).
+// 305 to 224 us.  The odd step needs ~133 VGPRs (3 waves per SIMD; forcing 4
+// spills) and runs slower than one cell per lane (400-590 vs 288 us), so by
+// default only even steps use this kernel (LBM_PAIR=2 selects it for odd
+// steps too, for measurement).
 #pragma once
 
 namespace lbm {
@@ -105,13 +105,12 @@ __device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict
     uint16_t *H = reinterpret_cast<uint16_t *>(A);
     const uint32_t exy = e0 & kXY;                              // X / Y faces: the same for the whole row
     // ---- read: pairs of h_i(z0), h_i(z0 + 1) -------------------------------------
-    float h0[Q], h1[Q];
+    uint32_t u[Q];
     unroll<Q>([&](auto I) {
         constexpr int O = opp<L>(I);
         constexpr int cz = L::c[I][2];
-        uint32_t u;
         if constexpr (MODE == 0) {
-            u = ld32<true>(W + (((int64_t)I * P + cell0) >> 1));
+            u[I] = ld32<true>(W + (((int64_t)I * P + cell0) >> 1));
         } else {
             // Addresses are selected, not branched on, so the loads of all
             // directions stay in flight together.  A source row across an X / Y
@@ -128,48 +127,57 @@ __device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict
                 const int64_t ea = (lane != 0 || wxy) ? own : (z0 == 0 ? own : src - 1);
                 const uint32_t ex = (uint32_t)H[ea] << 16;
                 const uint32_t sh = __builtin_amdgcn_alignbit(a, wave_shr1(a, ex), 16);
-                u = wxy ? a : sh;
+                u[I] = wxy ? a : sh;
             } else if constexpr (cz == -1) {
                 // cell z0 + 1 needs element z0 + 2: the next lane's low half; lane 63
                 // loads it (next wavefront, or own slot I at the z = nZ - 1 wall)
                 const int64_t ea = (lane != 63 || wxy) ? own : (z0 + 2 == p.nZ ? own + 1 : src + 2);
                 const uint32_t ex = (uint32_t)H[ea];
                 const uint32_t sh = __builtin_amdgcn_alignbit(wave_shl1(a, ex), a, 16);
-                u = wxy ? a : sh;
+                u[I] = wxy ? a : sh;
             } else {
-                u = a;
+                u[I] = a;
             }
         }
-        h0[I] = hval<L, ST, I>(u);
-        h1[I] = hval<L, ST, I>(u >> 16);
     });
-    // ---- collide both cells (step_cell's arithmetic) ------------------------------------
-    float hp0[Q], hp1[Q];
-    float r0, ux0, uy0, uz0, r1, ux1, uy1, uz1;
-    float s0 = 0.f, s1 = 0.f;
-    if constexpr (HAS_S) {
-        s0 = p.s[cell0];
-        s1 = p.s[cell0 + 1];
+    // ---- collide the two cells one after the other (step_cell's arithmetic) -------------
+    // out[i] packs the value each cell writes for direction i: the post-collision
+    // value, or, where x + c_i lies across a wall, the bounced value with the
+    // moving-wall term (only the bounce stores below use those).
+    uint32_t out[Q];
+    {
+        float h[Q], hp[Q];
+        float r, ux, uy, uz;
+        unroll<Q>([&](auto I) { h[I] = hval<L, ST, I>(u[I]); });
+        const float s0 = HAS_S ? p.s[cell0] : 0.f;
+        collide<L>(h, hp, p, s0, HAS_S, r, ux, uy, uz);
+        unroll<Q>([&](auto I) {
+            out[I] = hbits<L, ST, I>(wall_term<L, opp<L>(I)>(p, e0 & src_face_bits<L>(opp<L>(I)), hp[I]));
+        });
     }
-    collide<L>(h0, hp0, p, s0, HAS_S, r0, ux0, uy0, uz0);
-    collide<L>(h1, hp1, p, s1, HAS_S, r1, ux1, uy1, uz1);
+    {
+        float h[Q], hp[Q];
+        float r, ux, uy, uz;
+        unroll<Q>([&](auto I) { h[I] = hval<L, ST, I>(u[I] >> 16); });
+        const float s1 = HAS_S ? p.s[cell0 + 1] : 0.f;
+        collide<L>(h, hp, p, s1, HAS_S, r, ux, uy, uz);
+        unroll<Q>([&](auto I) {
+            out[I] |= hbits<L, ST, I>(wall_term<L, opp<L>(I)>(p, e1 & src_face_bits<L>(opp<L>(I)), hp[I])) << 16;
+        });
+    }
     // ---- write ------------------------------------------------------------------------
     unroll<Q>([&](auto I) {
         constexpr int O = opp<L>(I);
         constexpr int cz = L::c[I][2];
         constexpr uint32_t fb = src_face_bits<L>(O);  // faces x + c_i can lie across
+        const uint32_t v = out[I];
         if constexpr (MODE == 0) {
-            const uint32_t v = hbits<L, ST, I>(wall_term<L, O>(p, e0 & fb, hp0[I])) |
-                               (hbits<L, ST, I>(wall_term<L, O>(p, e1 & fb, hp1[I])) << 16);
             st32<true>(W + (((int64_t)O * P + cell0) >> 1), v);
         } else if (exy & fb) {
             // destination row across an X / Y wall: both values bounce into own slot O
-            const uint32_t v = hbits<L, ST, I>(wall_term<L, O>(p, e0 & fb, hp0[I])) |
-                               (hbits<L, ST, I>(wall_term<L, O>(p, e1 & fb, hp1[I])) << 16);
             st32<true>(W + (((int64_t)O * P + cell0) >> 1), v);
         } else {
             const int64_t rd = row + ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY);
-            const uint32_t v = hbits<L, ST, I>(hp0[I]) | (hbits<L, ST, I>(hp1[I]) << 16);
             if constexpr (cz == 0) {
                 st32<true>(W + (((int64_t)I * P + rd + z0) >> 1), v);
             } else if constexpr (cz == 1) {
@@ -178,20 +186,12 @@ __device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict
                 const uint32_t pv = __builtin_amdgcn_alignbit(v, wave_shr1(v, 0u), 16);
                 if (lane != 0) st32<false>(W + (((int64_t)I * P + rd + z0) >> 1), pv);
                 if (lane == 0 || lane == 63) {
-                    int64_t at;
-                    uint32_t b;
-                    if (lane == 0) {
-                        at = (int64_t)I * P + rd + z0 + 1;
-                        b = v & 0xffffu;
-                    } else if (z0 + 2 == p.nZ) {
-                        // z = nZ - 1 bounces off the z = nZ - 1 wall into its own slot O
-                        at = (int64_t)O * P + cell0 + 1;
-                        b = hbits<L, ST, I>(wall_term<L, O>(p, e1 & fb, hp1[I]));
-                    } else {
-                        at = (int64_t)I * P + rd + z0 + 2;
-                        b = v >> 16;
-                    }
-                    H[at] = (uint16_t)b;
+                    // lane 0: its first value; lane 63: its second value, into the next
+                    // wavefront's first element, or bounced off the z = nZ - 1 wall
+                    const int64_t at = lane == 0 ? (int64_t)I * P + rd + z0 + 1
+                                                 : (z0 + 2 == p.nZ ? (int64_t)O * P + cell0 + 1
+                                                                   : (int64_t)I * P + rd + z0 + 2);
+                    H[at] = (uint16_t)(lane == 0 ? v : v >> 16);
                 }
             } else {
                 // values go to z0 - 1, z0: the pair (z0, z0 + 1) takes this lane's second
@@ -199,20 +199,11 @@ __device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict
                 const uint32_t pv = __builtin_amdgcn_alignbit(wave_shl1(v, 0u), v, 16);
                 if (lane != 63) st32<false>(W + (((int64_t)I * P + rd + z0) >> 1), pv);
                 if (lane == 0 || lane == 63) {
-                    int64_t at;
-                    uint32_t b;
-                    if (lane == 63) {
-                        at = (int64_t)I * P + rd + z0;
-                        b = v >> 16;
-                    } else if (z0 == 0) {
-                        // z = 0 bounces off the z = 0 wall into its own slot O
-                        at = (int64_t)O * P + cell0;
-                        b = hbits<L, ST, I>(wall_term<L, O>(p, e0 & fb, hp0[I]));
-                    } else {
-                        at = (int64_t)I * P + rd + z0 - 1;
-                        b = v & 0xffffu;
-                    }
-                    H[at] = (uint16_t)b;
+                    // lane 63: its second value; lane 0: its first value, into the previous
+                    // wavefront's last element, or bounced off the z = 0 wall
+                    const int64_t at = lane == 63 ? (int64_t)I * P + rd + z0
+                                                  : (z0 == 0 ? (int64_t)O * P + cell0 : (int64_t)I * P + rd + z0 - 1);
+                    H[at] = (uint16_t)(lane == 63 ? v >> 16 : v);
                 }
             }
         }
