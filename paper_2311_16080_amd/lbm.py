@@ -92,8 +92,7 @@ def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python paper_2311_16080_amd/build.py` "
-                               "(or __graft_entry__.build())")
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python paper_2311_16080_amd/build.py`")
         # PyTorch-ROCm carries its own HIP runtime.  Loading torch first makes
         # liblbm.so bind to that same runtime (same soname), so the library and
         # torch share one HIP/HSA instance, devices and streams; loading
