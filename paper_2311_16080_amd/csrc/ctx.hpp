@@ -41,7 +41,7 @@ struct lbm_ctx {
     lbm_options opt{};
     int block = 256, zblocks = 1;
     int64_t grid = 1;
-    int nt = 1;                      // step kernel memory hints (LBM_NT = 0..4)
+    int nt = -1;                     // step kernel memory hints (LBM_NT = 0..4; -1: per storage type)
     int xcd_remap = 0;               // LBM_XCD_REMAP = 0 / 1 (measured: off is faster)
     int zrot = 0;                    // LBM_ZROT = 0 / 1: rotate lanes within a Z row by 32
     int pair = 1;                    // LBM_PAIR = 0 / 1 / 2: two cells per lane for FP16 / BF16 storage (0 never, 1 even steps, 2 all in-place steps)
