@@ -70,6 +70,7 @@ def lib():
         L.orc_init_equilibrium.argtypes = [P(_Sim), ctypes.c_void_p, ctypes.c_void_p, dp]
         L.orc_moments.argtypes = [P(_Sim), dp, dp, dp]
         L.orc_sums.argtypes = [P(_Sim), dp, dp]
+        L.orc_forces.argtypes = [P(_Sim), dp, dp]
         L.orc_adjoint_step.argtypes = [P(_Sim), dp, dp, dp, ctypes.c_void_p, dp, dp]
         L.orc_adjoint_step.restype = ctypes.c_int
         L.orc_num_threads.restype = ctypes.c_int
@@ -209,6 +210,14 @@ class Sim:
         out = np.zeros(5)
         lib().orc_sums(ctypes.byref(st), _dp(np.ascontiguousarray(f)), _dp(out))
         return out
+
+    def forces(self, f: np.ndarray):
+        """Momentum-exchange force of the step that produced f: (force on the
+        solid cells [3], force on each wall face [6, 3])."""
+        st = self._struct()
+        out = np.zeros(21)
+        lib().orc_forces(ctypes.byref(st), _dp(np.ascontiguousarray(f)), _dp(out))
+        return out[:3].copy(), out[3:].reshape(6, 3).copy()
 
     def collide_cell(self, f_cell: np.ndarray) -> np.ndarray:
         st = self._struct()

@@ -180,6 +180,7 @@ typedef struct {
     size_t cell;       /* SRC_FLUID: index of the (wrapped) source cell */
     double uw[3];      /* SRC_WALL: wall velocity (0 for solid cells, static walls) */
     int face;          /* face crossed (WALL with moving velocity / ZOUHE / OUTFLOW), else -1 */
+    int wall_face;     /* SRC_WALL across the domain boundary: lowest-index wall face crossed, else -1 */
 } orc_src;
 
 /* Domain faces are halfway outside the outermost cell layer, so every cell of
@@ -191,7 +192,7 @@ static orc_src classify(const orc_sim *S, const int x[3], const int *c)
     orc_src r;
     int y[3];
     int crossed[3], ncross = 0;
-    r.kind = SRC_FLUID; r.cell = 0; r.face = -1;
+    r.kind = SRC_FLUID; r.cell = 0; r.face = -1; r.wall_face = -1;
     r.uw[0] = r.uw[1] = r.uw[2] = 0.0;
     for (int a = 0; a < 3; ++a) {
         int n = dimn(S, a);
@@ -221,6 +222,7 @@ static orc_src classify(const orc_sim *S, const int x[3], const int *c)
     }
     if (nwall > 0) {
         r.kind = SRC_WALL;
+        r.wall_face = first_wall;
         if (!any_static) {
             r.face = first_wall;
             for (int a = 0; a < 3; ++a) r.uw[a] = S->face[first_wall].u[a];
@@ -641,6 +643,52 @@ int orc_adjoint_step(const orc_sim *S, const double *f, const double *a_next, do
     if (dLduw) for (int m = 0; m < 18; ++m) dLduw[m] += duw[m];
     free(ag); free(apost); free(au); free(fpost); free(vel);
     return 0;
+}
+
+/*
+ * Momentum-exchange force (Ladd 1994) of the step that produced f (= f(t+1)),
+ * the drag / lift sums of the paper's obstacle flows (Sec. 4.4).  For every
+ * fluid cell x and direction i whose neighbour x + c_i is a solid cell or
+ * lies across a wall face, the post-collision population f°_i(x, t) left
+ * along c_i and came back as f_opp(i)(x, t + 1) = f°_i + 6 w_opp rho0
+ * (c_opp . u_w).  The fluid lost (f°_i + f_opp(i)(x, t + 1)) c_i of momentum
+ * to that solid or wall; summed over links (Kahan, FP64):
+ *   out[0..2]          force on the solid cells,
+ *   out[3 + 3 f + a]   force on wall face f (a link across several wall faces
+ *                      counts for the lowest-index one).
+ */
+void orc_forces(const orc_sim *S, const double *f, double *out)
+{
+    const int q = S->q;
+    double s[21], comp[21];
+    for (int k = 0; k < 21; ++k) s[k] = comp[k] = 0.0;
+    int x[3];
+    for (x[0] = 0; x[0] < S->nx; ++x[0])
+        for (x[1] = 0; x[1] < S->ny; ++x[1])
+            for (x[2] = 0; x[2] < S->nz; ++x[2]) {
+                const size_t cell = cell_index(S, x);
+                if (S->solid && S->solid[cell]) continue;
+                for (int i = 1; i < q; ++i) {
+                    const int *c = cvec(q, i);
+                    const int o = opposite(q, i);
+                    int mc[3] = {-c[0], -c[1], -c[2]};
+                    const orc_src src = classify(S, x, mc);   /* the cell x + c_i */
+                    if (src.kind != SRC_WALL) continue;
+                    const int *co = cvec(q, o);
+                    const double back = f[cell * q + o];       /* f_opp(i)(x, t + 1) */
+                    const double term = 6.0 * weight(q, o) * S->rho0 *
+                                        (co[0] * src.uw[0] + co[1] * src.uw[1] + co[2] * src.uw[2]);
+                    const double ex = 2.0 * back - term;       /* f°_i + f_opp(i)(x, t + 1) */
+                    const int base = (src.wall_face >= 0) ? 3 + 3 * src.wall_face : 0;
+                    for (int a = 0; a < 3; ++a) {
+                        const double y = ex * c[a] - comp[base + a];
+                        const double t = s[base + a] + y;
+                        comp[base + a] = (t - s[base + a]) - y;
+                        s[base + a] = t;
+                    }
+                }
+            }
+    for (int k = 0; k < 21; ++k) out[k] = s[k];
 }
 
 int orc_num_threads(void)
