@@ -224,6 +224,24 @@ int64_t lbm_time(const lbm_ctx *ctx);
 int lbm_moments(lbm_ctx *ctx, void *rho, void *u, int dtype, double *sums_host);
 
 /*
+ * Momentum-exchange force (Ladd) of the most recent step: the momentum the
+ * fluid handed to the solid cells and to each wall face while streaming into
+ * them -- the drag / lift sums of the paper's obstacle flows (Sec. 4.4).  For
+ * every fluid cell x and direction i whose neighbour x + c_i is solid or
+ * across a wall face, the link contributes (f°_i(x, t) + f_opp(i)(x, t+1)) c_i,
+ * with f_opp(i)(x, t+1) = f°_i + 6 w_opp rho0 (c_opp . u_w).  In a closed domain
+ * the fluid momentum changes over the step by exactly minus the sum of all
+ * these forces.
+ * out: host double[21], overwritten: out[0..2] force on the solid cells,
+ * out[3 + 3 f + a] force on face f (f = -x, +x, -y, +y, -z, +z), axis a,
+ * caller axes (2-D: faces -x, +x, -y, +y and axes x, y; the rest 0); a link
+ * across several wall faces counts for the lowest-index one.  Summed in FP64
+ * in a fixed order (deterministic).  Synchronises.  LBM_ESTATE before the
+ * first step after init / load; LBM_EUNSUPPORTED on batch contexts.
+ */
+int lbm_forces(lbm_ctx *ctx, double *out);
+
+/*
  * Start recording a tape for lbm_backward: a bit-exact checkpoint of the
  * state now and every K >= 1 steps after it.  The segment between
  * checkpoints is recomputed during the backward pass.  LBM_ENOMEM if the

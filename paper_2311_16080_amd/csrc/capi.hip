@@ -412,6 +412,7 @@ void lbm::free_all(lbm_ctx *c) {
     dev_free((void *&)c->s);
     dev_free((void *&)c->ftd);
     dev_free((void *&)c->ftf);
+    dev_free((void *&)c->frows);
     batch_release(c);
 }
 
@@ -620,6 +621,39 @@ extern "C" int lbm_moments(lbm_ctx *c, void *rho, void *u, int dtype, double *su
         }
     }
     if (e != hipSuccess) return hip_fail(e, "lbm_moments");
+    return LBM_OK;
+}
+
+extern "C" int lbm_forces(lbm_ctx *c, double *out) {
+    if (!c || !out) return fail(LBM_EINVAL, "null argument");
+    if (c->batch) return fail(LBM_EUNSUPPORTED, "lbm_forces takes a single-domain context");
+    if (!c->A) return fail(LBM_ESTATE, "state not initialised (call lbm_init_equilibrium)");
+    if (c->t < 1) return fail(LBM_ESTATE, "no step taken since the last init / load");
+    int rc = ensure_device(c);
+    if (rc) return rc;
+    constexpr int kSlots = 21;
+    if (!c->frows) {
+        rc = dev_alloc((void **)&c->frows, ((size_t)c->grid + 1) * kSlots * sizeof(double), "force sums");
+        if (rc) return rc;
+    }
+    refresh_params(c);
+    double *sum_dev = c->frows + (size_t)c->grid * kSlots;
+    hipError_t e = launch_forces(make_launch(c), c->frows);
+    if (e == hipSuccess) e = launch_rows_reduce(c->frows, c->grid, kSlots, sum_dev, c->stream);
+    double m[kSlots];
+    if (e == hipSuccess) e = hipMemcpyAsync(m, sum_dev, sizeof m, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "lbm_forces");
+    // internal faces / axes -> caller faces / axes
+    for (int k = 0; k < kSlots; ++k) out[k] = 0.0;
+    if (c->D == 3) {
+        for (int k = 0; k < kSlots; ++k) out[k] = m[k];
+    } else {
+        out[0] = m[1];
+        out[1] = m[2];
+        for (int f = 2; f < 6; ++f)
+            for (int a = 1; a < 3; ++a) out[3 + 3 * (f - 2) + (a - 1)] = m[3 + 3 * f + a];
+    }
     return LBM_OK;
 }
 

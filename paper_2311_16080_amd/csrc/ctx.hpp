@@ -55,6 +55,7 @@ struct lbm_ctx {
     uint32_t *nbm = nullptr;
     float *s = nullptr;
     double *partial = nullptr, *sums_dev = nullptr;
+    double *frows = nullptr;         // force sums: grid rows + 1 result row of 21
     int64_t *rbeg = nullptr, *rend = nullptr;
     lbm::Params<double> pd{};
     lbm::Params<float> pf{};

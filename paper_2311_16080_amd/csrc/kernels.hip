@@ -80,6 +80,31 @@ hipError_t launch_reduce(const double *partial, const int64_t *begin, const int6
     return hipGetLastError();
 }
 
+hipError_t launch_forces(const Launch &g, double *rows) {
+    return dispatch(g, OP_FORCES, 0, false, nullptr, nullptr, nullptr, nullptr, rows, 0);
+}
+
+// out[k] = sum of rows[r * slots + k] over r, one block per slot, fixed order
+__global__ void __launch_bounds__(256) k_rows_reduce(const double *__restrict__ rows, int64_t nrows, int slots,
+                                                     double *__restrict__ out) {
+    __shared__ double red[256];
+    const int k = (int)blockIdx.x;
+    double v = 0.0;
+    for (int64_t r = threadIdx.x; r < nrows; r += 256) v += rows[r * slots + k];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = red[0];
+}
+
+hipError_t launch_rows_reduce(const double *rows, int64_t nrows, int slots, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_rows_reduce, dim3(slots), dim3(256), 0, s, rows, nrows, slots, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_solid(int lattice, const Launch &g, const uint8_t *solid, uint8_t *flags, uint32_t *nbm) {
     switch (lattice) {
         case LAT_D2Q9: return solid_t<D2Q9>(g, solid, flags, nbm);

@@ -11,7 +11,7 @@ namespace lbm {
 
 enum : int { LAT_D2Q9 = 0, LAT_D3Q19 = 1, LAT_D3Q27 = 2 };
 enum : int { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
-enum : int { OP_STEP = 0, OP_INIT = 1, OP_MOMENTS = 2 };
+enum : int { OP_STEP = 0, OP_INIT = 1, OP_MOMENTS = 2, OP_FORCES = 3 };
 
 // One launch: lattice, storage, a Params<CT> block, buffers, shape.
 struct Launch {
@@ -36,5 +36,9 @@ hipError_t launch_reduce(const double *partial, const int64_t *begin, const int6
                          hipStream_t s);
 hipError_t launch_solid(int lattice, const Launch &g, const uint8_t *solid, uint8_t *flags, uint32_t *nbm);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+// momentum-exchange force rows (grid x 21 FP64) of the current state, then
+// their fixed-order sum into out[21]
+hipError_t launch_forces(const Launch &g, double *rows);
+hipError_t launch_rows_reduce(const double *rows, int64_t nrows, int slots, double *out, hipStream_t s);
 
 }  // namespace lbm

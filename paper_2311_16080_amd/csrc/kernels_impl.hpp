@@ -487,6 +487,99 @@ hipError_t moments_t(const Launch &g, bool odd, void *rho, void *u, int out_f64,
     return hipGetLastError();
 }
 
+// Momentum-exchange force (Ladd) of the step that produced the current state.
+// For a fluid cell x and a direction i whose neighbour x + c_i is a solid
+// cell or lies across a wall face, the population that left along c_i came
+// back as f_opp(i)(x, t + 1) = f°_i + 6 w_opp rho0 (c_opp . u_w), stored in the
+// cell's own slot opp(i) in either AA parity; the link hands
+// (2 f_opp(i) - 6 w_opp rho0 c_opp . u_w) c_i of momentum to the solid / wall.
+// rows: one row of kForceSlots FP64 sums per block: [0..2] solids,
+// [3 + 3 f + a] wall face f (internal faces and axes; a link across several
+// wall faces counts for the lowest-index one).
+constexpr int kForceSlots = 21;
+
+template <class L, class ST>
+__global__ void __launch_bounds__(kMaxBlock) k_forces(const Params<typename Store<ST>::CT> p, const ST *__restrict__ A,
+                                                      double *__restrict__ rows) {
+    constexpr int Q = L::Q;
+    __shared__ double red[kForceSlots][kMaxBlock / 64];
+    int X, Y, Z;
+    double part[kForceSlots];
+#pragma unroll
+    for (int k = 0; k < kForceSlots; ++k) part[k] = 0.0;
+    bool links = false;
+    if (block_cell(p, X, Y, Z)) {
+        const int64_t cell = ((int64_t)X * p.nY + Y) * p.nZ + Z;
+        uint32_t nbm = 0;
+        bool solid = false;
+        if (p.flags) {
+            const uint8_t fl = p.flags[cell];
+            solid = fl & 1;
+            if (fl & 2) nbm = p.nbm[cell];
+        }
+        const uint32_t e = edge_bits(p, X, Y, Z);
+        if (!solid && (nbm || (e & p.wallmask))) {
+            unroll<Q>([&](auto I) {
+                constexpr int O = opp<L>(I);
+                if constexpr (I != 0) {
+                    const uint32_t cr = e & src_face_bits<L>(O) & p.wallmask;  // x + c_i across wall faces
+                    const bool wall = cr != 0;
+                    if (wall || ((nbm >> O) & 1u)) {
+                        links = true;
+                        const double back = (double)ldh<L, ST, O>(A, p.plane, cell) + weight<L>(O) * (double)p.rho0;
+                        double term = 0.0;
+                        int base = 0;
+                        if (wall) {
+                            const int f = (int)__builtin_ctz(cr);
+                            base = 3 + 3 * f;
+                            if (!(cr & p.staticmask)) {
+                                const FaceTab<typename Store<ST>::CT> &F = *p.ft;
+                                term = 6.0 * weight<L>(O) * (double)p.rho0 *
+                                       ((double)L::c[O][0] * (double)F.uw[f][0] + (double)L::c[O][1] * (double)F.uw[f][1] +
+                                        (double)L::c[O][2] * (double)F.uw[f][2]);
+                            }
+                        }
+                        const double ex = 2.0 * back - term;
+                        for (int k = 0; k < kForceSlots; k += 3)
+                            if (k == base) {
+                                part[k] += ex * L::c[I][0];
+                                part[k + 1] += ex * L::c[I][1];
+                                part[k + 2] += ex * L::c[I][2];
+                            }
+                    }
+                }
+            });
+        }
+    }
+    // fixed-order block sums (wavefronts without links contribute zeros)
+    const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+    if (__any(links)) {
+        for (int k = 0; k < kForceSlots; ++k) {
+            double v = part[k];
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if (lane == 0) red[k][wv] = v;
+        }
+    } else if (lane == 0) {
+        for (int k = 0; k < kForceSlots; ++k) red[k][wv] = 0.0;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < kForceSlots) {
+        const int nw = ((int)blockDim.x + 63) / 64;
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += red[threadIdx.x][w];
+        rows[(int64_t)blockIdx.x * kForceSlots + threadIdx.x] = t;
+    }
+}
+
+template <class L, class ST>
+hipError_t forces_t(const Launch &g, double *rows) {
+    using CT = typename Store<ST>::CT;
+    const Params<CT> &p = *static_cast<const Params<CT> *>(g.params);
+    hipLaunchKernelGGL((k_forces<L, ST>), dim3(g.grid), dim3(g.block), 0, g.stream, p, static_cast<const ST *>(g.A),
+                       rows);
+    return hipGetLastError();
+}
+
 // Launches for one (lattice, storage) pair; instantiated in kernels_<lat>_<st>.hip.
 template <class L, class ST>
 hipError_t dispatch_one(const Launch &g, int op, int a0, bool b0, const void *p0, const void *p1, void *q0, void *q1,
@@ -494,6 +587,7 @@ hipError_t dispatch_one(const Launch &g, int op, int a0, bool b0, const void *p0
     if (op == OP_STEP) return step_t<L, ST>(g, a0, b0);
     if (op == OP_INIT) return init_t<L, ST>(g, p0, p1, a0, N);
     if (op == OP_MOMENTS) return moments_t<L, ST>(g, b0, q0, q1, a0, partial, N);
+    if (op == OP_FORCES) return forces_t<L, ST>(g, partial);
     return hipErrorInvalidValue;
 }
 

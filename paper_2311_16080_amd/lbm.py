@@ -65,6 +65,7 @@ SIGNATURES = {
     "lbm_step": (_i, [_vp, _i]),
     "lbm_time": (_i64, [_vp]),
     "lbm_moments": (_i, [_vp, _vp, _vp, _i, _dp]),
+    "lbm_forces": (_i, [_vp, _dp]),
     "lbm_tape_begin": (_i, [_vp, _i, _i]),
     "lbm_tape_end": (_i, [_vp]),
     "lbm_tape_free": (_i, [_vp]),
@@ -266,6 +267,14 @@ class Sim:
         out = (ctypes.c_double * 5)()
         check(lib().lbm_moments(self.h, None, None, F64, out))
         return np.array(list(out))
+
+    def forces(self):
+        """Momentum-exchange force of the last step: (on solid cells [3], on each
+        face [6, 3]) in caller axes, FP64."""
+        out = (ctypes.c_double * 21)()
+        check(lib().lbm_forces(self.h, out))
+        a = np.array(list(out))
+        return a[:3], a[3:].reshape(6, 3)
 
     def sync(self):
         check(lib().lbm_sync(self.h))
