@@ -279,9 +279,13 @@ def channel_spheres_figures(torch, lbm, steps=50):
     N = int(np.prod(shape))
     mlups = N * steps / (T.ms / 1e3) / 1e6
     gbps = mlups * 1e6 * 216 / 1e9
+    # momentum-exchange force of the last step (drag / lift on the spheres, force on the walls)
+    with Timer(torch) as FT:
+        Fs, Ff = sim.forces()
     res = {"cells": N, "solid_fraction": round(float(solid.mean()), 4), "steps": steps,
            "MLUPS": round(mlups, 1), "GBps_at_216B": round(gbps, 1), "frac": round(gbps / PEAK_HBM_GBPS, 4),
-           "sphere_generation_s": round(gen_s, 1)}
+           "sphere_generation_s": round(gen_s, 1), "forces_ms": round(FT.ms, 3),
+           "sphere_force": [float(v) for v in Fs]}
     del sim
     return res
 

@@ -22,11 +22,6 @@
 // 2 Q values per cell.
 #include "kernels.hpp"
 
-// Lattices up to this Q take the wall path of step_cell (all by default;
-// the knob exists for measurement).
-#ifndef LBM_WALL_PATH_MAXQ
-#define LBM_WALL_PATH_MAXQ 27
-#endif
 
 
 namespace lbm {
@@ -114,7 +109,7 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
     // moving-wall term, chosen per lane by selects.  Same values as the
     // general path below (fill_value), without the per-direction classification.
     constexpr uint32_t kFaces = all_face_bits<L>();
-    if (L::Q <= LBM_WALL_PATH_MAXQ && __all((e & kFaces & ~p.wallmask) == 0)) {
+    if (__all((e & kFaces & ~p.wallmask) == 0)) {
         CT h[Q];
         if constexpr (MODE == 1) {
             unroll<Q>([&](auto I) {
@@ -211,24 +206,8 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
     });
 }
 
-// Waves per SIMD that the D3Q27 step kernels' registers must leave room for
-// (0: the compiler's choice).
-#ifndef LBM_STEP_WAVES_Q27
-#define LBM_STEP_WAVES_Q27 0
-#endif
-// ... and of the kernels with 2-byte storage.
-#ifndef LBM_STEP_WAVES_H
-#define LBM_STEP_WAVES_H 0
-#endif
-template <class L, class ST>
-struct StepWaves {
-    static constexpr int value = (sizeof(ST) == 2 && LBM_STEP_WAVES_H > 0)
-                                     ? LBM_STEP_WAVES_H
-                                     : ((L::Q == 27 && LBM_STEP_WAVES_Q27 > 0) ? LBM_STEP_WAVES_Q27 : 1);
-};
-
 template <class L, class ST, int MODE, bool HAS_S, int NT>
-__global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(StepWaves<L, ST>::value))) k_step(const Params<typename Store<ST>::CT> p, ST *__restrict__ A,
+__global__ void __launch_bounds__(kMaxBlock) k_step(const Params<typename Store<ST>::CT> p, ST *__restrict__ A,
                                                     ST *__restrict__ B) {
     int X, Y, Z;
     if (!block_cell(p, X, Y, Z)) return;
