@@ -46,7 +46,8 @@ class _Face(ctypes.Structure):
 class _Sim(ctypes.Structure):
     _fields_ = [("q", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("tau", ctypes.c_double), ("rho0", ctypes.c_double), ("face", _Face * 6),
-                ("solid", ctypes.c_void_p), ("s", ctypes.c_void_p), ("force", ctypes.c_double * 3)]
+                ("solid", ctypes.c_void_p), ("s", ctypes.c_void_p), ("force", ctypes.c_double * 3),
+                ("edm", ctypes.c_void_p)]
 
 
 _lib = None
@@ -132,6 +133,7 @@ class Sim:
     solid: Optional[np.ndarray] = None     # (nx,ny,nz) uint8
     s: Optional[np.ndarray] = None         # (nx,ny,nz) float64 solid fraction
     force: tuple = (0.0, 0.0, 0.0)
+    edm: Optional[np.ndarray] = None       # (nx,ny,nz,3) body force, exact-difference method
 
     @property
     def shape(self):
@@ -167,6 +169,15 @@ class Sim:
         ff = list(self.force) + [0.0] * (3 - len(self.force))
         for a in range(3):
             st.force[a] = float(ff[a])
+        if self.edm is not None:
+            e = np.zeros(self.shape + (3,))
+            ev = np.asarray(self.edm, dtype=np.float64).reshape(self.shape + (-1,))
+            e[..., : ev.shape[-1]] = ev
+            e = np.ascontiguousarray(e).reshape(-1)
+            self._keep.append(e)
+            st.edm = e.ctypes.data
+        else:
+            st.edm = None
         return st
 
     # --- state ---------------------------------------------------------------

@@ -52,6 +52,7 @@ typedef struct {
     const uint8_t *solid;       /* N bytes, 1 = solid; NULL = none */
     const double *s;            /* N solid fractions (partial bounce-back); NULL = none */
     double force[3];            /* body force, test hook only (Poiseuille pin) */
+    const double *edm;          /* N*3 body force per cell, exact-difference method; NULL = none */
 } orc_sim;
 
 /* ---------------------------------------------------------------------------
@@ -143,17 +144,28 @@ void orc_cell_moments(int q, const double *f, double *rho, double *u)
 }
 
 /* eq. (LBM-BGK) with dt = 1: f* = f - (1/tau)(f - feq).  The force hook adds
- * 3 w_i (c_i . F) after relaxation (oracle test hook only). */
-static void collide(const orc_sim *S, const double *f, double *fstar, double *rho, double u[3])
+ * 3 w_i (c_i . F) after relaxation (oracle test hook only).  A body force F
+ * by the exact-difference method (Sec. 6.2, after Kupershtokh) adds
+ * feq_i(rho, u + F/rho) - feq_i(rho, u) to the relaxed populations. */
+static void collide_f(const orc_sim *S, const double *f, double *fstar, double *rho, double u[3], const double *F)
 {
     int q = S->q;
     double omega = 1.0 / S->tau;
     moments(q, f, rho, u);
+    double w[3];
+    if (F)
+        for (int a = 0; a < 3; ++a) w[a] = u[a] + F[a] / *rho;
     for (int i = 0; i < q; ++i) {
         const int *c = cvec(q, i);
         fstar[i] = f[i] - omega * (f[i] - feq_i(q, i, *rho, u));
         fstar[i] += 3.0 * weight(q, i) * (c[0] * S->force[0] + c[1] * S->force[1] + c[2] * S->force[2]);
+        if (F) fstar[i] += feq_i(q, i, *rho, w) - feq_i(q, i, *rho, u);
     }
+}
+
+static void collide(const orc_sim *S, const double *f, double *fstar, double *rho, double u[3])
+{
+    collide_f(S, f, fstar, rho, u, NULL);
 }
 
 void orc_collide_cell(const orc_sim *S, const double *f, double *fstar)
@@ -338,7 +350,7 @@ static void step_impl(const orc_sim *S, const double *f, double *fn, double *fpo
         const double *fk = f + (size_t)k * q;
         double *fo = fpost + (size_t)k * q;
         double rho, u[3];
-        collide(S, fk, fo, &rho, u);
+        collide_f(S, fk, fo, &rho, u, S->edm ? S->edm + (size_t)k * 3 : NULL);
         if (S->s) {
             double s = S->s[k];
             double mixed[27];
