@@ -242,6 +242,28 @@ int lbm_moments(lbm_ctx *ctx, void *rho, void *u, int dtype, double *sums_host);
 int lbm_forces(lbm_ctx *ctx, double *out);
 
 /*
+ * Body force by the exact-difference method (Sec. 6.2, after Kupershtokh, the
+ * forcing of the paper's turbulent channel and of its neural corrector): from
+ * the next step on, every fluid cell's relaxed populations gain
+ * feq_i(rho, u + eps F / rho) - feq_i(rho, u), before any partial bounce-back
+ * mix, with F = force + field(x) and u, rho the cell's moments before the
+ * force.  lbm_moments keeps reporting u = j / rho (the method's physical
+ * velocity is u + eps F / (2 rho)).
+ *   force : host double[D] (caller axes), the uniform part; NULL = 0.
+ *   field : device pointer or NULL: D planes of N values (component-major,
+ *           cells in the order of lbm_moments' output), float for FP32 /
+ *           FP16 / BF16 storage, double for FP64 storage.  Read by every later
+ *           step: the caller keeps it allocated until the force is replaced
+ *           or the context destroyed, and may update it between steps on the
+ *           context's stream.
+ *   eps   : scale on both parts (the paper's epsilon; 1 for a plain force).
+ * A zero force with no field (or eps = 0) switches the force off.  LBM_EINVAL
+ * for a non-finite force or eps; LBM_EUNSUPPORTED on batch contexts; while a
+ * force is on, lbm_backward returns LBM_EUNSUPPORTED.  Drops a captured graph.
+ */
+int lbm_set_force(lbm_ctx *ctx, const double *force, const void *field, double eps);
+
+/*
  * Start recording a tape for lbm_backward: a bit-exact checkpoint of the
  * state now and every K >= 1 steps after it.  The segment between
  * checkpoints is recomputed during the backward pass.  LBM_ENOMEM if the

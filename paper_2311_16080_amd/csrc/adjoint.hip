@@ -160,12 +160,13 @@ __device__ __forceinline__ typename Store<ST>::CT adjoint_cell(const Params<type
             const int64_t dst = cell + ((int64_t)L::c[K][0] * p.sX + (int64_t)L::c[K][1] * p.sY + L::c[K][2]);
             b[K] = An[(int64_t)K * P + dst];
         });
-    } else if (__all((e & kFaces & ~p.wallmask) == 0)) {
+    } else if (__all((e & kFaces & ~(p.wallmask | (p.permask & kZFaces))) == 0)) {
+        const ZWrap zw = z_wrap(p, e & p.permask);
         unroll<Q>([&](auto K) {
             constexpr int O = opp<L>(K);
-            // x + c_k is across a wall or solid
-            const bool wall = ((e & src_face_bits<L>(O)) | (nbm & (1u << O))) != 0;
-            const int64_t dst = cell + ((int64_t)L::c[K][0] * p.sX + (int64_t)L::c[K][1] * p.sY + L::c[K][2]);
+            // x + c_k is across a wall or solid (periodic Z faces wrap)
+            const bool wall = ((e & p.wallmask & src_face_bits<L>(O)) | (nbm & (1u << O))) != 0;
+            const int64_t dst = cell + src_off<L, O>(p, zw);
             b[K] = An[wall ? (int64_t)O * P + cell : (int64_t)K * P + dst];
         });
     } else {

@@ -154,6 +154,7 @@ static void fill_params(Params<CT> &p, const lbm_ctx *c) {
             if (F.u[0] == 0.0 && F.u[1] == 0.0 && F.u[2] == 0.0) p.staticmask |= 1u << f;
         }
         if (F.type == LBM_ZOUHE_VELOCITY || F.type == LBM_ZOUHE_PRESSURE) p.zhmask |= 1u << f;
+        if (F.type == LBM_PERIODIC) p.permask |= 1u << f;
     }
     p.zh_pending = c->t > 0 ? 1 : 0;
     p.xcd_remap = c->xcd_remap;
@@ -164,6 +165,16 @@ static void fill_params(Params<CT> &p, const lbm_ctx *c) {
     p.flags = c->flags;
     p.nbm = c->nbm;
     p.s = c->s;
+    if (c->force_on) {
+        // caller axis a -> internal axis (2-D: x, y -> Y, Z)
+        const int off = (c->D == 3) ? 0 : 1;
+        const CT *field = static_cast<const CT *>(c->force_field);
+        for (int a = 0; a < c->D; ++a) {
+            p.fu[a + off] = (CT)c->force_u[a];
+            p.fld[a + off] = field ? field + (int64_t)a * c->N : nullptr;
+        }
+        p.feps = (CT)c->force_eps;
+    }
 }
 
 void lbm::refresh_params(lbm_ctx *c) {
@@ -442,6 +453,8 @@ Launch lbm::make_launch(lbm_ctx *c) {
     g.nt = c->nt >= 0 ? c->nt : ((c->opt.storage == LBM_F16 || c->opt.storage == LBM_BF16) ? 0 : 1);
     g.pair = 0;
     g.pgrid = g.pblock = 0;
+    g.force = c->force_on ? 1 : 0;
+    if (g.force) return g;   // the body force runs on the one-cell-per-lane kernel
     // two cells per lane for 2-byte storage: rows of nZ % 128 == 0 cells, no
     // lane rotation or XCD remap (the pair kernel's row mapping is fixed)
     if ((c->opt.storage == LBM_F16 || c->opt.storage == LBM_BF16) && c->pair && !c->batch && c->nZ % 128 == 0 &&
@@ -654,6 +667,26 @@ extern "C" int lbm_forces(lbm_ctx *c, double *out) {
         for (int f = 2; f < 6; ++f)
             for (int a = 1; a < 3; ++a) out[3 + 3 * (f - 2) + (a - 1)] = m[3 + 3 * f + a];
     }
+    return LBM_OK;
+}
+
+extern "C" int lbm_set_force(lbm_ctx *c, const double *force, const void *field, double eps) {
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if (c->batch) return fail(LBM_EUNSUPPORTED, "body forces are not supported on batch contexts");
+    if (!std::isfinite(eps)) return fail(LBM_EINVAL, "eps must be finite");
+    double u[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < c->D; ++a) {
+        if (force) {
+            if (!std::isfinite(force[a])) return fail(LBM_EINVAL, "force must be finite");
+            u[a] = eps * force[a];
+        }
+    }
+    drop_graph(c);
+    c->force_on = (field != nullptr && eps != 0.0) || u[0] != 0.0 || u[1] != 0.0 || u[2] != 0.0;
+    for (int a = 0; a < 3; ++a) c->force_u[a] = u[a];
+    c->force_field = c->force_on ? field : nullptr;
+    c->force_eps = eps;
+    refresh_params(c);
     return LBM_OK;
 }
 

@@ -53,7 +53,7 @@ struct Params {
     uint32_t wallmask;     // faces of type wall
     uint32_t staticmask;   // wall faces with zero velocity
     uint32_t zhmask;       // Zou-He faces
-    uint32_t pad0;
+    uint32_t permask;      // periodic faces
     uint8_t ftype[8];
     CT uw[6][3];           // wall / inlet velocity per face (internal axes)
     CT frho[6];            // face density (pressure / outflow)
@@ -67,6 +67,9 @@ struct Params {
     const uint32_t *nbm;   // N words: bit k set when x - c_k is a solid cell
     const float *s;        // N or null: partial bounce-back solid fraction
     const FaceTab<CT> *ft; // device copy of the face data
+    const CT *fld[3];      // body-force field per internal axis (N values, cell order) or null
+    CT fu[3];              // uniform body force per internal axis, scale applied
+    CT feps;               // scale of the field
 };
 
 // ---- storage formats -------------------------------------------------------
@@ -295,6 +298,25 @@ __device__ __forceinline__ uint32_t edge_bits(const Params<CT> &p, int X, int Y,
            ((uint32_t)(Y == p.nY - 1) << 3) | ((uint32_t)(Z == 0) << 4) | ((uint32_t)(Z == p.nZ - 1) << 5);
 }
 
+// Periodic Z faces in the select paths.  A wavefront spans Z, so only its
+// lanes at Z = 0 or nZ - 1 wrap: the Z step of a neighbour address is -1 / +1
+// in the box and nZ - 1 / 1 - nZ across a periodic face.  zl: the step to
+// Z - 1, zh: the step to Z + 1 (pe: the cell's periodic face bits).
+struct ZWrap {
+    int zl, zh;
+};
+template <class CT>
+__device__ __forceinline__ ZWrap z_wrap(const Params<CT> &p, uint32_t pe) {
+    return ZWrap{(pe & 16u) ? p.nZ - 1 : -1, (pe & 32u) ? 1 - p.nZ : 1};
+}
+// address offset of the source x - c_i
+template <class L, int I, class CT>
+__device__ __forceinline__ int64_t src_off(const Params<CT> &p, const ZWrap &w) {
+    const int dz = (L::c[I][2] > 0) ? w.zl : ((L::c[I][2] < 0) ? w.zh : 0);
+    return -((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY) + dz;
+}
+constexpr uint32_t kZFaces = 48u;
+
 // Which directions have a source that is not a plain in-box fluid neighbour.
 template <class L>
 __device__ __forceinline__ uint32_t irregular_mask(uint32_t e, uint32_t nbm) {
@@ -315,11 +337,40 @@ __device__ __forceinline__ int zh_face_of(const Params<CT> &p, uint32_t e) {
     return (int)__builtin_ctz(z);
 }
 
-// Collision (eq. LBM-BGK) of the deviations h -> post-collision hp, returning
-// the moments.  Partial bounce-back: hp_i = (1 - s) h*_i + s h_opp(i).
+// Body force by the exact-difference method (Sec. 6.2, after Kupershtokh):
+// hp_i += feq_i(rho, u + du) - feq_i(rho, u), du = F / rho, written as
+// w_i rho [3 c.du + 4.5 (c.du)(c.(u + u')) - 1.5 du.(u + u')] with
+// u' = u + du, which has no cancellation between two equilibria.
+template <class CT>
+__device__ __forceinline__ void load_body_force(const Params<CT> &p, int64_t cell, CT &fx, CT &fy, CT &fz) {
+    fx = p.fu[0];
+    fy = p.fu[1];
+    fz = p.fu[2];
+    if (p.fld[0]) fx += p.feps * p.fld[0][cell];
+    if (p.fld[1]) fy += p.feps * p.fld[1][cell];
+    if (p.fld[2]) fz += p.feps * p.fld[2][cell];
+}
+
 template <class L, class CT>
+__device__ __forceinline__ void add_body_force(CT *hp, CT fx, CT fy, CT fz, CT rho, CT inv, CT ux, CT uy, CT uz) {
+    const CT dx = fx * inv, dy = fy * inv, dz = fz * inv;
+    const CT sx = (CT)2 * ux + dx, sy = (CT)2 * uy + dy, sz = (CT)2 * uz + dz;
+    const CT b = (CT)1.5 * (dx * sx + dy * sy + dz * sz);
+    unroll<L::Q>([&](auto I) {
+        CT cd = 0, cs = 0;
+        if constexpr (L::c[I][0] != 0) { cd += (CT)L::c[I][0] * dx; cs += (CT)L::c[I][0] * sx; }
+        if constexpr (L::c[I][1] != 0) { cd += (CT)L::c[I][1] * dy; cs += (CT)L::c[I][1] * sy; }
+        if constexpr (L::c[I][2] != 0) { cd += (CT)L::c[I][2] * dz; cs += (CT)L::c[I][2] * sz; }
+        hp[I] += (CT)weight<L>(I) * rho * ((CT)3 * cd + (CT)4.5 * cd * cs - b);
+    });
+}
+
+// Collision (eq. LBM-BGK) of the deviations h -> post-collision hp, returning
+// the moments (u without the force).  FRC: add the body force (fx, fy, fz)
+// before the partial bounce-back mix hp_i = (1 - s) h*_i + s h_opp(i).
+template <class L, bool FRC = false, class CT>
 __device__ __forceinline__ void collide(const CT *h, CT *hp, const Params<CT> &p, CT s, bool has_s,
-                                        CT &rho_out, CT &ux, CT &uy, CT &uz) {
+                                        CT &rho_out, CT &ux, CT &uy, CT &uz, CT fx = 0, CT fy = 0, CT fz = 0) {
     CT drho = 0, jx = 0, jy = 0, jz = 0;
     unroll<L::Q>([&](auto I) {
         drho += h[I];
@@ -338,6 +389,7 @@ __device__ __forceinline__ void collide(const CT *h, CT *hp, const Params<CT> &p
         const CT e = heq<L, I>(drho, rho, ux, uy, uz, usq15);
         hp[I] = h[I] - om * (h[I] - e);
     });
+    if constexpr (FRC) add_body_force<L>(hp, fx, fy, fz, rho, inv, ux, uy, uz);
     if (has_s) {
         CT t[L::Q];
         unroll<L::Q>([&](auto I) { t[I] = ((CT)1 - s) * hp[I] + s * h[opp<L>(I)]; });

@@ -62,6 +62,12 @@ struct lbm_ctx {
     lbm::FaceTab<double> *ftd = nullptr;   // device face tables
     lbm::FaceTab<float> *ftf = nullptr;
 
+    // body force (exact-difference method)
+    bool force_on = false;
+    double force_u[3] = {0.0, 0.0, 0.0};   // uniform part, scale applied (caller axes)
+    const void *force_field = nullptr;     // device: D planes of N values (CT of the storage)
+    double force_eps = 1.0;
+
     // time
     int64_t t = 0;
 

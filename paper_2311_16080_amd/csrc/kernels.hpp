@@ -27,6 +27,7 @@ struct Launch {
     int pair;            // 2-byte storage: two cells per lane (k_step_pair) for 1: even steps, 2: all in-place steps
     unsigned pgrid;      // launch shape of k_step_pair
     unsigned pblock;
+    int force;           // body force on (params carry it)
 };
 
 hipError_t launch_step(const Launch &g, int mode, bool has_s);

@@ -48,7 +48,11 @@ __device__ __forceinline__ bool block_cell(const Params<CT> &p, int &X, int &Y, 
 
 // One cell of one step.  p: the domain's parameters; A (and B for the push
 // step) the domain's state; pending: the state read needs the Zou-He closure.
-template <class L, class ST, int MODE, bool HAS_S, int NT>
+// XF bit 0: partial bounce-back field; bit 1: body force; bit 2: periodic
+// faces on the select path (a variant of its own, so that walls-only domains
+// keep the leaner kernel): any periodic face in the local even step, which has
+// no neighbour addresses, and periodic Z faces in the odd / push steps.
+template <class L, class ST, int MODE, int XF, int NT>
 __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &p, ST *__restrict__ A,
                                           ST *__restrict__ B, int X, int Y, int Z, int pending) {
     // NT 0: plain accesses.  NT 1: non-temporal loads and stores wherever the
@@ -57,6 +61,9 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
     // cached, since neighbouring wavefronts share their boundary cache lines.
     // NT 2: non-temporal everywhere.  NT 3: as 1 plus non-temporal Z-shifted
     // stores.  NT 4: as 1 plus non-temporal Z-shifted loads.
+    constexpr bool HAS_S = (XF & 1) != 0;
+    constexpr bool FRC = (XF & 2) != 0;
+    constexpr bool PZ = (XF & 4) != 0;
     constexpr bool NTA = (NT >= 1);
     constexpr bool NTZL = (NT == 2) || (NT == 4);
     constexpr bool NTZS = (NT == 2) || (NT == 3);
@@ -69,6 +76,8 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
         if (fl & 1) return;                 // solid cells carry no state
         if (fl & 2) nbm = p.nbm[cell];
     }
+    CT fx = 0, fy = 0, fz = 0;
+    if constexpr (FRC) load_body_force(p, cell, fx, fy, fz);   // issued with the population loads
     const uint32_t e = edge_bits(p, X, Y, Z);
     const uint32_t irr = irregular_mask<L>(e, nbm);
     const int64_t P = p.plane;
@@ -90,7 +99,7 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
         CT rho, ux, uy, uz;
         CT s = 0;
         if constexpr (HAS_S) s = (CT)p.s[cell];
-        collide<L>(h, hp, p, s, HAS_S, rho, ux, uy, uz);
+        collide<L, FRC>(h, hp, p, s, HAS_S, rho, ux, uy, uz, fx, fy, fz);
         ST *W = (MODE == 2) ? B : A;
         unroll<Q>([&](auto I) {
             constexpr int O = opp<L>(I);
@@ -104,19 +113,25 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
         return;
     }
 
-    // Wavefronts whose only non-regular directions meet wall faces or solid
-    // cells (no open or periodic face): halfway bounce-back with the
-    // moving-wall term, chosen per lane by selects.  Same values as the
-    // general path below (fill_value), without the per-direction classification.
+    // Wavefronts whose only non-regular directions meet wall faces, solid
+    // cells or (PZ) periodic faces: halfway bounce-back with the moving-wall
+    // term and periodic images, chosen per lane by selects.  Same values as
+    // the general path below (classify_src, fill_value), without the
+    // per-direction classification; a direction across a wall face and a
+    // periodic face bounces back, as there.
     constexpr uint32_t kFaces = all_face_bits<L>();
-    if (__all((e & kFaces & ~p.wallmask) == 0)) {
+    const uint32_t sel_faces = p.wallmask | (PZ ? (MODE == 0 ? p.permask : (p.permask & kZFaces)) : 0u);
+    if (__all((e & kFaces & ~sel_faces) == 0)) {
+        const ZWrap zw = (PZ && MODE != 0) ? z_wrap(p, e & p.permask) : ZWrap{-1, 1};
+        // wall faces of this cell (without PZ, e's lattice faces are all walls here)
+        const uint32_t we = PZ ? (e & p.wallmask) : e;
         CT h[Q];
         if constexpr (MODE == 1) {
             unroll<Q>([&](auto I) {
                 constexpr int O = opp<L>(I);
                 // x - c_i is across a wall or solid
-                const bool wall = ((e & src_face_bits<L>(I)) | (nbm & (1u << I))) != 0;
-                const ST *nb = pop_ptr<L, O>(A, P, cell - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]));
+                const bool wall = ((we & src_face_bits<L>(I)) | (nbm & (1u << I))) != 0;
+                const ST *nb = pop_ptr<L, O>(A, P, cell + src_off<L, I>(p, zw));
                 const ST *ptr = wall ? pop_ptr<L, I>(A, P, cell) : nb;
                 h[I] = ldp<L, ST, O, (L::c[I][2] == 0) ? NTA : NTZL>(ptr);  // w_O = w_I
             });
@@ -127,18 +142,18 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
         CT rho, ux, uy, uz;
         CT s = 0;
         if constexpr (HAS_S) s = (CT)p.s[cell];
-        collide<L>(h, hp, p, s, HAS_S, rho, ux, uy, uz);
+        collide<L, FRC>(h, hp, p, s, HAS_S, rho, ux, uy, uz, fx, fy, fz);
         ST *W = (MODE == 2) ? B : A;
         unroll<Q>([&](auto I) {
             constexpr int O = opp<L>(I);
             constexpr uint32_t fb = src_face_bits<L>(O);     // faces x + c_i can lie across
             constexpr bool NTW = (MODE == 0 || L::c[I][2] == 0) ? NTA : NTZS;
-            const uint32_t cr = e & fb;
+            const uint32_t cr = we & fb;
             const bool wall = (cr | (nbm & (1u << O))) != 0;  // x + c_i is across a wall or solid
             ST *own = pop_ptr<L, O>(W, P, cell);
             ST *ptr = own;
             if constexpr (MODE != 0)
-                ptr = wall ? own : pop_ptr<L, I>(W, P, cell + ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]));
+                ptr = wall ? own : pop_ptr<L, I>(W, P, cell + src_off<L, O>(p, zw));  // x + c_i = x - c_opp(i)
             CT v = hp[I];
             if (cr && !(cr & p.staticmask)) {
                 // moving wall: the lowest-index face crossed (static walls win);
@@ -180,7 +195,7 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
     CT rho, ux, uy, uz;
     CT s = 0;
     if constexpr (HAS_S) s = (CT)p.s[cell];
-    collide<L>(h, hp, p, s, HAS_S, rho, ux, uy, uz);
+    collide<L, FRC>(h, hp, p, s, HAS_S, rho, ux, uy, uz, fx, fy, fz);
     const bool perim = (e & p.wallmask) != 0;
 
     ST *W = (MODE == 2) ? B : A;
@@ -206,12 +221,12 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
     });
 }
 
-template <class L, class ST, int MODE, bool HAS_S, int NT>
+template <class L, class ST, int MODE, int XF, int NT>
 __global__ void __launch_bounds__(kMaxBlock) k_step(const Params<typename Store<ST>::CT> p, ST *__restrict__ A,
                                                     ST *__restrict__ B) {
     int X, Y, Z;
     if (!block_cell(p, X, Y, Z)) return;
-    step_cell<L, ST, MODE, HAS_S, NT>(p, A, B, X, Y, Z, p.zh_pending);
+    step_cell<L, ST, MODE, XF, NT>(p, A, B, X, Y, Z, p.zh_pending);
 }
 
 }  // namespace lbm
@@ -403,7 +418,9 @@ hipError_t step_t(const Launch &g, int mode, bool has_s) {
     ST *A = static_cast<ST *>(g.A);
     ST *B = static_cast<ST *>(g.B);
     if constexpr (sizeof(ST) == 2) {
-        if ((g.pair == 1 && mode == 0) || (g.pair == 2 && mode != 2)) {
+        // two cells per lane (walls and, in the even step, periodic faces on its
+        // own path); not with a body force
+        if (!g.force && ((g.pair == 1 && mode == 0) || (g.pair == 2 && mode != 2))) {
 #define LBM_PAIR_CASE(M, S) \
     if (mode == M && has_s == S) hipLaunchKernelGGL((k_step_pair<L, ST, M, S>), dim3(g.pgrid), dim3(g.pblock), 0, g.stream, p, A);
             LBM_PAIR_CASE(0, false)
@@ -413,6 +430,41 @@ hipError_t step_t(const Launch &g, int mode, bool has_s) {
 #undef LBM_PAIR_CASE
             return hipGetLastError();
         }
+    }
+    // periodic faces of the lattice's own axes (2-D: not the dummy X axis)
+    const uint32_t per = p.permask & all_face_bits<L>();
+    const bool pz = (mode == 0) ? per != 0 : (per & kZFaces) != 0;
+    if (g.force || pz) {
+        // body force and / or periodic Z faces: the one-cell-per-lane kernel
+        // with the storage type's default memory hints (plain for 2-byte
+        // storage, non-temporal where aligned otherwise)
+        constexpr int NTD = sizeof(ST) == 2 ? 0 : 1;
+        const int xf = (has_s ? 1 : 0) | (g.force ? 2 : 0) | (pz ? 4 : 0);
+#define LBM_XF_CASE(M, X)                                                                                    \
+    if (mode == M && xf == X) {                                                                              \
+        hipLaunchKernelGGL((k_step<L, ST, M, X, NTD>), dim3(g.grid), dim3(g.block), 0, g.stream, p, A, B); \
+        return hipGetLastError();                                                                            \
+    }
+        LBM_XF_CASE(0, 2)
+        LBM_XF_CASE(0, 3)
+        LBM_XF_CASE(0, 4)
+        LBM_XF_CASE(0, 5)
+        LBM_XF_CASE(0, 6)
+        LBM_XF_CASE(0, 7)
+        LBM_XF_CASE(1, 2)
+        LBM_XF_CASE(1, 3)
+        LBM_XF_CASE(1, 4)
+        LBM_XF_CASE(1, 5)
+        LBM_XF_CASE(1, 6)
+        LBM_XF_CASE(1, 7)
+        LBM_XF_CASE(2, 2)
+        LBM_XF_CASE(2, 3)
+        LBM_XF_CASE(2, 4)
+        LBM_XF_CASE(2, 5)
+        LBM_XF_CASE(2, 6)
+        LBM_XF_CASE(2, 7)
+#undef LBM_XF_CASE
+        return hipErrorInvalidValue;
     }
 #define LBM_STEP_CASE(M, S)                                                                            \
     if (mode == M && has_s == S) {                                                                     \

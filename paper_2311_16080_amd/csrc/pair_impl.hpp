@@ -95,9 +95,13 @@ __device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict
     if (p.flags) plain = (p.flags[cell0] | p.flags[cell0 + 1]) == 0;
     const uint32_t e0 = edge_bits(p, X, Y, z0);
     const uint32_t e1 = edge_bits(p, X, Y, z0 + 1);
-    if (!__all(plain && ((e0 | e1) & kFaces & ~p.wallmask) == 0)) {
-        step_cell<L, ST, MODE, HAS_S, 1>(p, A, nullptr, X, Y, z0, pending);
-        step_cell<L, ST, MODE, HAS_S, 1>(p, A, nullptr, X, Y, z0 + 1, pending);
+    // walls, and in the local even step periodic faces too (no neighbour addresses)
+    const uint32_t sel_faces = p.wallmask | (MODE == 0 ? p.permask : 0u);
+    if (!__all(plain && ((e0 | e1) & kFaces & ~sel_faces) == 0)) {
+        // (the even step's select path takes periodic faces too)
+        constexpr int XF = (HAS_S ? 1 : 0) | (MODE == 0 ? 4 : 0);
+        step_cell<L, ST, MODE, XF, 1>(p, A, nullptr, X, Y, z0, pending);
+        step_cell<L, ST, MODE, XF, 1>(p, A, nullptr, X, Y, z0 + 1, pending);
         return;
     }
     const int lane = (int)threadIdx.x & 63;
@@ -152,7 +156,7 @@ __device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict
         const float s0 = HAS_S ? p.s[cell0] : 0.f;
         collide<L>(h, hp, p, s0, HAS_S, r, ux, uy, uz);
         unroll<Q>([&](auto I) {
-            out[I] = hbits<L, ST, I>(wall_term<L, opp<L>(I)>(p, e0 & src_face_bits<L>(opp<L>(I)), hp[I]));
+            out[I] = hbits<L, ST, I>(wall_term<L, opp<L>(I)>(p, e0 & p.wallmask & src_face_bits<L>(opp<L>(I)), hp[I]));
         });
     }
     {
@@ -162,7 +166,7 @@ __device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict
         const float s1 = HAS_S ? p.s[cell0 + 1] : 0.f;
         collide<L>(h, hp, p, s1, HAS_S, r, ux, uy, uz);
         unroll<Q>([&](auto I) {
-            out[I] |= hbits<L, ST, I>(wall_term<L, opp<L>(I)>(p, e1 & src_face_bits<L>(opp<L>(I)), hp[I])) << 16;
+            out[I] |= hbits<L, ST, I>(wall_term<L, opp<L>(I)>(p, e1 & p.wallmask & src_face_bits<L>(opp<L>(I)), hp[I])) << 16;
         });
     }
     // ---- write ------------------------------------------------------------------------

@@ -250,6 +250,7 @@ extern "C" int lbm_backward(lbm_ctx *c, const void *dL_drho, const void *dL_du, 
     if ((dL_drho || dL_du) && dtype != LBM_F64 && dtype != LBM_F32)
         return fail(LBM_EINVAL, "dtype must be LBM_F64 or LBM_F32");
     if (!c->tape) return fail(LBM_ESTATE, "no tape recorded");
+    if (c->force_on) return fail(LBM_EUNSUPPORTED, "the adjoint of the body force is not implemented");
     if (c->tape_recording) lbm_tape_end(c);
     TapeState *T = c->tape;
     if (c->moved_since_tape || c->t != T->t_end) return fail(LBM_ESTATE, "the state moved since the tape ended");

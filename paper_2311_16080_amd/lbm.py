@@ -66,6 +66,7 @@ SIGNATURES = {
     "lbm_time": (_i64, [_vp]),
     "lbm_moments": (_i, [_vp, _vp, _vp, _i, _dp]),
     "lbm_forces": (_i, [_vp, _dp]),
+    "lbm_set_force": (_i, [_vp, _dp, _vp, ctypes.c_double]),
     "lbm_tape_begin": (_i, [_vp, _i, _i]),
     "lbm_tape_end": (_i, [_vp]),
     "lbm_tape_free": (_i, [_vp]),
@@ -267,6 +268,28 @@ class Sim:
         out = (ctypes.c_double * 5)()
         check(lib().lbm_moments(self.h, None, None, F64, out))
         return np.array(list(out))
+
+    def set_force(self, force=None, field=None, eps: float = 1.0):
+        """Body force by the exact-difference method for the following steps:
+        force = uniform part (D values, caller axes) or None; field = device
+        tensor (D, *shape) or None (kept alive here, converted to the compute
+        type); eps scales both.  set_force() switches it off."""
+        torch = _torch()
+        fu = None
+        if force is not None:
+            v = [float(x) for x in force] + [0.0] * 3
+            fu = (ctypes.c_double * 3)(*v[:3])
+        fp = None
+        self._force_field = None
+        if field is not None:
+            if not (isinstance(field, torch.Tensor) and field.is_cuda):
+                raise TypeError("field must be a device tensor of shape (D, *shape)")
+            if tuple(field.shape) != (self.D,) + self.shape:
+                raise ValueError(f"field must have shape {(self.D,) + self.shape}")
+            t = field.to(torch.float64 if self.storage == "f64" else torch.float32).contiguous()
+            self._force_field = t
+            fp = ctypes.c_void_p(t.data_ptr())
+        check(lib().lbm_set_force(self.h, fu, fp, float(eps)))
 
     def forces(self):
         """Momentum-exchange force of the last step: (on solid cells [3], on each

@@ -91,6 +91,14 @@ def spheres3d(storage, steps=12):
                                           (P,), (P,)], steps=steps, storage=storage, init_seed=62, solid=sol, s=s)
 
 
+def zperiodic3d(storage, steps=14):
+    """Walls on x and y (one moving), periodic z, solids: the adjoint's select
+    path with periodic images."""
+    sol = inputs.sphere_obstacles(10, 12, 64, seed=8, rmin=1.5, rmax=3, xlo=3, xhi=7, fraction=0.04)
+    return Case(19, (10, 12, 64), 0.7, [(W,), (W, (0.0, 0.02, 0.01)), (W,), (W,), (P,), (P,)], steps=steps,
+                storage=storage, init_seed=63, solid=sol)
+
+
 ADJ_CASES = {
     "channel2d_pbb_f64_K5": (channel2d("f64"), 5, 0, 1e-10),
     "channel2d_pbb_f64_K24": (channel2d("f64"), 24, 0, 1e-10),
@@ -98,6 +106,8 @@ ADJ_CASES = {
     "cavity3d_f64_K6_oddstart": (cavity3d("f64"), 6, 3, 1e-10),
     "cavity3d_f32_K7": (cavity3d("f32"), 7, 0, 1e-4),
     "spheres3d_d3q27_f64_K4": (spheres3d("f64"), 4, 1, 1e-10),
+    "zperiodic3d_f64_K5": (zperiodic3d("f64"), 5, 1, 1e-10),
+    "zperiodic3d_f32_K7": (zperiodic3d("f32"), 7, 0, 1e-4),
 }
 
 
