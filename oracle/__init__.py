@@ -72,7 +72,7 @@ def lib():
         L.orc_moments.argtypes = [P(_Sim), dp, dp, dp]
         L.orc_sums.argtypes = [P(_Sim), dp, dp]
         L.orc_forces.argtypes = [P(_Sim), dp, dp]
-        L.orc_adjoint_step.argtypes = [P(_Sim), dp, dp, dp, ctypes.c_void_p, dp, dp]
+        L.orc_adjoint_step.argtypes = [P(_Sim), dp, dp, dp, ctypes.c_void_p, dp, dp, ctypes.c_void_p]
         L.orc_adjoint_step.restype = ctypes.c_int
         L.orc_num_threads.restype = ctypes.c_int
         _lib = L
@@ -242,20 +242,25 @@ class Sim:
         lib().orc_zouhe_closure(ctypes.byref(st), int(face), _dp(out))
         return out
 
-    def adjoint_step(self, f_t: np.ndarray, a_next: np.ndarray):
-        """Adjoint of one step at state f_t: returns (a_t, dL/ds, dL/dtau, dL/du_w[6,3])."""
+    def adjoint_step(self, f_t: np.ndarray, a_next: np.ndarray, with_force: bool = False):
+        """Adjoint of one step at state f_t: returns (a_t, dL/ds, dL/dtau, dL/du_w[6,3])
+        (+ dL/dF [*shape, 3] of the body force field if with_force)."""
         st = self._struct()
         a_out = np.zeros_like(a_next)
         dlds = np.zeros(self.N)
         dtau = np.zeros(1)
         duw = np.zeros(18)
+        dldf = np.zeros(self.N * 3)
         rc = lib().orc_adjoint_step(ctypes.byref(st), _dp(np.ascontiguousarray(f_t)),
                                     _dp(np.ascontiguousarray(a_next)), _dp(a_out),
                                     dlds.ctypes.data if self.s is not None else None,
-                                    _dp(dtau), _dp(duw))
+                                    _dp(dtau), _dp(duw), dldf.ctypes.data)
         if rc != 0:
             raise MemoryError("oracle allocation failed")
-        return a_out, dlds.reshape(self.shape), float(dtau[0]), duw.reshape(6, 3)
+        out = (a_out, dlds.reshape(self.shape), float(dtau[0]), duw.reshape(6, 3))
+        if with_force:
+            out = out + (dldf.reshape(self.shape + (3,)),)
+        return out
 
     # --- loss seeds (adjoint inputs) -------------------------------------------
     def seed_from_velocity_grad(self, f: np.ndarray, g_u: np.ndarray, g_rho=None) -> np.ndarray:
@@ -281,17 +286,22 @@ class Sim:
             states.append(f.copy())
         return states
 
-    def adjoint(self, states, a_final):
-        """Run the adjoint back through the trajectory: (a(0), dL/ds, dL/dtau, dL/du_w)."""
+    def adjoint(self, states, a_final, with_force: bool = False):
+        """Run the adjoint back through the trajectory: (a(0), dL/ds, dL/dtau, dL/du_w)
+        (+ dL/dF [*shape, 3] of the body force field if with_force)."""
         a = a_final
         dlds = np.zeros(self.shape)
         dtau = 0.0
         duw = np.zeros((6, 3))
+        dldf = np.zeros(self.shape + (3,))
         for t in range(len(states) - 2, -1, -1):
-            a, ds, dt, du = self.adjoint_step(states[t], a)
+            a, ds, dt, du, df = self.adjoint_step(states[t], a, with_force=True)
             dlds += ds
             dtau += dt
             duw += du
+            dldf += df
+        if with_force:
+            return a, dlds, dtau, duw, dldf
         return a, dlds, dtau, duw
 
 

@@ -506,8 +506,29 @@ static void closure_matrix(const orc_sim *S, int face, double A[27][27], double 
     }
 }
 
+/* Jacobian d feq_i(rho(f), v(f)) / d f_j of the equilibrium at a cell whose
+ * velocity argument is v = (j + F) / rho (F = 0: the cell's own velocity):
+ * d feq_i / d rho at fixed v, plus d feq_i / d v . (c_j - v) / rho. */
+static void feq_jacobian(int q, double rho, const double v[3], double out[27][27])
+{
+    double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    for (int i = 0; i < q; ++i) {
+        const int *c = cvec(q, i);
+        double cv = c[0] * v[0] + c[1] * v[1] + c[2] * v[2];
+        double d_rho = weight(q, i) * (1.0 + 3.0 * cv + 4.5 * cv * cv - 1.5 * vv);
+        double d_v[3];
+        for (int a = 0; a < 3; ++a) d_v[a] = weight(q, i) * rho * (3.0 * c[a] + 9.0 * cv * c[a] - 3.0 * v[a]);
+        for (int j = 0; j < q; ++j) {
+            const int *cj = cvec(q, j);
+            double x = d_rho;
+            for (int a = 0; a < 3; ++a) x += d_v[a] * (cj[a] - v[a]) / rho;
+            out[i][j] = x;
+        }
+    }
+}
+
 int orc_adjoint_step(const orc_sim *S, const double *f, const double *a_next, double *a_out,
-                     double *dLds, double *dLdtau, double *dLduw)
+                     double *dLds, double *dLdtau, double *dLduw, double *dLdF)
 {
     const int q = S->q;
     const long N = (long)S->nx * S->ny * S->nz;
@@ -612,24 +633,20 @@ int orc_adjoint_step(const orc_sim *S, const double *f, const double *a_next, do
         double s = S->s ? S->s[k] : 0.0;
         /* J_ij = d f°_i / d f_j */
         double J[27][27];
-        double dfeq[27][27];
-        for (int i = 0; i < q; ++i) {
-            const int *c = cvec(q, i);
-            double cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
-            double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-            double d_rho = weight(q, i) * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);  /* d feq_i / d rho at fixed u */
-            double d_u[3];
-            for (int a = 0; a < 3; ++a) d_u[a] = weight(q, i) * rho * (3.0 * c[a] + 9.0 * cu * c[a] - 3.0 * u[a]);
-            for (int j = 0; j < q; ++j) {
-                const int *cj = cvec(q, j);
-                double v = d_rho;       /* d rho / d f_j = 1 */
-                for (int a = 0; a < 3; ++a) v += d_u[a] * (cj[a] - u[a]) / rho;   /* d u / d f_j */
-                dfeq[i][j] = v;
-            }
+        double dfeq[27][27], dfeqF[27][27];
+        feq_jacobian(q, rho, u, dfeq);
+        /* body force (exact-difference method): f* gains feq(rho, u') - feq(rho, u),
+         * u' = (j + F) / rho, whose Jacobian is that of feq at u' minus that at u */
+        const double *F = S->edm ? S->edm + (size_t)k * 3 : NULL;
+        double up[3] = {u[0], u[1], u[2]};
+        if (F) {
+            for (int a = 0; a < 3; ++a) up[a] = u[a] + F[a] / rho;
+            feq_jacobian(q, rho, up, dfeqF);
         }
         for (int i = 0; i < q; ++i)
             for (int j = 0; j < q; ++j)
-                J[i][j] = (1.0 - s) * (((i == j) ? 1.0 : 0.0) * (1.0 - omega) + omega * dfeq[i][j])
+                J[i][j] = (1.0 - s) * (((i == j) ? 1.0 : 0.0) * (1.0 - omega) + omega * dfeq[i][j]
+                                       + (F ? dfeqF[i][j] - dfeq[i][j] : 0.0))
                           + s * ((j == opposite(q, i)) ? 1.0 : 0.0);
         double *ao = a_out + (size_t)k * q;
         for (int j = 0; j < q; ++j) {
@@ -642,7 +659,19 @@ int orc_adjoint_step(const orc_sim *S, const double *f, const double *a_next, do
         }
         /* parameters */
         double fstar[27];
-        for (int i = 0; i < q; ++i) fstar[i] = fk[i] - omega * (fk[i] - feq_i(q, i, rho, u));
+        for (int i = 0; i < q; ++i) {
+            fstar[i] = fk[i] - omega * (fk[i] - feq_i(q, i, rho, u));
+            if (F) fstar[i] += feq_i(q, i, rho, up) - feq_i(q, i, rho, u);
+        }
+        /* d f°_i / d F = (1-s) d feq_i(rho, u') / d u' / rho */
+        if (dLdF && F) {
+            for (int i = 0; i < q; ++i) {
+                const int *c = cvec(q, i);
+                double cv = c[0] * up[0] + c[1] * up[1] + c[2] * up[2];
+                for (int a = 0; a < 3; ++a)
+                    dLdF[(size_t)k * 3 + a] += ap[i] * (1.0 - s) * weight(q, i) * (3.0 * c[a] + 9.0 * cv * c[a] - 3.0 * up[a]);
+            }
+        }
         if (dLds && S->s) {
             double g = 0.0;
             for (int i = 0; i < q; ++i) g += ap[i] * (fk[opposite(q, i)] - fstar[i]);

@@ -138,3 +138,106 @@ def test_poiseuille_edm_magic_tau_exact(q):
         errs[tau] = np.max(np.abs(u[0, :, 0, 0] + Fx / (2 * rho[0, :, 0]) - ex)) / ex.max()
     assert errs[0.5 + np.sqrt(3) / 4] < 1e-10
     assert 1e-3 < errs[0.8] < 3e-2
+
+
+# ---- adjoint of the body force ------------------------------------------------
+# Pinned by linear algebra on the forward oracle alone: the dot-product identity
+# <w, J v> = <J^T w, v> of one step with the force on, and central differences
+# of a velocity loss through several steps with respect to force-field entries,
+# the uniform force, s and tau.
+from test_oracle_adjoint import _scene, _step   # noqa: E402
+
+
+def _with_force(S, rng, amp=3e-3):
+    F = np.zeros(S.shape + (3,))
+    D = 2 if S.q == 9 else 3
+    F[..., :D] = amp * rng.standard_normal(S.shape + (D,))
+    S.edm = F
+    return F
+
+
+@pytest.mark.parametrize("q", [9, 19, 27])
+@pytest.mark.parametrize("kind", ["cavity", "channel", "pressure"])
+def test_edm_dot_product_identity(q, kind):
+    rng = np.random.default_rng(300 + q)
+    S, f = _scene(q, kind, rng)
+    _with_force(S, rng)
+    fluid = ~S.solid.astype(bool)
+    v = rng.standard_normal(f.shape) * fluid[..., None]
+    w = rng.standard_normal(f.shape) * fluid[..., None]
+    eps = 1e-6
+    Jv = (_step(S, f + eps * v) - _step(S, f - eps * v)) / (2 * eps)
+    JTw, _, _, _ = S.adjoint_step(f, w)
+    lhs = np.sum(w * Jv)
+    rhs = np.sum(JTw * v)
+    assert abs(lhs - rhs) <= 1e-7 * max(abs(lhs), 1.0)
+    # and the force term is really in the transpose: without it the identity fails
+    S.edm = None
+    JTw0, _, _, _ = S.adjoint_step(f, w)
+    assert abs(np.sum(JTw0 * v) - lhs) > 1e-6 * max(abs(lhs), 1.0)
+
+
+def _edm_loss(S, f0, nsteps, target):
+    f = f0.copy()
+    S.run(f, nsteps)
+    _, u = S.moments(f)
+    fluid = ~S.solid.astype(bool)
+    return np.sum(((u - target) * fluid[..., None]) ** 2)
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_edm_gradients_match_finite_differences(q):
+    rng = np.random.default_rng(320 + q)
+    S, f0 = _scene(q, "channel", rng)
+    F = _with_force(S, rng)
+    nsteps = 6
+    target = 0.02 * rng.standard_normal(S.shape + (3,))
+    states = S.trajectory(f0, nsteps)
+    _, u = S.moments(states[-1])
+    fluid = ~S.solid.astype(bool)
+    diff = (u - target) * fluid[..., None]
+    L = np.sum(diff ** 2)
+    seed = S.seed_from_velocity_grad(states[-1], 2 * diff)
+    _, dlds, dtau, _, dldf = S.adjoint(states, seed, with_force=True)
+    h = 1e-6
+    D = 2 if q == 9 else 3
+    cells = [tuple(c) for c in np.argwhere(fluid)[::4]]
+    for cell in cells:
+        for a in range(D):
+            Fp, Fm = F.copy(), F.copy()
+            Fp[cell + (a,)] += h
+            Fm[cell + (a,)] -= h
+            S.edm = Fp
+            Lp = _edm_loss(S, f0, nsteps, target)
+            S.edm = Fm
+            Lm = _edm_loss(S, f0, nsteps, target)
+            fd = (Lp - Lm) / (2 * h)
+            assert abs(fd - dldf[cell + (a,)]) <= 1e-6 * max(abs(fd), 1e-3 * abs(L)), (cell, a)
+    # uniform part: the sum of the per-cell gradients over fluid cells
+    for a in range(D):
+        S.edm = F + h * np.eye(3)[a]
+        Lp = _edm_loss(S, f0, nsteps, target)
+        S.edm = F - h * np.eye(3)[a]
+        Lm = _edm_loss(S, f0, nsteps, target)
+        fd = (Lp - Lm) / (2 * h)
+        g = dldf[..., a][fluid].sum()
+        assert abs(fd - g) <= 1e-6 * max(abs(fd), 1e-3 * abs(L))
+    S.edm = F
+    # s and tau with the force on (the force enters before the mix)
+    base_s = S.s.copy()
+    for cell in cells[:6]:
+        S.s = base_s.copy(); S.s[cell] += h
+        Lp = _edm_loss(S, f0, nsteps, target)
+        S.s = base_s.copy(); S.s[cell] -= h
+        Lm = _edm_loss(S, f0, nsteps, target)
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - dlds[cell]) <= 1e-6 * max(abs(fd), 1e-3 * abs(L)), cell
+    S.s = base_s
+    tau0 = S.tau
+    S.tau = tau0 + h
+    Lp = _edm_loss(S, f0, nsteps, target)
+    S.tau = tau0 - h
+    Lm = _edm_loss(S, f0, nsteps, target)
+    S.tau = tau0
+    fd = (Lp - Lm) / (2 * h)
+    assert abs(fd - dtau) <= 1e-6 * abs(fd)
