@@ -257,9 +257,11 @@ int lbm_forces(lbm_ctx *ctx, double *out);
  *           or the context destroyed, and may update it between steps on the
  *           context's stream.
  *   eps   : scale on both parts (the paper's epsilon; 1 for a plain force).
- * A zero force with no field (or eps = 0) switches the force off.  LBM_EINVAL
- * for a non-finite force or eps; LBM_EUNSUPPORTED on batch contexts; while a
- * force is on, lbm_backward returns LBM_EUNSUPPORTED.  Drops a captured graph.
+ * A zero force with no field (or eps = 0) switches the force off.  The taped
+ * adjoint (lbm_backward, lbm_backward_force) differentiates through the force
+ * as set when it runs: keep it unchanged over the taped steps.  LBM_EINVAL for
+ * a non-finite force or eps; LBM_EUNSUPPORTED on batch contexts.  Drops a
+ * captured graph.
  */
 int lbm_set_force(lbm_ctx *ctx, const double *force, const void *field, double eps);
 
@@ -294,6 +296,24 @@ int lbm_tape_free(lbm_ctx *ctx);
  */
 int lbm_backward(lbm_ctx *ctx, const void *dL_drho, const void *dL_du, int dtype,
                  float *dL_ds, double *dL_dtau, double *dL_duw);
+
+/*
+ * lbm_backward plus the gradients with respect to the body force of
+ * lbm_set_force (Sec. 6.2: training a corrector force through unrolled steps):
+ *   dL_dfield : device pointer or NULL: D x N values of `dtype` (component-
+ *               major, caller axes, the field's layout), overwritten with
+ *               dL/dfield(x) = eps sum_t sum_i lambda_i dfeq_i/dm at
+ *               m = j + eps F (lambda: the adjoint of the post-collision values);
+ *   dL_dforce : host double[D] or NULL: gradient with respect to the uniform
+ *               part, the FP64 fixed-order sum of dL_dfield over the cells.
+ * eps is that of the last lbm_set_force (1 if none); with no force set the
+ * gradients are taken at F = 0.  The adjoint accumulates dL/dF in the compute
+ * type (FP64 storage: FP64, otherwise FP32).  LBM_EUNSUPPORTED on batch
+ * contexts when either output is requested; otherwise as lbm_backward.
+ */
+int lbm_backward_force(lbm_ctx *ctx, const void *dL_drho, const void *dL_du, int dtype,
+                       float *dL_ds, double *dL_dtau, double *dL_duw,
+                       void *dL_dfield, double *dL_dforce);
 
 /*
  * Capture n_steps >= 1 steps into a HIP graph that lbm_graph_launch replays

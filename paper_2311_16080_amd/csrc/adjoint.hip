@@ -16,7 +16,11 @@
 //   outflow : the equilibrium fills depend on u(x, t): a_j += e . (c_j - u) / rho;
 //   Zou-He  : the unknowns are affine in the knowns at the same cell, so their
 //             adjoints are folded into the knowns' (closure transpose);
-//   walls   : dL/du_w += a_i(x) 6 w_i rho0 c_i for populations bounced off a moving wall.
+//   walls   : dL/du_w += a_i(x) 6 w_i rho0 c_i for populations bounced off a moving wall;
+//   force   : the exact-difference term G_i = feq_i(rho, (j + F)/rho) - feq_i(rho, j/rho)
+//             (inside the (1 - s) factor) adds a_j += A_F + c_j . V_F with
+//             A_F = sum lambda_i dG_i/drho, V_F = sum lambda_i dG_i/dj, and
+//             dL/dF(x) += sum lambda_i dfeq_i/dm at m = j + F (= V + V_F).
 // The step kernel adds the block's FP64 sum of sum_i lambda_i (f_i - feq_i)
 // into the block's own accumulator row (times 1/tau^2 on the host); a second,
 // small kernel over the cells of the moving-wall faces adds the wall-velocity
@@ -107,14 +111,18 @@ __device__ __forceinline__ void zouhe_transpose(CT *a, const Params<CT> &p, int 
 
 // Adjoint step at time t for one fluid cell.  F: natural state f(t) (storage
 // type ST); An: a(t+1) (CT planes); Ao: a(t).  ds: per-cell dL/ds accumulator
-// (HAS_S).  Returns sum_i lambda_i (f_i - feq_i), the cell's dL/dtau * tau^2.
-template <class L, class ST, bool HAS_S>
+// (HAS_S).  FRC: the body force is on; dF (or null): per-cell dL/dF
+// accumulators, 3 planes of N (internal axes).  Returns
+// sum_i lambda_i (f_i - feq_i), the cell's dL/dtau * tau^2.
+template <class L, class ST, bool HAS_S, bool FRC = false>
 __device__ __forceinline__ typename Store<ST>::CT adjoint_cell(const Params<typename Store<ST>::CT> &p,
                                                                const ST *__restrict__ F,
                                                                const typename Store<ST>::CT *__restrict__ An,
                                                                typename Store<ST>::CT *__restrict__ Ao,
                                                                typename Store<ST>::CT *__restrict__ ds, int X, int Y,
-                                                               int Z, int pending) {
+                                                               int Z, int pending,
+                                                               typename Store<ST>::CT *__restrict__ dF = nullptr,
+                                                               int64_t N = 0) {
     using CT = typename Store<ST>::CT;
     constexpr int Q = L::Q;
     const int64_t P = p.plane;
@@ -203,15 +211,34 @@ __device__ __forceinline__ typename Store<ST>::CT adjoint_cell(const Params<type
 
     CT s = 0;
     if constexpr (HAS_S) s = (CT)p.s[cell];
+    // body force: du = F / rho, bq = 1.5 du . (u + u'), u' = u + du
+    CT dx = 0, dy = 0, dz = 0, bq = 0;
+    if constexpr (FRC) {
+        CT fx, fy, fz;
+        load_body_force(p, cell, fx, fy, fz);
+        dx = fx * inv;
+        dy = fy * inv;
+        dz = fz * inv;
+        bq = (CT)1.5 * (dx * ((CT)2 * ux + dx) + dy * ((CT)2 * uy + dy) + dz * ((CT)2 * uz + dz));
+    }
     // lambda = (1 - s) b (partial bounce-back), dL/ds, dL/dtau * tau^2, A, V
+    // (force: AFs = sum w lambda cd (9 cu + 4.5 cd), T3 = sum w lambda cd c, cd = c . du)
     CT gs = 0, gt = 0, Aa = 0, Vx = 0, Vy = 0, Vz = 0, Sw = 0;
+    CT AFs = 0, Tx = 0, Ty = 0, Tz = 0;
     unroll<Q>([&](auto I) {
         constexpr int O = opp<L>(I);
         const CT lam = HAS_S ? ((CT)1 - s) * b[I] : b[I];
         const CT neq = h[I] - heq<L, I>(drho, rho, ux, uy, uz, usq15);
-        if constexpr (HAS_S) gs += b[I] * (h[O] - (h[I] - om * neq));
-        gt += lam * neq;
         const CT cu = (CT)L::c[I][0] * ux + (CT)L::c[I][1] * uy + (CT)L::c[I][2] * uz;
+        CT cd = 0;
+        if constexpr (FRC) cd = (CT)L::c[I][0] * dx + (CT)L::c[I][1] * dy + (CT)L::c[I][2] * dz;
+        if constexpr (HAS_S) {
+            CT post = h[I] - om * neq;
+            if constexpr (FRC)
+                post += (CT)weight<L>(I) * rho * ((CT)3 * cd + (CT)4.5 * cd * ((CT)2 * cu + cd) - bq);
+            gs += b[I] * (h[O] - post);
+        }
+        gt += lam * neq;
         const CT wl = (CT)weight<L>(I) * lam;
         Aa += wl * ((CT)1 - (CT)4.5 * cu * cu + (CT)1.5 * uu);
         Sw += wl;
@@ -219,6 +246,13 @@ __device__ __forceinline__ typename Store<ST>::CT adjoint_cell(const Params<type
         if constexpr (L::c[I][0] != 0) Vx += wl * t9 * (CT)L::c[I][0];
         if constexpr (L::c[I][1] != 0) Vy += wl * t9 * (CT)L::c[I][1];
         if constexpr (L::c[I][2] != 0) Vz += wl * t9 * (CT)L::c[I][2];
+        if constexpr (FRC) {
+            const CT wcd = wl * cd;
+            AFs += wcd * ((CT)9 * cu + (CT)4.5 * cd);
+            if constexpr (L::c[I][0] != 0) Tx += wcd * (CT)L::c[I][0];
+            if constexpr (L::c[I][1] != 0) Ty += wcd * (CT)L::c[I][1];
+            if constexpr (L::c[I][2] != 0) Tz += wcd * (CT)L::c[I][2];
+        }
     });
     if constexpr (HAS_S) {
         if (ds) ds[cell] += gs;
@@ -226,6 +260,19 @@ __device__ __forceinline__ typename Store<ST>::CT adjoint_cell(const Params<type
     Vx -= (CT)3 * ux * Sw;
     Vy -= (CT)3 * uy * Sw;
     Vz -= (CT)3 * uz * Sw;
+    // force: A_F = bq Sw - AFs, V_F = 9 T3 - 3 du Sw; dL/dF = V + V_F
+    CT AF = 0, VFx = 0, VFy = 0, VFz = 0;
+    if constexpr (FRC) {
+        AF = bq * Sw - AFs;
+        VFx = (CT)9 * Tx - (CT)3 * dx * Sw;
+        VFy = (CT)9 * Ty - (CT)3 * dy * Sw;
+        VFz = (CT)9 * Tz - (CT)3 * dz * Sw;
+        if (dF) {
+            dF[cell] += Vx + VFx;
+            dF[N + cell] += Vy + VFy;
+            dF[2 * N + cell] += Vz + VFz;
+        }
+    }
     const CT eu = ex * ux + ey * uy + ez * uz;
     CT a[Q];
     unroll<Q>([&](auto J) {
@@ -234,6 +281,7 @@ __device__ __forceinline__ typename Store<ST>::CT adjoint_cell(const Params<type
         const CT cV = (CT)L::c[J][0] * Vx + (CT)L::c[J][1] * Vy + (CT)L::c[J][2] * Vz;
         const CT ce = (CT)L::c[J][0] * ex + (CT)L::c[J][1] * ey + (CT)L::c[J][2] * ez;
         CT v = ((CT)1 - om) * lam + om * (Aa + cV) + (ce - eu) * inv;
+        if constexpr (FRC) v += AF + (CT)L::c[J][0] * VFx + (CT)L::c[J][1] * VFy + (CT)L::c[J][2] * VFz;
         if constexpr (HAS_S) v += s * b[O];
         a[J] = v;
     });
@@ -272,15 +320,44 @@ struct AdjWaves {
 #define LBM_ADJ_ATTR __attribute__((amdgpu_waves_per_eu(AdjWaves<L, ST>::value)))
 #endif
 
-template <class L, class ST, bool HAS_S>
+template <class L, class ST, bool HAS_S, bool FRC>
 __global__ void __launch_bounds__(kMaxBlock) LBM_ADJ_ATTR k_adjoint(const Params<typename Store<ST>::CT> p, const ST *__restrict__ F,
                                                        const typename Store<ST>::CT *__restrict__ An,
                                                        typename Store<ST>::CT *__restrict__ Ao,
-                                                       typename Store<ST>::CT *__restrict__ ds, double *__restrict__ acc) {
+                                                       typename Store<ST>::CT *__restrict__ ds, double *__restrict__ acc,
+                                                       typename Store<ST>::CT *__restrict__ dF, int64_t N) {
     int X, Y, Z;
     double g = 0.0;
-    if (adj_block_cell(p, X, Y, Z)) g = (double)adjoint_cell<L, ST, HAS_S>(p, F, An, Ao, ds, X, Y, Z, p.zh_pending);
+    if (adj_block_cell(p, X, Y, Z))
+        g = (double)adjoint_cell<L, ST, HAS_S, FRC>(p, F, An, Ao, ds, X, Y, Z, p.zh_pending, dF, N);
     block_add(g, acc, blockIdx.x);
+}
+
+// dL/dF out: out[a N + cell] = eps dF[(a + off) N + cell] (caller axis a < D;
+// off = 1 for 2-D, whose caller axes x, y are the internal Y, Z), and one row
+// of D FP64 block sums per workgroup (for the uniform force's gradient).
+template <class CT, class OT>
+__global__ void __launch_bounds__(256) k_df_out(const CT *__restrict__ dF, OT *__restrict__ out, int64_t N, int D,
+                                                int off, double eps, double *__restrict__ rows) {
+    __shared__ double red[3][4];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+    for (int a = 0; a < D; ++a) {
+        double v = 0.0;
+        if (i < N) {
+            v = eps * (double)dF[(int64_t)(a + off) * N + i];
+            if (out) out[(int64_t)a * N + i] = (OT)v;
+        }
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) red[a][wv] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < D) {
+        const int nw = ((int)blockDim.x + 63) / 64;
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += red[threadIdx.x][w];
+        rows[(int64_t)blockIdx.x * D + threadIdx.x] = t;
+    }
 }
 
 // Wall-velocity gradient of one step: tile k covers `blockDim.x` cells of
@@ -522,13 +599,17 @@ static hipError_t adj_dispatch(const AdjLaunch &g) {
             if (batch)
                 hipLaunchKernelGGL((k_adjoint_batch<L, ST>), grid, block, 0, g.stream, bd, static_cast<const ST *>(g.F),
                                    static_cast<const CT *>(g.An), static_cast<CT *>(g.Ao), g.acc, g.pending);
-            else if (g.ds)
-                hipLaunchKernelGGL((k_adjoint<L, ST, true>), grid, block, 0, g.stream, p, static_cast<const ST *>(g.F),
-                                   static_cast<const CT *>(g.An), static_cast<CT *>(g.Ao), static_cast<CT *>(g.ds),
-                                   g.acc);
-            else
-                hipLaunchKernelGGL((k_adjoint<L, ST, false>), grid, block, 0, g.stream, p, static_cast<const ST *>(g.F),
-                                   static_cast<const CT *>(g.An), static_cast<CT *>(g.Ao), nullptr, g.acc);
+            else {
+#define LBM_ADJ(S, FR)                                                                                             \
+    hipLaunchKernelGGL((k_adjoint<L, ST, S, FR>), grid, block, 0, g.stream, p, static_cast<const ST *>(g.F),       \
+                       static_cast<const CT *>(g.An), static_cast<CT *>(g.Ao), static_cast<CT *>(g.ds), g.acc,    \
+                       static_cast<CT *>(g.dF), g.N);
+                if (g.ds && g.force) LBM_ADJ(true, true)
+                else if (g.ds) LBM_ADJ(true, false)
+                else if (g.force) LBM_ADJ(false, true)
+                else LBM_ADJ(false, false)
+#undef LBM_ADJ
+            }
             break;
         case ADJ_WALLS:
             if (g.walls.n == 0) break;
@@ -568,6 +649,20 @@ static hipError_t adj_dispatch(const AdjLaunch &g) {
             const unsigned nb = (unsigned)((g.N + 255) / 256);
             hipLaunchKernelGGL((k_to_float<CT>), dim3(nb), dim3(256), 0, g.stream, static_cast<const CT *>(g.ds),
                                g.ds_out, g.N);
+            break;
+        }
+        case ADJ_DF_OUT: {
+            const unsigned nb = (unsigned)((g.N + 255) / 256);
+            const int D = (g.lattice == LAT_D2Q9) ? 2 : 3;
+            const int off = (D == 2) ? 1 : 0;
+            if (g.in_f64)
+                hipLaunchKernelGGL((k_df_out<CT, double>), dim3(nb), dim3(256), 0, g.stream,
+                                   static_cast<const CT *>(g.dF), static_cast<double *>(g.df_out), g.N, D, off, g.eps,
+                                   g.acc);
+            else
+                hipLaunchKernelGGL((k_df_out<CT, float>), dim3(nb), dim3(256), 0, g.stream,
+                                   static_cast<const CT *>(g.dF), static_cast<float *>(g.df_out), g.N, D, off, g.eps,
+                                   g.acc);
             break;
         }
         default: return hipErrorInvalidValue;

@@ -4,7 +4,7 @@
 
 namespace lbm {
 
-enum : int { ADJ_STEP = 0, ADJ_SEED = 1, ADJ_MATERIALIZE = 2, ADJ_DS_OUT = 3, ADJ_WALLS = 4 };
+enum : int { ADJ_STEP = 0, ADJ_SEED = 1, ADJ_MATERIALIZE = 2, ADJ_DS_OUT = 3, ADJ_WALLS = 4, ADJ_DF_OUT = 5 };
 
 // Tiles of moving-wall face cells: tile k = cells [start[k], start[k] + block)
 // (face-local order) of face face[k] of domain dom[k].
@@ -35,6 +35,10 @@ struct AdjLaunch {
     double *accw;           // 3 rows per wall tile
     WallTiles walls;
     const void *grho, *gu;
+    int force;              // ADJ_STEP: the body force is on
+    void *dF;               // dL/dF accumulators (CT, 3 planes of N, internal axes) or null
+    void *df_out;           // ADJ_DF_OUT destination (D planes of N, caller axes, in_f64 ? double : float) or null
+    double eps;             // ADJ_DF_OUT: scale of the force (rows in acc: D FP64 sums per 256 cells)
     int in_f64;
     int pending;            // batch: the state read needs the Zou-He closure
     int64_t N;

@@ -36,6 +36,9 @@ struct TapeState {
     int *wt = nullptr;        // device: dom[nwt], face[nwt], start[nwt]
     int nwt = 0;
     double *accw = nullptr;   // 3 rows per wall tile
+    // body-force gradient (allocated by the first backward that asks for it)
+    void *dF = nullptr;       // 3 planes of N compute-type accumulators
+    double *frows = nullptr;  // D FP64 sums per 256 cells, then D totals
 };
 }  // namespace lbm
 
@@ -55,6 +58,8 @@ void lbm::tape_release(lbm_ctx *c) {
         dev_free((void *&)T->acc);
         dev_free((void *&)T->wt);
         dev_free((void *&)T->accw);
+        dev_free(T->dF);
+        dev_free((void *&)T->frows);
         delete T;
     }
     c->tape = nullptr;
@@ -244,17 +249,28 @@ struct Backward {
 };
 }  // namespace
 
-extern "C" int lbm_backward(lbm_ctx *c, const void *dL_drho, const void *dL_du, int dtype, float *dL_ds,
-                            double *dL_dtau, double *dL_duw) {
+static int backward_impl(lbm_ctx *c, const void *dL_drho, const void *dL_du, int dtype, float *dL_ds,
+                         double *dL_dtau, double *dL_duw, void *dL_dfield, double *dL_dforce) {
     if (!c) return fail(LBM_EINVAL, "null context");
-    if ((dL_drho || dL_du) && dtype != LBM_F64 && dtype != LBM_F32)
+    const bool want_force = dL_dfield || dL_dforce;
+    if ((dL_drho || dL_du || dL_dfield) && dtype != LBM_F64 && dtype != LBM_F32)
         return fail(LBM_EINVAL, "dtype must be LBM_F64 or LBM_F32");
     if (!c->tape) return fail(LBM_ESTATE, "no tape recorded");
-    if (c->force_on) return fail(LBM_EUNSUPPORTED, "the adjoint of the body force is not implemented");
+    if (want_force && c->batch) return fail(LBM_EUNSUPPORTED, "body forces are not supported on batch contexts");
     if (c->tape_recording) lbm_tape_end(c);
     TapeState *T = c->tape;
     if (c->moved_since_tape || c->t != T->t_end) return fail(LBM_ESTATE, "the state moved since the tape ended");
     (void)hipSetDevice(c->device);
+    const int64_t fblocks = (c->N + 255) / 256;
+    if (want_force && !T->dF) {
+        int rc = dev_alloc(&T->dF, (size_t)3 * (size_t)c->N * compute_size(c), "dL/dF accumulator");
+        if (!rc) rc = dev_alloc((void **)&T->frows, ((size_t)fblocks + 1) * 3 * sizeof(double), "dL/dF sums");
+        if (rc) {
+            dev_free(T->dF);
+            dev_free((void *&)T->frows);
+            return rc;
+        }
+    }
     refresh_params(c);
     Backward bw{c, T};
     if (c->batch) bw.bl = batch_launch_of(c);
@@ -278,6 +294,7 @@ extern "C" int lbm_backward(lbm_ctx *c, const void *dL_drho, const void *dL_du, 
     if (e == hipSuccess) e = hipMemsetAsync(T->acc, 0, (size_t)T->rows * sizeof(double), c->stream);
     if (e == hipSuccess && T->nwt) e = hipMemsetAsync(T->accw, 0, (size_t)3 * T->nwt * sizeof(double), c->stream);
     if (e == hipSuccess && T->ds) e = hipMemsetAsync(T->ds, 0, (size_t)c->N * compute_size(c), c->stream);
+    if (e == hipSuccess && want_force) e = hipMemsetAsync(T->dF, 0, (size_t)3 * (size_t)c->N * compute_size(c), c->stream);
 
     const int nseg = (int)((n + T->K - 1) / T->K);
     std::vector<const void *> S((size_t)T->K);
@@ -304,6 +321,8 @@ extern "C" int lbm_backward(lbm_ctx *c, const void *dL_drho, const void *dL_du, 
             g.Ao = T->abuf[1 - cur];
             g.ds = T->ds;
             g.acc = T->acc;
+            g.force = (c->force_on || want_force) ? 1 : 0;
+            g.dF = want_force ? T->dF : nullptr;
             e = launch_adjoint(g);
             cur = 1 - cur;
         }
@@ -320,6 +339,22 @@ extern "C" int lbm_backward(lbm_ctx *c, const void *dL_drho, const void *dL_du, 
             e = hipMemsetAsync(dL_ds, 0, (size_t)c->N * sizeof(float), c->stream);
         }
     }
+    // body-force gradient: the field's (scaled by eps), and its fixed-order sum
+    double fsum[3] = {0.0, 0.0, 0.0};
+    if (e == hipSuccess && want_force) {
+        AdjLaunch g = bw.launch(ADJ_DF_OUT, c->t);
+        g.dF = T->dF;
+        g.df_out = dL_dfield;
+        g.in_f64 = dtype == LBM_F64;
+        g.eps = c->force_eps;
+        g.acc = T->frows;
+        e = launch_adjoint(g);
+        if (e == hipSuccess)
+            e = launch_rows_reduce(T->frows, fblocks, c->D, T->frows + (size_t)fblocks * 3, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(fsum, T->frows + (size_t)fblocks * 3, (size_t)c->D * sizeof(double),
+                               hipMemcpyDeviceToHost, c->stream);
+    }
     // FP64 row sums, added on the host in a fixed order
     std::vector<double> acc((size_t)T->rows), accw((size_t)3 * T->nwt);
     if (e == hipSuccess) e = hipMemcpyAsync(acc.data(), T->acc, acc.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
@@ -327,6 +362,8 @@ extern "C" int lbm_backward(lbm_ctx *c, const void *dL_drho, const void *dL_du, 
         e = hipMemcpyAsync(accw.data(), T->accw, accw.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "lbm_backward");
+    if (dL_dforce)
+        for (int a = 0; a < c->D; ++a) dL_dforce[a] = fsum[a];
     const int nd = c->ndomains;
     std::vector<double> dtau((size_t)nd, 0.0), duw((size_t)nd * 18, 0.0);   // duw in internal faces / axes
     if (c->batch) {
@@ -358,4 +395,14 @@ extern "C" int lbm_backward(lbm_ctx *c, const void *dL_drho, const void *dL_du, 
         }
     }
     return LBM_OK;
+}
+
+extern "C" int lbm_backward(lbm_ctx *c, const void *dL_drho, const void *dL_du, int dtype, float *dL_ds,
+                            double *dL_dtau, double *dL_duw) {
+    return backward_impl(c, dL_drho, dL_du, dtype, dL_ds, dL_dtau, dL_duw, nullptr, nullptr);
+}
+
+extern "C" int lbm_backward_force(lbm_ctx *c, const void *dL_drho, const void *dL_du, int dtype, float *dL_ds,
+                                  double *dL_dtau, double *dL_duw, void *dL_dfield, double *dL_dforce) {
+    return backward_impl(c, dL_drho, dL_du, dtype, dL_ds, dL_dtau, dL_duw, dL_dfield, dL_dforce);
 }

@@ -71,6 +71,7 @@ SIGNATURES = {
     "lbm_tape_end": (_i, [_vp]),
     "lbm_tape_free": (_i, [_vp]),
     "lbm_backward": (_i, [_vp, _vp, _vp, _i, _vp, _dp, _dp]),
+    "lbm_backward_force": (_i, [_vp, _vp, _vp, _i, _vp, _dp, _dp, _vp, _dp]),
     "lbm_capture_graph": (_i, [_vp, _i]),
     "lbm_graph_launch": (_i, [_vp]),
     "lbm_state_bytes": (_sz, [_vp]),
@@ -347,6 +348,26 @@ class Sim:
         check(lib().lbm_backward(self.h, _ptr(dL_drho), _ptr(dL_du), dt, _ptr(ds), dtau, duw))
         return ds, np.array(list(dtau)), np.array(list(duw)).reshape(n_domains, 6, 3)
 
+    def backward_force(self, dL_drho=None, dL_du=None, want_s: bool = False):
+        """backward() plus the body-force gradients: returns (dL_ds or None,
+        dL_dtau [1], dL_duw [1, 6, 3], dL_dfield tensor (D, *shape), dL_dforce [D])."""
+        torch = _torch()
+        dt = F64 if self.storage == "f64" else F32
+        tdt = torch.float64 if dt == F64 else torch.float32
+        if dL_drho is not None:
+            dL_drho = dL_drho.to(tdt).contiguous()
+        if dL_du is not None:
+            dL_du = dL_du.to(tdt).contiguous()
+        ds = torch.zeros(self.shape, dtype=torch.float32, device="cuda") if want_s else None
+        dfield = torch.empty((self.D,) + self.shape, dtype=tdt, device="cuda")
+        dtau = (ctypes.c_double * 1)()
+        duw = (ctypes.c_double * 18)()
+        dforce = (ctypes.c_double * 3)()
+        check(lib().lbm_backward_force(self.h, _ptr(dL_drho), _ptr(dL_du), dt, _ptr(ds), dtau, duw,
+                                       _ptr(dfield), dforce))
+        return (ds, np.array(list(dtau)), np.array(list(duw)).reshape(1, 6, 3), dfield,
+                np.array(list(dforce))[: self.D])
+
 
 def copy_probe(dst, src, nbytes: int):
     torch = _torch()
@@ -366,10 +387,13 @@ class _Rollout:
 
             class LbmRollout(torch.autograd.Function):
                 @staticmethod
-                def forward(ctx, s, tau, sim, nsteps, K, rho0, u0):
+                def forward(ctx, s, tau, sim, nsteps, K, rho0, u0, field=None, eps=1.0):
                     sim.set_params(tau=float(tau))
                     if s is not None:
                         sim.set_solid_fraction(s.detach())
+                    if field is not None:
+                        sim.set_force(None, field.detach(), eps)
+                    ctx.has_field = field is not None
                     sim.init_equilibrium(rho0, u0)
                     sim.tape_begin(K, max(int(nsteps), 1))
                     sim.step(int(nsteps))
@@ -383,23 +407,28 @@ class _Rollout:
                 @staticmethod
                 def backward(ctx, g_rho, g_u):
                     sim = ctx.sim
-                    ds, dtau, _ = sim.backward(g_rho, g_u, want_s=ctx.has_s)
+                    g_field = None
+                    if ctx.has_field:
+                        ds, dtau, _, g_field, _ = sim.backward_force(g_rho, g_u, want_s=ctx.has_s)
+                    else:
+                        ds, dtau, _ = sim.backward(g_rho, g_u, want_s=ctx.has_s)
                     g_tau = torch.tensor(dtau[0], dtype=ctx.tau_dtype)
-                    return ds, g_tau, None, None, None, None, None
+                    return ds, g_tau, None, None, None, None, None, g_field, None
 
             cls.fn = LbmRollout
         return cls.fn
 
 
-def rollout(sim: "Sim", nsteps: int, K: int, s=None, tau=None, rho0=None, u0=None):
+def rollout(sim: "Sim", nsteps: int, K: int, s=None, tau=None, rho0=None, u0=None, field=None, eps: float = 1.0):
     """Differentiable run: init at equilibrium(rho0, u0), `nsteps` steps with a
     checkpoint every K steps, returns (rho, u) of the final state.  Gradients
-    flow to the solid fraction `s` (device tensor) and `tau` (0-d tensor)
-    through the library's adjoint (lbm_backward)."""
+    flow to the solid fraction `s` (device tensor), `tau` (0-d tensor) and a
+    body-force field `field` (device tensor (D, *shape), applied with scale eps
+    by the exact-difference method) through the library's adjoint."""
     torch = _torch()
     if tau is None:
         tau = torch.tensor(sim.tau, dtype=torch.float64)
-    return _Rollout.get().apply(s, tau, sim, nsteps, K, rho0, u0)
+    return _Rollout.get().apply(s, tau, sim, nsteps, K, rho0, u0, field, float(eps))
 
 
 class BatchSim:

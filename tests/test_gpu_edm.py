@@ -8,7 +8,7 @@ import sys
 import numpy as np
 import pytest
 
-from cases import Case, _oface, compare, gpu_sim
+from cases import Case, _oface, compare, fluid_mask, gpu_sim
 from paper_2311_16080_amd import inputs, lbm
 
 pytestmark = pytest.mark.gpu
@@ -217,14 +217,122 @@ def test_force_errors():
         sim.set_force([float("nan"), 0, 0])
     with pytest.raises(lbm.LbmError):
         sim.set_force([1e-4, 0, 0], eps=float("inf"))
-    sim.set_force([1e-4, 0, 0])
-    sim.tape_begin(2, 4)
-    sim.step(2)
-    sim.tape_end()
-    rho_bar = torch.zeros((6, 7, 64), dtype=torch.float32, device="cuda")
-    with pytest.raises(lbm.LbmError) as ei:
-        sim.backward(rho_bar, None)
-    assert ei.value.code == lbm.LBM_EUNSUPPORTED
     bs = lbm.BatchSim("D2Q9", [(8, 8)], [0.7], [[(W,), (W,), (W,), (W, (0.05, 0.0)), (P,), (P,)]])
     f = (lbm.ctypes.c_double * 3)(1e-4, 0, 0)
     assert lbm.lib().lbm_set_force(bs.h, f, None, 1.0) == lbm.LBM_EUNSUPPORTED
+    bs.init_equilibrium()
+    bs.tape_begin(2, 4)
+    bs.step(2)
+    bs.tape_end()
+    out = (lbm.ctypes.c_double * 3)()
+    assert lbm.lib().lbm_backward_force(bs.h, None, None, lbm.F32, None, None, None, None, out) == \
+        lbm.LBM_EUNSUPPORTED
+
+
+# ---- adjoint of the body force ---------------------------------------------------------
+def _adj_case(name, storage):
+    if name == "d2q9_channel_pbb":
+        c = Case(9, (40, 24), 0.6, [(ZV, (0.04, 0.0)), (OUT, (0, 0, 0), 1.0), (W,), (W, (0.03, 0.0)), (P,), (P,)],
+                 steps=16, storage=storage, init_seed=250,
+                 s=inputs.smooth_solid_fraction(40, 24, seed=4, sigma=3, edge=4))
+        return c, 5, 0.5
+    c = Case(19, (10, 12, 64), 0.7, [(W,), (W, (0.0, 0.02, 0.01)), (W,), (W,), (P,), (P,)], steps=12,
+             storage=storage, init_seed=251,
+             solid=inputs.sphere_obstacles(10, 12, 64, seed=8, rmin=1.5, rmax=3, xlo=3, xhi=7, fraction=0.04))
+    return c, 4, 1.0
+
+
+def _oracle_force_grads(case, fld, uni, eps, target):
+    import oracle
+    e = np.zeros(case.oshape + (3,))
+    e[..., : case.D] = eps * (fld.reshape(case.oshape + (case.D,)) + uni)
+    faces = [_oface(F) for F in case.faces]
+    if case.q == 9:
+        faces[4] = faces[5] = oracle.Face()
+    sol = None if case.solid is None else case.solid.reshape(case.oshape).astype(np.uint8)
+    sv = None if case.s is None else case.s.reshape(case.oshape).astype(np.float32).astype(np.float64)
+    S = oracle.Sim(q=case.q, nx=case.oshape[0], ny=case.oshape[1], nz=case.oshape[2], tau=case.tau, faces=faces,
+                   solid=sol, s=sv, edm=e)
+    rho, u = case.init_fields()
+    f = S.equilibrium_state(rho=rho.reshape(case.oshape), u=u.reshape(case.oshape + (case.D,)))
+    states = S.trajectory(f, case.steps)
+    _, uf = S.moments(states[-1])
+    m = fluid_mask(case)[..., None]
+    seed = S.seed_from_velocity_grad(states[-1], 2.0 * (uf[..., : case.D] - target) * m)
+    _, dlds, dtau, duw, dldf = S.adjoint(states, seed, with_force=True)
+    dfield = eps * dldf[..., : case.D]
+    dforce = dfield[fluid_mask(case)].sum(0)
+    return dlds, dtau, duw, dfield, dforce
+
+
+@pytest.mark.parametrize("name", ["d2q9_channel_pbb", "d3q19_zperiodic_spheres"])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_force_adjoint_matches_oracle(name, storage, tol):
+    import torch
+    case, K, eps = _adj_case(name, storage)
+    _announce(f"edm adjoint {name} {storage}")
+    fld, uni = _field(case, 350, amp=1e-3)
+    fld_s = _field_as_stored(fld, storage)
+    target = inputs.random_velocity(case.oshape, case.D, 71, amp=0.02)
+    sim = gpu_sim(case)
+    ft = torch.tensor(np.moveaxis(fld, -1, 0).copy(), dtype=torch.float64, device="cuda")
+    sim.set_force(uni, ft, eps)
+    sim.tape_begin(K, case.steps)
+    sim.step(case.steps)
+    sim.tape_end()
+    dt = torch.float64 if storage == "f64" else torch.float32
+    rho, u = sim.moments(dtype=dt)
+    m = torch.tensor(fluid_mask(case).reshape(case.shape), device="cuda")
+    tgt = torch.tensor(np.moveaxis(target[..., : case.D].reshape(case.shape + (case.D,)), -1, 0).copy(),
+                       dtype=dt, device="cuda")
+    ds, dtau, duw, dfield, dforce = sim.backward_force(None, 2.0 * (u - tgt) * m, want_s=case.s is not None)
+    o_ds, o_dtau, o_duw, o_dfield, o_dforce = _oracle_force_grads(case, fld_s, uni, eps, target[..., : case.D])
+    g = np.moveaxis(dfield.double().cpu().numpy(), 0, -1).reshape(case.oshape + (case.D,))
+    fm = fluid_mask(case)
+    e_field = np.linalg.norm((g - o_dfield)[fm]) / np.linalg.norm(o_dfield[fm])
+    e_force = np.max(np.abs(dforce - o_dforce)) / np.max(np.abs(o_dforce))
+    print(f"[case] {name} {storage}: dL/dfield rel-L2 {e_field:.3e}, dL/dforce rel {e_force:.3e}, "
+          f"dtau {dtau[0]:.6e} vs {o_dtau:.6e}", flush=True)
+    assert e_field <= tol and e_force <= tol
+    assert abs(dtau[0] - o_dtau) <= tol * abs(o_dtau)
+    nz = np.abs(o_duw) > 0
+    if np.any(nz):
+        assert np.linalg.norm(duw[0][nz] - o_duw[nz]) <= tol * np.linalg.norm(o_duw[nz])
+    if case.s is not None:
+        d = ds.double().cpu().numpy().reshape(case.oshape)
+        assert np.linalg.norm((d - o_ds)[fm]) <= max(tol, 1e-7) * np.linalg.norm(o_ds[fm])
+    # lbm_backward with the force on gives the same tau gradient
+    _, dtau2, _ = sim.backward(None, 2.0 * (u - tgt) * m)
+    assert abs(dtau2[0] - dtau[0]) <= 1e-12 * abs(dtau[0])
+
+
+def test_force_autograd_matches_finite_differences():
+    """torch.autograd through lbm.rollout with a force field: field.grad against
+    central differences of the GPU forward itself (FP64)."""
+    import torch
+    _announce("edm autograd FD")
+    shape = (24, 20)
+    faces = [(P,), (P,), (W,), (W, (0.03, 0.0)), (P,), (P,)]
+    sim = lbm.Sim("D2Q9", shape, 0.7, faces=faces, storage="f64")
+    rho0 = torch.tensor(inputs.random_density(shape, 80, amp=0.01), device="cuda")
+    u0 = torch.tensor(np.moveaxis(inputs.random_velocity(shape, 2, 81, amp=0.03), -1, 0).copy(), device="cuda")
+    target = torch.tensor(np.moveaxis(inputs.random_velocity(shape, 2, 82, amp=0.02), -1, 0).copy(), device="cuda")
+    field = torch.tensor(np.moveaxis(inputs.random_velocity(shape, 2, 83, amp=1e-3), -1, 0).copy(), device="cuda",
+                         requires_grad=True)
+
+    def loss_of(fl):
+        _, u = lbm.rollout(sim, 10, 4, rho0=rho0, u0=u0, field=fl, eps=0.5)
+        return torch.sum((u - target) ** 2)
+
+    L = loss_of(field)
+    L.backward()
+    g = field.grad.detach().cpu().numpy()
+    h = 1e-6
+    for idx in [(0, 3, 4), (1, 10, 0), (0, 23, 19), (1, 12, 9)]:
+        fp = field.detach().clone()
+        fp[idx] += h
+        fm = field.detach().clone()
+        fm[idx] -= h
+        with torch.no_grad():
+            fd = (float(loss_of(fp)) - float(loss_of(fm))) / (2 * h)
+        assert abs(fd - g[idx]) <= 1e-6 * max(abs(fd), 1e-6 * float(L)), idx
