@@ -290,6 +290,63 @@ def channel_spheres_figures(torch, lbm, steps=50):
     return res
 
 
+def forced_channel_figures(torch, lbm, steps=100, adj_steps=40, K=10):
+    """Force-driven channel (the paper's turbulent-channel setup, Sec. 6.2):
+    D3Q19 FP32, walls 2h apart in y, periodic streamwise (6h) and spanwise (3h),
+    h = 128 (768 x 256 x 384 cells), driven by F_x = Re_tau^2 nu^2 / h^3 at
+    Re_tau = 180 through the exact-difference method; once as a uniform force,
+    once as a per-cell field (3 more FP32 reads per cell), plus the adjoint /
+    forward time ratio with the field gradient requested."""
+    from paper_2311_16080_amd import inputs
+    h = 128
+    shape = (6 * h, 2 * h, 3 * h)
+    N = int(np.prod(shape))
+    nu = 0.01 * h / 180.0            # u_tau = Re_tau nu / h = 0.01
+    tau = 0.5 + 3.0 * nu
+    Fx = 180.0 ** 2 * nu ** 2 / h ** 3
+    faces = [(lbm.PERIODIC,), (lbm.PERIODIC,), (lbm.WALL,), (lbm.WALL,), (lbm.PERIODIC,), (lbm.PERIODIC,)]
+    res = {"shape": list(shape), "tau": round(tau, 6), "Fx": Fx}
+    field = torch.tensor(np.moveaxis(inputs.random_velocity(shape, 3, 90, amp=0.1 * Fx), -1, 0).copy(),
+                         dtype=torch.float32, device="cuda")
+    for kind, bpc in (("none", 152), ("uniform", 152), ("field", 164)):
+        sim = lbm.Sim("D3Q19", shape, tau, faces=faces, storage="f32")
+        sim.use_current_stream()
+        sim.init_equilibrium()
+        if kind == "uniform":
+            sim.set_force([Fx, 0.0, 0.0])
+        elif kind == "field":
+            sim.set_force([Fx, 0.0, 0.0], field)
+        sim.step(10)
+        with Timer(torch) as T:
+            sim.step(steps)
+        mlups = N * steps / (T.ms / 1e3) / 1e6
+        gbps = mlups * 1e6 * bpc / 1e9
+        res[kind] = {"MLUPS": round(mlups, 1), "GBps": round(gbps, 1), "frac": round(gbps / PEAK_HBM_GBPS, 4),
+                     "bytes_per_lattice_update": bpc}
+        if kind == "field":
+            # adjoint / forward ratio with dL/dfield requested (mean kinetic energy loss)
+            sim.init_equilibrium()
+            sim.step(2)
+            with Timer(torch) as F:
+                sim.step(adj_steps)
+            sim.init_equilibrium()
+            sim.tape_begin(K, adj_steps)
+            sim.step(adj_steps)
+            sim.tape_end()
+            rho, u = sim.moments(dtype=torch.float32)
+            g_rho, g_u = _ke_seed(torch, rho, u, float(N))
+            with Timer(torch) as B:
+                _, _, _, dfield, dforce = sim.backward_force(g_rho, g_u)
+            res["adjoint_with_force"] = {"steps": adj_steps, "K": K, "forward_ms": round(F.ms, 3),
+                                         "backward_ms": round(B.ms, 3), "ratio": round(B.ms / F.ms, 3),
+                                         "dL_dforce": [float(v) for v in dforce]}
+            del dfield
+            sim.tape_free()
+        del sim
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -302,6 +359,10 @@ def main():
     ap.add_argument("--no-copy", action="store_true", help="skip the HBM copy probe")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP16/BF16, adjoint, batched and D3Q27 channel figures")
+    ap.add_argument("--extra", default=None,
+                    choices=["storage_f16_bf16", "adjoint_forward_ratio", "batched_cavities", "d3q27_channel_spheres",
+                             "d3q19_forced_channel"],
+                    help="run only this secondary figure and print it as one JSON line (for profiling)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -310,6 +371,15 @@ def main():
 
     import torch
     from paper_2311_16080_amd import lbm
+
+    if args.extra:
+        fns = {"storage_f16_bf16": lambda: storage_variants(torch, lbm, args.n, 0.55, args.steps),
+               "adjoint_forward_ratio": lambda: adjoint_figures(torch, lbm),
+               "batched_cavities": lambda: batch_figures(torch, lbm),
+               "d3q27_channel_spheres": lambda: channel_spheres_figures(torch, lbm),
+               "d3q19_forced_channel": lambda: forced_channel_figures(torch, lbm)}
+        print(json.dumps({"extra": args.extra, "result": fns[args.extra]()}), flush=True)
+        return
 
     n = args.n
     tau = 0.55
@@ -388,7 +458,8 @@ def main():
         for key, fn in (("storage_f16_bf16", lambda: storage_variants(torch, lbm, n, tau, args.steps)),
                         ("adjoint_forward_ratio", lambda: adjoint_figures(torch, lbm)),
                         ("batched_cavities", lambda: batch_figures(torch, lbm)),
-                        ("d3q27_channel_spheres", lambda: channel_spheres_figures(torch, lbm))):
+                        ("d3q27_channel_spheres", lambda: channel_spheres_figures(torch, lbm)),
+                        ("d3q19_forced_channel", lambda: forced_channel_figures(torch, lbm))):
             t0 = time.perf_counter()
             try:
                 extras[key] = fn()

@@ -45,7 +45,7 @@ struct lbm_ctx {
     int xcd_remap = 0;               // LBM_XCD_REMAP = 0 / 1 (measured: off is faster)
     int zrot = 0;                    // LBM_ZROT = 0 / 1: rotate lanes within a Z row by 32
     int pair = 1;                    // LBM_PAIR = 0 / 1 / 2: two cells per lane for FP16 / BF16 storage (0 never, 1 even steps, 2 all in-place steps)
-    int block_req = 256;             // LBM_BLOCK = 64 / 128 / 256 (threads per block, along Z)
+    int block_req = 0;               // LBM_BLOCK = 64 / 128 / 192 / 256 (threads per block, along Z); 0: by row length
 
     // device
     int device = -1;
