@@ -25,7 +25,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
-PERIODIC, WALL, ZOUHE_VEL, ZOUHE_PRES, OUTFLOW = 0, 1, 2, 3, 4
+PERIODIC, WALL, ZOUHE_VEL, ZOUHE_PRES, OUTFLOW, REG_VEL, REG_PRES = 0, 1, 2, 3, 4, 5, 6
 FACE_NAMES = ("-x", "+x", "-y", "+y", "-z", "+z")
 
 
@@ -255,6 +255,8 @@ class Sim:
                                     _dp(np.ascontiguousarray(a_next)), _dp(a_out),
                                     dlds.ctypes.data if self.s is not None else None,
                                     _dp(dtau), _dp(duw), dldf.ctypes.data)
+        if rc == -2:
+            raise NotImplementedError("the oracle adjoint does not cover regularized faces")
         if rc != 0:
             raise MemoryError("oracle allocation failed")
         out = (a_out, dlds.reshape(self.shape), float(dtau[0]), duw.reshape(6, 3))

@@ -35,7 +35,11 @@
 #endif
 
 /* face types */
-enum { ORC_PERIODIC = 0, ORC_WALL = 1, ORC_ZOUHE_VEL = 2, ORC_ZOUHE_PRES = 3, ORC_OUTFLOW = 4 };
+enum { ORC_PERIODIC = 0, ORC_WALL = 1, ORC_ZOUHE_VEL = 2, ORC_ZOUHE_PRES = 3, ORC_OUTFLOW = 4,
+       ORC_REG_VEL = 5, ORC_REG_PRES = 6 };
+/* velocity / pressure faces (Zou-He or regularized) */
+static int vel_face(int t) { return t == ORC_ZOUHE_VEL || t == ORC_REG_VEL; }
+static int pres_face(int t) { return t == ORC_ZOUHE_PRES || t == ORC_REG_PRES; }
 
 typedef struct {
     int type;
@@ -289,7 +293,7 @@ static void zouhe_closure(const orc_sim *S, int face, double *f)
         if (cn == -1) sumO += f[i];
     }
     double rho, u[3];
-    if (F->type == ORC_ZOUHE_VEL) {
+    if (vel_face(F->type)) {
         double un = F->u[0] * n[0] + F->u[1] * n[1] + F->u[2] * n[2];
         rho = (sumZ + 2.0 * sumO) / (1.0 - un);
         for (int a = 0; a < 3; ++a) u[a] = F->u[a];
@@ -323,7 +327,69 @@ static void zouhe_closure(const orc_sim *S, int face, double *f)
     }
 }
 
-void orc_zouhe_closure(const orc_sim *S, int face, double *f) { zouhe_closure(S, face, f); }
+
+/* Regularized velocity / pressure face (Latt, Chopard, Malaspinas, Deville &
+ * Michler 2008; the paper lists it among XLB's boundary conditions, Sec. 3.5).
+ * rho and u as for Zou-He: a velocity face takes u_w and the density from the
+ * known populations, a pressure face rho_w and the normal velocity from them.
+ * The unknown populations get the non-equilibrium part of their opposite
+ * (bounce-back of f - feq); then every population is rebuilt from the
+ * equilibrium and the non-equilibrium momentum flux alone:
+ *   f_i = feq_i(rho, u) + w_i / (2 cs^4) (c_i c_i - cs^2 I) : Pi_neq,
+ *   Pi_neq = sum_i c_i c_i (f_i - feq_i),  cs^2 = 1/3. */
+static void regularized_closure(const orc_sim *S, int face, double *f)
+{
+    int q = S->q;
+    int n[3];
+    inward_normal(face, n);
+    const orc_face *F = &S->face[face];
+    double sumZ = 0.0, sumO = 0.0;
+    for (int i = 0; i < q; ++i) {
+        const int *c = cvec(q, i);
+        int cn = c[0] * n[0] + c[1] * n[1] + c[2] * n[2];
+        if (cn == 0) sumZ += f[i];
+        if (cn == -1) sumO += f[i];
+    }
+    double rho, u[3];
+    if (vel_face(F->type)) {
+        double un = F->u[0] * n[0] + F->u[1] * n[1] + F->u[2] * n[2];
+        rho = (sumZ + 2.0 * sumO) / (1.0 - un);
+        for (int a = 0; a < 3; ++a) u[a] = F->u[a];
+    } else {
+        rho = F->rho;
+        double un = 1.0 - (sumZ + 2.0 * sumO) / rho;
+        for (int a = 0; a < 3; ++a) u[a] = un * n[a];
+    }
+    double fneq[27];
+    for (int i = 0; i < q; ++i) fneq[i] = f[i] - feq_i(q, i, rho, u);
+    for (int i = 0; i < q; ++i) {
+        const int *c = cvec(q, i);
+        if (c[0] * n[0] + c[1] * n[1] + c[2] * n[2] == 1) fneq[i] = fneq[opposite(q, i)];
+    }
+    double Pi[3][3] = {{0.0}};
+    for (int i = 0; i < q; ++i) {
+        const int *c = cvec(q, i);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) Pi[a][b] += c[a] * c[b] * fneq[i];
+    }
+    for (int i = 0; i < q; ++i) {
+        const int *c = cvec(q, i);
+        double qp = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) qp += (c[a] * c[b] - ((a == b) ? 1.0 / 3.0 : 0.0)) * Pi[a][b];
+        f[i] = feq_i(q, i, rho, u) + 4.5 * weight(q, i) * qp;
+    }
+}
+
+/* closure of an open velocity / pressure face, by its type */
+static void open_closure(const orc_sim *S, int face, double *f)
+{
+    int t = S->face[face].type;
+    if (t == ORC_REG_VEL || t == ORC_REG_PRES) regularized_closure(S, face, f);
+    else zouhe_closure(S, face, f);
+}
+
+void orc_zouhe_closure(const orc_sim *S, int face, double *f) { open_closure(S, face, f); }
 
 /* ---------------------------------------------------------------------------
  * One step f(t) -> f(t+1).
@@ -392,7 +458,7 @@ static void step_impl(const orc_sim *S, const double *f, double *fn, double *fpo
             case SRC_ZOUHE: {
                 const orc_face *F = &S->face[src.face];
                 if (perimeter) {
-                    if (F->type == ORC_ZOUHE_VEL) out[i] = feq_i(q, i, S->rho0, F->u);
+                    if (vel_face(F->type)) out[i] = feq_i(q, i, S->rho0, F->u);
                     else out[i] = feq_i(q, i, F->rho, u_here);
                 } else {
                     out[i] = 0.0;          /* unknown: filled by the closure below */
@@ -402,7 +468,7 @@ static void step_impl(const orc_sim *S, const double *f, double *fn, double *fpo
             }
             }
         }
-        if (zh_face >= 0) zouhe_closure(S, zh_face, out);
+        if (zh_face >= 0) open_closure(S, zh_face, out);
     }
 }
 
@@ -532,6 +598,10 @@ int orc_adjoint_step(const orc_sim *S, const double *f, const double *a_next, do
 {
     const int q = S->q;
     const long N = (long)S->nx * S->ny * S->nz;
+    /* the regularized closure rewrites the known populations too and is not
+     * affine for pressure faces: its transpose is not written here */
+    for (int fc = 0; fc < 6; ++fc)
+        if (S->face[fc].type == ORC_REG_VEL || S->face[fc].type == ORC_REG_PRES) return -2;
     double *ag = (double *)calloc((size_t)N * q, sizeof(double));
     double *apost = (double *)calloc((size_t)N * q, sizeof(double));
     double *au = (double *)calloc((size_t)N * 3, sizeof(double));
@@ -609,7 +679,7 @@ int orc_adjoint_step(const orc_sim *S, const double *f, const double *a_next, do
                 int uses_u = 0;
                 double rf = 0.0;
                 if (src.kind == SRC_OUTFLOW) { uses_u = 1; rf = S->face[src.face].rho; }
-                else if (perimeter && S->face[src.face].type == ORC_ZOUHE_PRES) { uses_u = 1; rf = S->face[src.face].rho; }
+                else if (perimeter && pres_face(S->face[src.face].type)) { uses_u = 1; rf = S->face[src.face].rho; }
                 if (uses_u) {
                     double cu = c[0] * u_here[0] + c[1] * u_here[1] + c[2] * u_here[2];
                     for (int a = 0; a < 3; ++a) {
