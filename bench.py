@@ -347,6 +347,31 @@ def forced_channel_figures(torch, lbm, steps=100, adj_steps=40, K=10):
     return res
 
 
+def regularized_channel_figures(torch, lbm, steps=100):
+    """D3Q19 FP32 512 x 256 x 256 channel, velocity inlet u = 0.04 on -x and
+    pressure outlet rho = 1 on +x, walls on y and z: the same run with
+    Zou-He faces and with regularized faces (the closure runs on the two
+    open face planes only)."""
+    shape = (512, 256, 256)
+    N = int(np.prod(shape))
+    res = {"shape": list(shape)}
+    for name, vel, pres in (("zouhe", lbm.ZOUHE_VELOCITY, lbm.ZOUHE_PRESSURE),
+                            ("regularized", lbm.REG_VELOCITY, lbm.REG_PRESSURE)):
+        faces = [(vel, (0.04, 0.0, 0.0)), (pres, (0.0, 0.0, 0.0), 1.0), (lbm.WALL,), (lbm.WALL,), (lbm.WALL,),
+                 (lbm.WALL,)]
+        sim = lbm.Sim("D3Q19", shape, 0.6, faces=faces, storage="f32")
+        sim.use_current_stream()
+        sim.init_equilibrium()
+        sim.step(10)
+        with Timer(torch) as T:
+            sim.step(steps)
+        mlups = N * steps / (T.ms / 1e3) / 1e6
+        gbps = mlups * 1e6 * 152 / 1e9
+        res[name] = {"MLUPS": round(mlups, 1), "GBps": round(gbps, 1), "frac": round(gbps / PEAK_HBM_GBPS, 4)}
+        del sim
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -361,7 +386,7 @@ def main():
                     help="skip the FP16/BF16, adjoint, batched and D3Q27 channel figures")
     ap.add_argument("--extra", default=None,
                     choices=["storage_f16_bf16", "adjoint_forward_ratio", "batched_cavities", "d3q27_channel_spheres",
-                             "d3q19_forced_channel"],
+                             "d3q19_forced_channel", "d3q19_regularized_channel"],
                     help="run only this secondary figure and print it as one JSON line (for profiling)")
     args = ap.parse_args()
 
@@ -377,7 +402,8 @@ def main():
                "adjoint_forward_ratio": lambda: adjoint_figures(torch, lbm),
                "batched_cavities": lambda: batch_figures(torch, lbm),
                "d3q27_channel_spheres": lambda: channel_spheres_figures(torch, lbm),
-               "d3q19_forced_channel": lambda: forced_channel_figures(torch, lbm)}
+               "d3q19_forced_channel": lambda: forced_channel_figures(torch, lbm),
+               "d3q19_regularized_channel": lambda: regularized_channel_figures(torch, lbm)}
         print(json.dumps({"extra": args.extra, "result": fns[args.extra]()}), flush=True)
         return
 
@@ -459,7 +485,8 @@ def main():
                         ("adjoint_forward_ratio", lambda: adjoint_figures(torch, lbm)),
                         ("batched_cavities", lambda: batch_figures(torch, lbm)),
                         ("d3q27_channel_spheres", lambda: channel_spheres_figures(torch, lbm)),
-                        ("d3q19_forced_channel", lambda: forced_channel_figures(torch, lbm))):
+                        ("d3q19_forced_channel", lambda: forced_channel_figures(torch, lbm)),
+                        ("d3q19_regularized_channel", lambda: regularized_channel_figures(torch, lbm))):
             t0 = time.perf_counter()
             try:
                 extras[key] = fn()

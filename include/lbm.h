@@ -61,6 +61,9 @@ extern "C" {
 #define LBM_ZOUHE_VELOCITY  2  /* Zou-He non-equilibrium bounce-back, velocity u */
 #define LBM_ZOUHE_PRESSURE  3  /* Zou-He, density rho (u normal to the face) */
 #define LBM_EQ_OUTFLOW      4  /* missing populations = feq(rho, u of the cell) */
+#define LBM_REG_VELOCITY    5  /* regularized (Latt et al. 2008), velocity u: rho as for Zou-He; the whole
+                                  cell rebuilt from feq and the regularized non-equilibrium momentum flux */
+#define LBM_REG_PRESSURE    6  /* regularized, density rho (u normal to the face) */
 
 /* ---- storage / arithmetic types (Sec. 3.7 "computation/storage" pairs) --- */
 #define LBM_F64  0
@@ -75,12 +78,12 @@ extern "C" {
 /*
  * One face of the box.  Faces are ordered -x, +x, -y, +y, -z, +z.
  *  type : LBM_PERIODIC / LBM_WALL / LBM_ZOUHE_VELOCITY / LBM_ZOUHE_PRESSURE /
- *         LBM_EQ_OUTFLOW.
+ *         LBM_EQ_OUTFLOW / LBM_REG_VELOCITY / LBM_REG_PRESSURE.
  *  u    : wall velocity (LBM_WALL; its normal component must be 0) or inlet
- *         velocity (LBM_ZOUHE_VELOCITY).
- *  rho  : face density (LBM_ZOUHE_PRESSURE, LBM_EQ_OUTFLOW); must be > 0 there.
+ *         velocity (LBM_ZOUHE_VELOCITY, LBM_REG_VELOCITY).
+ *  rho  : face density (LBM_ZOUHE_PRESSURE, LBM_REG_PRESSURE, LBM_EQ_OUTFLOW); must be > 0 there.
  * Rules (else LBM_EINVAL): periodic on both faces of an axis or on neither;
- * Zou-He / outflow faces on at most one axis, that axis at least 2 cells
+ * Zou-He / regularized / outflow faces on at most one axis, that axis at least 2 cells
  * long; for 2-D lattices the z faces are ignored.
  */
 typedef struct {
@@ -292,7 +295,8 @@ int lbm_tape_free(lbm_ctx *ctx);
  *   dL_duw   : host double[n_domains * 6 * 3], gradient w.r.t. each face's
  *              wall velocity (LBM_WALL faces only; other entries 0).
  * The forward state is left unchanged.  Synchronises.  LBM_ESTATE without a
- * tape or if the state moved since the tape ended.
+ * tape or if the state moved since the tape ended; LBM_EUNSUPPORTED when a
+ * domain has regularized faces.
  */
 int lbm_backward(lbm_ctx *ctx, const void *dL_drho, const void *dL_du, int dtype,
                  float *dL_ds, double *dL_dtau, double *dL_duw);

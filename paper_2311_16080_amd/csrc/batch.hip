@@ -86,7 +86,9 @@ static void domain_params(Params<CT> &p, const lbm_ctx *c, const Domain &D, cons
             p.wallmask |= 1u << f;
             if (F.u[0] == 0.0 && F.u[1] == 0.0 && F.u[2] == 0.0) p.staticmask |= 1u << f;
         }
-        if (F.type == LBM_ZOUHE_VELOCITY || F.type == LBM_ZOUHE_PRESSURE) p.zhmask |= 1u << f;
+        if (F.type == LBM_ZOUHE_VELOCITY || F.type == LBM_ZOUHE_PRESSURE || F.type == LBM_REG_VELOCITY ||
+            F.type == LBM_REG_PRESSURE)
+            p.zhmask |= 1u << f;
         if (F.type == LBM_PERIODIC) p.permask |= 1u << f;
     }
     p.ft = ft;

@@ -66,7 +66,7 @@ int lbm::validate_domain(int lattice, int nx, int ny, int nz, double tau, const 
     for (int a = 0; a < naxes; ++a) {
         const lbm_face &lo = bc->face[2 * a], &hi = bc->face[2 * a + 1];
         for (const lbm_face *F : {&lo, &hi}) {
-            if (F->type < LBM_PERIODIC || F->type > LBM_EQ_OUTFLOW)
+            if (F->type < LBM_PERIODIC || F->type > LBM_REG_PRESSURE)
                 return fail(LBM_EINVAL, "face %d: unknown boundary type %d", (int)(F - bc->face), F->type);
             for (int c = 0; c < 3; ++c)
                 if (!std::isfinite(F->u[c])) return fail(LBM_EINVAL, "face %d: velocity not finite", (int)(F - bc->face));
@@ -77,13 +77,15 @@ int lbm::validate_domain(int lattice, int nx, int ny, int nz, double tau, const 
             const lbm_face &F = bc->face[2 * a + sd];
             if (F.type == LBM_WALL && F.u[a] != 0.0)
                 return fail(LBM_EINVAL, "face %d: a wall velocity must be tangential", 2 * a + sd);
-            if (F.type == LBM_ZOUHE_VELOCITY && std::fabs(F.u[a]) >= 1.0)
+            const bool vel = F.type == LBM_ZOUHE_VELOCITY || F.type == LBM_REG_VELOCITY;
+            const bool pres = F.type == LBM_ZOUHE_PRESSURE || F.type == LBM_REG_PRESSURE;
+            if (vel && std::fabs(F.u[a]) >= 1.0)
                 return fail(LBM_EINVAL, "face %d: inlet normal velocity must be below 1", 2 * a + sd);
-            if ((F.type == LBM_ZOUHE_PRESSURE || F.type == LBM_EQ_OUTFLOW) && !(F.rho > 0.0))
+            if ((pres || F.type == LBM_EQ_OUTFLOW) && !(F.rho > 0.0))
                 return fail(LBM_EINVAL, "face %d: density must be > 0", 2 * a + sd);
-            if (F.type == LBM_ZOUHE_VELOCITY || F.type == LBM_ZOUHE_PRESSURE || F.type == LBM_EQ_OUTFLOW) {
+            if (vel || pres || F.type == LBM_EQ_OUTFLOW) {
                 if (open_axis >= 0 && open_axis != a)
-                    return fail(LBM_EINVAL, "Zou-He / outflow faces must all lie on one axis");
+                    return fail(LBM_EINVAL, "Zou-He / regularized / outflow faces must all lie on one axis");
                 open_axis = a;
                 if (n[a] < 2) return fail(LBM_EINVAL, "axis %d carries an open face and needs >= 2 cells", a);
             }
@@ -153,7 +155,9 @@ static void fill_params(Params<CT> &p, const lbm_ctx *c) {
             p.wallmask |= 1u << f;
             if (F.u[0] == 0.0 && F.u[1] == 0.0 && F.u[2] == 0.0) p.staticmask |= 1u << f;
         }
-        if (F.type == LBM_ZOUHE_VELOCITY || F.type == LBM_ZOUHE_PRESSURE) p.zhmask |= 1u << f;
+        if (F.type == LBM_ZOUHE_VELOCITY || F.type == LBM_ZOUHE_PRESSURE || F.type == LBM_REG_VELOCITY ||
+            F.type == LBM_REG_PRESSURE)
+            p.zhmask |= 1u << f;   // faces closed at read time
         if (F.type == LBM_PERIODIC) p.permask |= 1u << f;
     }
     p.zh_pending = c->t > 0 ? 1 : 0;

@@ -29,7 +29,7 @@
 
 namespace lbm {
 
-enum : uint8_t { F_PERIODIC = 0, F_WALL = 1, F_ZH_VEL = 2, F_ZH_PRES = 3, F_OUT = 4 };
+enum : uint8_t { F_PERIODIC = 0, F_WALL = 1, F_ZH_VEL = 2, F_ZH_PRES = 3, F_OUT = 4, F_REG_VEL = 5, F_REG_PRES = 6 };
 
 constexpr int kMaxBlock = 256;
 
@@ -241,7 +241,14 @@ __device__ __forceinline__ CT heq(CT drho, CT rho, CT ux, CT uy, CT uz, CT usq15
 // (sum_Z w + 2 sum_O w = 1).  The face is a runtime value and every choice
 // below is a value select, so the populations stay in registers.
 template <class L, class CT>
+__device__ __forceinline__ void regularize(CT *h, const Params<CT> &p, int face);
+
+template <class L, class CT>
 __device__ __forceinline__ void zouhe(CT *h, const Params<CT> &p, int face) {
+    if (p.ft->type[face] >= F_REG_VEL) {
+        regularize<L>(h, p, face);
+        return;
+    }
     const int ax = face >> 1;
     const int sg = (face & 1) ? -1 : 1;
     int cn[L::Q];
@@ -288,6 +295,74 @@ __device__ __forceinline__ void zouhe(CT *h, const Params<CT> &p, int face) {
             if constexpr (L::c[I][T] != 0) v -= (CT)L::c[I][T] * Nt[T];
         });
         h[I] = (cn[I] == 1) ? v : h[I];
+    });
+}
+
+// Regularized velocity / pressure face (Latt et al. 2008, one of the boundary
+// conditions of Sec. 3.5), applied where zouhe() would be: rho and u as for
+// Zou-He; the unknown populations take the non-equilibrium part of their
+// opposite; then every population becomes
+//   feq_i(rho, u) + 4.5 w_i (c_i c_i - I/3) : Pi_neq,  Pi_neq = sum_i c_i c_i (f_i - feq_i).
+// In deviation variables f_i - feq_i = h_i - heq_i.
+template <class L, class CT>
+__device__ __forceinline__ void regularize(CT *h, const Params<CT> &p, int face) {
+    const int ax = face >> 1;
+    const int sg = (face & 1) ? -1 : 1;
+    int cn[L::Q];
+    unroll<L::Q>([&](auto I) {
+        const int ca = (ax == 0) ? L::c[I][0] : ((ax == 1) ? L::c[I][1] : L::c[I][2]);
+        cn[I] = sg * ca;
+    });
+    CT SZ = 0, SO = 0;
+    unroll<L::Q>([&](auto I) {
+        SZ += (cn[I] == 0) ? h[I] : (CT)0;
+        SO += (cn[I] == -1) ? h[I] : (CT)0;
+    });
+    const CT known = SZ + (CT)2 * SO;
+    const FaceTab<CT> &F = *p.ft;
+    CT rho, u[3];
+    if (F.type[face] == F_REG_VEL) {
+        u[0] = F.uw[face][0];
+        u[1] = F.uw[face][1];
+        u[2] = F.uw[face][2];
+        const CT un = (CT)sg * ((ax == 0) ? u[0] : ((ax == 1) ? u[1] : u[2]));
+        rho = p.rho0 + (known + p.rho0 * un) / ((CT)1 - un);
+    } else {
+        rho = F.rho[face];
+        const CT un = (rho - p.rho0 - known) / rho;
+        u[0] = (ax == 0) ? (CT)sg * un : (CT)0;
+        u[1] = (ax == 1) ? (CT)sg * un : (CT)0;
+        u[2] = (ax == 2) ? (CT)sg * un : (CT)0;
+    }
+    const CT drho = rho - p.rho0;
+    const CT usq15 = (CT)1.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    // non-equilibrium parts, in place; unknowns from their (known) opposites
+    unroll<L::Q>([&](auto I) { h[I] -= heq<L, I>(drho, rho, u[0], u[1], u[2], usq15); });
+    unroll<L::Q>([&](auto I) {
+        constexpr int O = opp<L>(I);
+        h[I] = (cn[I] == 1) ? h[O] : h[I];
+    });
+    CT P00 = 0, P11 = 0, P22 = 0, P01 = 0, P02 = 0, P12 = 0;
+    unroll<L::Q>([&](auto I) {
+        constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
+        if constexpr (cx != 0) P00 += h[I];
+        if constexpr (cy != 0) P11 += h[I];
+        if constexpr (cz != 0) P22 += h[I];
+        if constexpr (cx * cy != 0) P01 += (CT)(cx * cy) * h[I];
+        if constexpr (cx * cz != 0) P02 += (CT)(cx * cz) * h[I];
+        if constexpr (cy * cz != 0) P12 += (CT)(cy * cz) * h[I];
+    });
+    const CT tr3 = (P00 + P11 + P22) * (CT)(1.0 / 3.0);
+    unroll<L::Q>([&](auto I) {
+        constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
+        CT qp = -tr3;
+        if constexpr (cx != 0) qp += P00;
+        if constexpr (cy != 0) qp += P11;
+        if constexpr (cz != 0) qp += P22;
+        if constexpr (cx * cy != 0) qp += (CT)(2 * cx * cy) * P01;
+        if constexpr (cx * cz != 0) qp += (CT)(2 * cx * cz) * P02;
+        if constexpr (cy * cz != 0) qp += (CT)(2 * cy * cz) * P12;
+        h[I] = heq<L, I>(drho, rho, u[0], u[1], u[2], usq15) + (CT)(4.5 * weight<L>(I)) * qp;
     });
 }
 
@@ -418,7 +493,7 @@ __device__ __forceinline__ CT fill_value(const Params<CT> &p, const Nb &nb, CT h
     if (nb.kind == NB_OUT || (nb.kind == NB_ZH && perimeter)) {
         const FaceTab<CT> &F = *p.ft;
         CT r, vx, vy, vz;
-        if (nb.kind == NB_ZH && F.type[nb.face] == F_ZH_VEL) {
+        if (nb.kind == NB_ZH && (F.type[nb.face] == F_ZH_VEL || F.type[nb.face] == F_REG_VEL)) {
             r = p.rho0;
             vx = F.uw[nb.face][0];
             vy = F.uw[nb.face][1];

@@ -108,7 +108,9 @@ extern "C" int lbm_graph_launch(lbm_ctx *c) {
     const bool same_buffers = c->A == c->graph_A;
     bool zh = c->pf.zhmask != 0;
     for (const Domain &D : c->dom)
-        for (const lbm_face &F : D.iface) zh = zh || F.type == LBM_ZOUHE_VELOCITY || F.type == LBM_ZOUHE_PRESSURE;
+        for (const lbm_face &F : D.iface)
+            zh = zh || F.type == LBM_ZOUHE_VELOCITY || F.type == LBM_ZOUHE_PRESSURE || F.type == LBM_REG_VELOCITY ||
+                 F.type == LBM_REG_PRESSURE;
     if (!same_buffers || (c->opt.pattern == LBM_INPLACE && !same_parity) || (zh && ((c->t > 0) != (c->graph_t0 > 0))))
         return fail(LBM_ESTATE, "the state's step parity / buffers differ from those at capture");
     (void)hipSetDevice(c->device);

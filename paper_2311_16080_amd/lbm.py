@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 # ---- constants (include/lbm.h) ------------------------------------------------
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ESTATE, LBM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 D2Q9, D3Q19, D3Q27 = 0, 1, 2
-PERIODIC, WALL, ZOUHE_VELOCITY, ZOUHE_PRESSURE, EQ_OUTFLOW = 0, 1, 2, 3, 4
+PERIODIC, WALL, ZOUHE_VELOCITY, ZOUHE_PRESSURE, EQ_OUTFLOW, REG_VELOCITY, REG_PRESSURE = 0, 1, 2, 3, 4, 5, 6
 F64, F32, F16, BF16 = 0, 1, 2, 3
 INPLACE, DOUBLE = 0, 1
 
