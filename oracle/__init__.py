@@ -26,6 +26,7 @@ _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
 PERIODIC, WALL, ZOUHE_VEL, ZOUHE_PRES, OUTFLOW, REG_VEL, REG_PRES = 0, 1, 2, 3, 4, 5, 6
+BGK, KBC = 0, 1
 FACE_NAMES = ("-x", "+x", "-y", "+y", "-z", "+z")
 
 
@@ -47,7 +48,7 @@ class _Sim(ctypes.Structure):
     _fields_ = [("q", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("tau", ctypes.c_double), ("rho0", ctypes.c_double), ("face", _Face * 6),
                 ("solid", ctypes.c_void_p), ("s", ctypes.c_void_p), ("force", ctypes.c_double * 3),
-                ("edm", ctypes.c_void_p)]
+                ("edm", ctypes.c_void_p), ("collision", ctypes.c_int)]
 
 
 _lib = None
@@ -134,6 +135,7 @@ class Sim:
     s: Optional[np.ndarray] = None         # (nx,ny,nz) float64 solid fraction
     force: tuple = (0.0, 0.0, 0.0)
     edm: Optional[np.ndarray] = None       # (nx,ny,nz,3) body force, exact-difference method
+    collision: int = 0                     # 0 BGK, 1 KBC (D2Q9 / D3Q27)
 
     @property
     def shape(self):
@@ -178,6 +180,7 @@ class Sim:
             st.edm = e.ctypes.data
         else:
             st.edm = None
+        st.collision = int(self.collision)
         return st
 
     # --- state ---------------------------------------------------------------
@@ -256,7 +259,7 @@ class Sim:
                                     dlds.ctypes.data if self.s is not None else None,
                                     _dp(dtau), _dp(duw), dldf.ctypes.data)
         if rc == -2:
-            raise NotImplementedError("the oracle adjoint does not cover regularized faces")
+            raise NotImplementedError("the oracle adjoint covers BGK with Zou-He / outflow / wall faces only")
         if rc != 0:
             raise MemoryError("oracle allocation failed")
         out = (a_out, dlds.reshape(self.shape), float(dtau[0]), duw.reshape(6, 3))

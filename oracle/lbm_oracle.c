@@ -57,6 +57,7 @@ typedef struct {
     const double *s;            /* N solid fractions (partial bounce-back); NULL = none */
     double force[3];            /* body force, test hook only (Poiseuille pin) */
     const double *edm;          /* N*3 body force per cell, exact-difference method; NULL = none */
+    int collision;              /* 0: BGK; 1: KBC entropic multi-relaxation (D2Q9, D3Q27) */
 } orc_sim;
 
 /* ---------------------------------------------------------------------------
@@ -151,6 +152,55 @@ void orc_cell_moments(int q, const double *f, double *rho, double *u)
  * 3 w_i (c_i . F) after relaxation (oracle test hook only).  A body force F
  * by the exact-difference method (Sec. 6.2, after Kupershtokh) adds
  * feq_i(rho, u + F/rho) - feq_i(rho, u) to the relaxed populations. */
+/* KBC collision (Karlin, Bosch & Chikatamarla 2014; the paper's collision for
+ * its D2Q9 / D3Q27 runs, Sec. 3.2).  f - feq splits into a shear part ds,
+ * built from the deviatoric non-equilibrium momentum flux on the axis and
+ * face-diagonal velocities only (zero mass, momentum and trace), and the rest
+ * dh:
+ *   D2Q9 : axis (+-1, 0): (P_xx - P_yy) / 4, axis (0, +-1): -(P_xx - P_yy) / 4,
+ *          diagonal c: c_x c_y P_xy / 4;
+ *   D3Q27: axis +-e_a: (2 P_aa - P_bb - P_cc) / 6, face diagonal in the (a, b)
+ *          plane: c_a c_b P_ab / 4, corners and rest 0;
+ * with P = sum_i c_i c_i (f_i - feq_i).  Then
+ *   f*_i = f_i - beta (2 ds_i + gamma dh_i),  beta = 1 / (2 tau),
+ *   gamma = 1/beta - (2 - 1/beta) <ds|dh> / <dh|dh>,  <x|y> = sum_i x_i y_i / feq_i,
+ * the gamma that minimizes the quadratic entropy <f* - feq|f* - feq>; with
+ * dh = 0 it is BGK. */
+static void kbc_collide(int q, const double *f, const double *feq, double tau, double *fstar)
+{
+    double fneq[27], ds[27], dh[27];
+    for (int i = 0; i < q; ++i) fneq[i] = f[i] - feq[i];
+    double P[3][3] = {{0.0}};
+    for (int i = 0; i < q; ++i) {
+        const int *c = cvec(q, i);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) P[a][b] += c[a] * c[b] * fneq[i];
+    }
+    for (int i = 0; i < q; ++i) {
+        const int *c = cvec(q, i);
+        int nz = (c[0] != 0) + (c[1] != 0) + (c[2] != 0);
+        double v = 0.0;
+        if (nz == 1) {
+            int a = (c[0] != 0) ? 0 : ((c[1] != 0) ? 1 : 2);
+            if (q == 9) v = (a == 0 ? 1.0 : -1.0) * (P[0][0] - P[1][1]) / 4.0;
+            else v = (2.0 * P[a][a] - P[(a + 1) % 3][(a + 1) % 3] - P[(a + 2) % 3][(a + 2) % 3]) / 6.0;
+        } else if (nz == 2) {
+            int a = (c[0] == 0) ? 1 : 0;
+            int b = (c[2] != 0) ? 2 : 1;
+            v = c[a] * c[b] * P[a][b] / 4.0;
+        }
+        ds[i] = v;
+        dh[i] = fneq[i] - v;
+    }
+    double beta = 0.5 / tau, sh = 0.0, hh = 0.0;
+    for (int i = 0; i < q; ++i) {
+        sh += ds[i] * dh[i] / feq[i];
+        hh += dh[i] * dh[i] / feq[i];
+    }
+    double gamma = (hh > 0.0) ? 1.0 / beta - (2.0 - 1.0 / beta) * sh / hh : 2.0;
+    for (int i = 0; i < q; ++i) fstar[i] = f[i] - beta * (2.0 * ds[i] + gamma * dh[i]);
+}
+
 static void collide_f(const orc_sim *S, const double *f, double *fstar, double *rho, double u[3], const double *F)
 {
     int q = S->q;
@@ -159,9 +209,14 @@ static void collide_f(const orc_sim *S, const double *f, double *fstar, double *
     double w[3];
     if (F)
         for (int a = 0; a < 3; ++a) w[a] = u[a] + F[a] / *rho;
+    if (S->collision == 1) {
+        double feq[27];
+        for (int i = 0; i < q; ++i) feq[i] = feq_i(q, i, *rho, u);
+        kbc_collide(q, f, feq, S->tau, fstar);
+    }
     for (int i = 0; i < q; ++i) {
         const int *c = cvec(q, i);
-        fstar[i] = f[i] - omega * (f[i] - feq_i(q, i, *rho, u));
+        if (S->collision != 1) fstar[i] = f[i] - omega * (f[i] - feq_i(q, i, *rho, u));
         fstar[i] += 3.0 * weight(q, i) * (c[0] * S->force[0] + c[1] * S->force[1] + c[2] * S->force[2]);
         if (F) fstar[i] += feq_i(q, i, *rho, w) - feq_i(q, i, *rho, u);
     }
@@ -602,6 +657,7 @@ int orc_adjoint_step(const orc_sim *S, const double *f, const double *a_next, do
      * affine for pressure faces: its transpose is not written here */
     for (int fc = 0; fc < 6; ++fc)
         if (S->face[fc].type == ORC_REG_VEL || S->face[fc].type == ORC_REG_PRES) return -2;
+    if (S->collision != 0) return -2;   /* the adjoint covers BGK only */
     double *ag = (double *)calloc((size_t)N * q, sizeof(double));
     double *apost = (double *)calloc((size_t)N * q, sizeof(double));
     double *au = (double *)calloc((size_t)N * 3, sizeof(double));
