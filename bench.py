@@ -372,6 +372,30 @@ def regularized_channel_figures(torch, lbm, steps=100):
     return res
 
 
+def kbc_figures(torch, lbm, steps=60):
+    """KBC vs BGK step rate: D3Q27 FP32 256^3 and D2Q9 FP32 4096^2 lid-driven
+    cavities at tau = 0.5005 (KBC's use: nearly inviscid flow)."""
+    res = {}
+    for lat, shape, bpc in (("D3Q27", (256, 256, 256), 216), ("D2Q9", (4096, 4096), 72)):
+        faces = cavity_faces(lbm) if lat == "D3Q27" else [(lbm.WALL,), (lbm.WALL,), (lbm.WALL,),
+                                                           (lbm.WALL, (0.05, 0.0)), (lbm.PERIODIC,), (lbm.PERIODIC,)]
+        N = int(np.prod(shape))
+        for model in ("BGK", "KBC"):
+            sim = lbm.Sim(lat, shape, 0.5005, faces=faces, storage="f32")
+            sim.use_current_stream()
+            sim.set_collision(model)
+            sim.init_equilibrium()
+            sim.step(4)
+            with Timer(torch) as T:
+                sim.step(steps)
+            mlups = N * steps / (T.ms / 1e3) / 1e6
+            gbps = mlups * 1e6 * bpc / 1e9
+            res[f"{lat}_{model}"] = {"MLUPS": round(mlups, 1), "GBps": round(gbps, 1),
+                                     "frac": round(gbps / PEAK_HBM_GBPS, 4)}
+            del sim
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -386,7 +410,7 @@ def main():
                     help="skip the FP16/BF16, adjoint, batched and D3Q27 channel figures")
     ap.add_argument("--extra", default=None,
                     choices=["storage_f16_bf16", "adjoint_forward_ratio", "batched_cavities", "d3q27_channel_spheres",
-                             "d3q19_forced_channel", "d3q19_regularized_channel"],
+                             "d3q19_forced_channel", "d3q19_regularized_channel", "kbc_cavities"],
                     help="run only this secondary figure and print it as one JSON line (for profiling)")
     args = ap.parse_args()
 
@@ -403,7 +427,8 @@ def main():
                "batched_cavities": lambda: batch_figures(torch, lbm),
                "d3q27_channel_spheres": lambda: channel_spheres_figures(torch, lbm),
                "d3q19_forced_channel": lambda: forced_channel_figures(torch, lbm),
-               "d3q19_regularized_channel": lambda: regularized_channel_figures(torch, lbm)}
+               "d3q19_regularized_channel": lambda: regularized_channel_figures(torch, lbm),
+               "kbc_cavities": lambda: kbc_figures(torch, lbm)}
         print(json.dumps({"extra": args.extra, "result": fns[args.extra]()}), flush=True)
         return
 
@@ -486,7 +511,8 @@ def main():
                         ("batched_cavities", lambda: batch_figures(torch, lbm)),
                         ("d3q27_channel_spheres", lambda: channel_spheres_figures(torch, lbm)),
                         ("d3q19_forced_channel", lambda: forced_channel_figures(torch, lbm)),
-                        ("d3q19_regularized_channel", lambda: regularized_channel_figures(torch, lbm))):
+                        ("d3q19_regularized_channel", lambda: regularized_channel_figures(torch, lbm)),
+                        ("kbc_cavities", lambda: kbc_figures(torch, lbm))):
             t0 = time.perf_counter()
             try:
                 extras[key] = fn()

@@ -71,6 +71,10 @@ extern "C" {
 #define LBM_F16  2
 #define LBM_BF16 3
 
+/* ---- collision models ----------------------------------------------------- */
+#define LBM_BGK 0  /* eq. LBM-BGK (default) */
+#define LBM_KBC 1  /* KBC entropic multi-relaxation (D2Q9 / D3Q27) */
+
 /* ---- streaming patterns --------------------------------------------------- */
 #define LBM_INPLACE 0  /* one buffer, AA access pattern (Bailey et al. 2009) */
 #define LBM_DOUBLE  1  /* two buffers, push streaming */
@@ -267,6 +271,21 @@ int lbm_forces(lbm_ctx *ctx, double *out);
  * captured graph.
  */
 int lbm_set_force(lbm_ctx *ctx, const double *force, const void *field, double eps);
+
+/*
+ * Collision model for the following steps (Sec. 3.2 lists BGK and KBC; the
+ * paper runs KBC on D2Q9 and D3Q27).  LBM_KBC (Karlin, Bosch & Chikatamarla
+ * 2014): f - feq splits into a shear part ds -- the deviatoric non-equilibrium
+ * momentum flux P, carried by the axis velocities ((P_aa - tr P / D) / 2 each)
+ * and the face diagonals (c_a c_b P_ab / 4) -- and the rest dh; the step takes
+ * f*_i = f_i - beta (2 ds_i + gamma dh_i), beta = 1 / (2 tau),
+ * gamma = 1/beta - (2 - 1/beta) <ds|dh> / <dh|dh> with <x|y> = sum x_i y_i / feq_i
+ * (the minimiser of the quadratic entropy; BGK when dh = 0 or tau = 1).
+ * LBM_EINVAL for an unknown model; LBM_EUNSUPPORTED for KBC on D3Q19, on batch
+ * contexts or with a partial bounce-back field; lbm_backward returns
+ * LBM_EUNSUPPORTED while KBC is set.  Drops a captured graph.
+ */
+int lbm_set_collision(lbm_ctx *ctx, int model);
 
 /*
  * Start recording a tape for lbm_backward: a bit-exact checkpoint of the

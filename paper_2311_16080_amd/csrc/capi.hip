@@ -473,7 +473,8 @@ Launch lbm::make_launch(lbm_ctx *c) {
     g.pair = 0;
     g.pgrid = g.pblock = 0;
     g.force = c->force_on ? 1 : 0;
-    if (g.force) return g;   // the body force runs on the one-cell-per-lane kernel
+    g.kbc = c->collision == LBM_KBC ? 1 : 0;
+    if (g.force || g.kbc) return g;   // these run on the one-cell-per-lane kernel
     // two cells per lane for 2-byte storage: rows of nZ % 128 == 0 cells, no
     // lane rotation or XCD remap (the pair kernel's row mapping is fixed)
     if ((c->opt.storage == LBM_F16 || c->opt.storage == LBM_BF16) && c->pair && !c->batch && c->nZ % 128 == 0 &&
@@ -532,6 +533,8 @@ extern "C" int lbm_set_solid_fraction(lbm_ctx *c, const float *s, int on_device)
     if (!c) return fail(LBM_EINVAL, "null context");
     if (c->batch) return fail(LBM_EUNSUPPORTED, "partial bounce-back is not supported on batch contexts");
     if (on_device != 0 && on_device != 1) return fail(LBM_EINVAL, "on_device must be 0 or 1");
+    if (s && c->collision == LBM_KBC)
+        return fail(LBM_EUNSUPPORTED, "KBC does not combine with a partial bounce-back field");
     int rc = ensure_device(c);
     if (rc) return rc;
     drop_graph(c);
@@ -686,6 +689,19 @@ extern "C" int lbm_forces(lbm_ctx *c, double *out) {
         for (int f = 2; f < 6; ++f)
             for (int a = 1; a < 3; ++a) out[3 + 3 * (f - 2) + (a - 1)] = m[3 + 3 * f + a];
     }
+    return LBM_OK;
+}
+
+extern "C" int lbm_set_collision(lbm_ctx *c, int model) {
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if (model != LBM_BGK && model != LBM_KBC) return fail(LBM_EINVAL, "unknown collision model %d", model);
+    if (model == LBM_KBC) {
+        if (c->lattice == LBM_D3Q19) return fail(LBM_EUNSUPPORTED, "KBC is defined here for D2Q9 and D3Q27");
+        if (c->batch) return fail(LBM_EUNSUPPORTED, "KBC is not supported on batch contexts");
+        if (c->s) return fail(LBM_EUNSUPPORTED, "KBC does not combine with a partial bounce-back field");
+    }
+    drop_graph(c);
+    c->collision = model;
     return LBM_OK;
 }
 

@@ -62,6 +62,8 @@ struct lbm_ctx {
     lbm::FaceTab<double> *ftd = nullptr;   // device face tables
     lbm::FaceTab<float> *ftf = nullptr;
 
+    int collision = 0;                     // LBM_BGK / LBM_KBC
+
     // body force (exact-difference method)
     bool force_on = false;
     double force_u[3] = {0.0, 0.0, 0.0};   // uniform part, scale applied (caller axes)

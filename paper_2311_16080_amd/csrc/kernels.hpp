@@ -28,6 +28,7 @@ struct Launch {
     unsigned pgrid;      // launch shape of k_step_pair
     unsigned pblock;
     int force;           // body force on (params carry it)
+    int kbc;             // KBC collision
 };
 
 hipError_t launch_step(const Launch &g, int mode, bool has_s);

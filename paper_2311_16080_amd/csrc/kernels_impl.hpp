@@ -48,7 +48,8 @@ __device__ __forceinline__ bool block_cell(const Params<CT> &p, int &X, int &Y, 
 
 // One cell of one step.  p: the domain's parameters; A (and B for the push
 // step) the domain's state; pending: the state read needs the Zou-He closure.
-// XF bit 0: partial bounce-back field; bit 1: body force; bit 2: periodic
+// XF bit 0: partial bounce-back field; bit 1: body force; bit 3: KBC
+// collision (D2Q9 / D3Q27, without the partial bounce-back field); bit 2: periodic
 // faces on the select path (a variant of its own, so that walls-only domains
 // keep the leaner kernel): any periodic face in the local even step, which has
 // no neighbour addresses, and periodic Z faces in the odd / push steps.
@@ -64,6 +65,7 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
     constexpr bool HAS_S = (XF & 1) != 0;
     constexpr bool FRC = (XF & 2) != 0;
     constexpr bool PZ = (XF & 4) != 0;
+    constexpr bool KB = (XF & 8) != 0;   // KBC collision
     constexpr bool NTA = (NT >= 1);
     constexpr bool NTZL = (NT == 2) || (NT == 4);
     constexpr bool NTZS = (NT == 2) || (NT == 3);
@@ -99,7 +101,7 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
         CT rho, ux, uy, uz;
         CT s = 0;
         if constexpr (HAS_S) s = (CT)p.s[cell];
-        collide<L, FRC>(h, hp, p, s, HAS_S, rho, ux, uy, uz, fx, fy, fz);
+        collide<L, FRC, KB>(h, hp, p, s, HAS_S, rho, ux, uy, uz, fx, fy, fz);
         ST *W = (MODE == 2) ? B : A;
         unroll<Q>([&](auto I) {
             constexpr int O = opp<L>(I);
@@ -142,7 +144,7 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
         CT rho, ux, uy, uz;
         CT s = 0;
         if constexpr (HAS_S) s = (CT)p.s[cell];
-        collide<L, FRC>(h, hp, p, s, HAS_S, rho, ux, uy, uz, fx, fy, fz);
+        collide<L, FRC, KB>(h, hp, p, s, HAS_S, rho, ux, uy, uz, fx, fy, fz);
         ST *W = (MODE == 2) ? B : A;
         unroll<Q>([&](auto I) {
             constexpr int O = opp<L>(I);
@@ -195,7 +197,7 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
     CT rho, ux, uy, uz;
     CT s = 0;
     if constexpr (HAS_S) s = (CT)p.s[cell];
-    collide<L, FRC>(h, hp, p, s, HAS_S, rho, ux, uy, uz, fx, fy, fz);
+    collide<L, FRC, KB>(h, hp, p, s, HAS_S, rho, ux, uy, uz, fx, fy, fz);
     const bool perim = (e & p.wallmask) != 0;
 
     ST *W = (MODE == 2) ? B : A;
@@ -419,8 +421,8 @@ hipError_t step_t(const Launch &g, int mode, bool has_s) {
     ST *B = static_cast<ST *>(g.B);
     if constexpr (sizeof(ST) == 2) {
         // two cells per lane (walls and, in the even step, periodic faces on its
-        // own path); not with a body force
-        if (!g.force && ((g.pair == 1 && mode == 0) || (g.pair == 2 && mode != 2))) {
+        // own path); not with a body force or the KBC collision
+        if (!g.force && !g.kbc && ((g.pair == 1 && mode == 0) || (g.pair == 2 && mode != 2))) {
 #define LBM_PAIR_CASE(M, S) \
     if (mode == M && has_s == S) hipLaunchKernelGGL((k_step_pair<L, ST, M, S>), dim3(g.pgrid), dim3(g.pblock), 0, g.stream, p, A);
             LBM_PAIR_CASE(0, false)
@@ -434,12 +436,12 @@ hipError_t step_t(const Launch &g, int mode, bool has_s) {
     // periodic faces of the lattice's own axes (2-D: not the dummy X axis)
     const uint32_t per = p.permask & all_face_bits<L>();
     const bool pz = (mode == 0) ? per != 0 : (per & kZFaces) != 0;
-    if (g.force || pz) {
-        // body force and / or periodic Z faces: the one-cell-per-lane kernel
+    if (g.force || pz || g.kbc) {
+        // body force, periodic faces and / or KBC: the one-cell-per-lane kernel
         // with the storage type's default memory hints (plain for 2-byte
         // storage, non-temporal where aligned otherwise)
         constexpr int NTD = sizeof(ST) == 2 ? 0 : 1;
-        const int xf = (has_s ? 1 : 0) | (g.force ? 2 : 0) | (pz ? 4 : 0);
+        const int xf = (has_s ? 1 : 0) | (g.force ? 2 : 0) | (pz ? 4 : 0) | (g.kbc ? 8 : 0);
 #define LBM_XF_CASE(M, X)                                                                                    \
     if (mode == M && xf == X) {                                                                              \
         hipLaunchKernelGGL((k_step<L, ST, M, X, NTD>), dim3(g.grid), dim3(g.block), 0, g.stream, p, A, B); \
@@ -463,6 +465,20 @@ hipError_t step_t(const Launch &g, int mode, bool has_s) {
         LBM_XF_CASE(2, 5)
         LBM_XF_CASE(2, 6)
         LBM_XF_CASE(2, 7)
+        if constexpr (L::Q != 19) {
+            LBM_XF_CASE(0, 8)
+            LBM_XF_CASE(0, 10)
+            LBM_XF_CASE(0, 12)
+            LBM_XF_CASE(0, 14)
+            LBM_XF_CASE(1, 8)
+            LBM_XF_CASE(1, 10)
+            LBM_XF_CASE(1, 12)
+            LBM_XF_CASE(1, 14)
+            LBM_XF_CASE(2, 8)
+            LBM_XF_CASE(2, 10)
+            LBM_XF_CASE(2, 12)
+            LBM_XF_CASE(2, 14)
+        }
 #undef LBM_XF_CASE
         return hipErrorInvalidValue;
     }

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ESTATE, LBM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 D2Q9, D3Q19, D3Q27 = 0, 1, 2
 PERIODIC, WALL, ZOUHE_VELOCITY, ZOUHE_PRESSURE, EQ_OUTFLOW, REG_VELOCITY, REG_PRESSURE = 0, 1, 2, 3, 4, 5, 6
+BGK, KBC = 0, 1
 F64, F32, F16, BF16 = 0, 1, 2, 3
 INPLACE, DOUBLE = 0, 1
 
@@ -67,6 +68,7 @@ SIGNATURES = {
     "lbm_moments": (_i, [_vp, _vp, _vp, _i, _dp]),
     "lbm_forces": (_i, [_vp, _dp]),
     "lbm_set_force": (_i, [_vp, _dp, _vp, ctypes.c_double]),
+    "lbm_set_collision": (_i, [_vp, _i]),
     "lbm_tape_begin": (_i, [_vp, _i, _i]),
     "lbm_tape_end": (_i, [_vp]),
     "lbm_tape_free": (_i, [_vp]),
@@ -269,6 +271,11 @@ class Sim:
         out = (ctypes.c_double * 5)()
         check(lib().lbm_moments(self.h, None, None, F64, out))
         return np.array(list(out))
+
+    def set_collision(self, model):
+        """"BGK" / "KBC" (or LBM_BGK / LBM_KBC) for the following steps."""
+        m = {"BGK": BGK, "KBC": KBC}.get(model, model) if isinstance(model, str) else int(model)
+        check(lib().lbm_set_collision(self.h, m))
 
     def set_force(self, force=None, field=None, eps: float = 1.0):
         """Body force by the exact-difference method for the following steps:
