@@ -440,10 +440,71 @@ __device__ __forceinline__ void add_body_force(CT *hp, CT fx, CT fy, CT fz, CT r
     });
 }
 
-// Collision (eq. LBM-BGK) of the deviations h -> post-collision hp, returning
-// the moments (u without the force).  FRC: add the body force (fx, fy, fz)
-// before the partial bounce-back mix hp_i = (1 - s) h*_i + s h_opp(i).
-template <class L, bool FRC = false, class CT>
+// KBC collision (Karlin, Bosch & Chikatamarla 2014), D2Q9 / D3Q27: the
+// non-equilibrium part n = f - feq splits into a shear part ds -- the
+// deviatoric non-equilibrium momentum flux P carried by the axis velocities
+// ((P_aa - tr P / D) / 2 each) and the face diagonals (c_a c_b P_ab / 4) -- and
+// the rest dh = n - ds; then
+//   f*_i = f_i - beta (2 ds_i + gamma dh_i),  beta = omega / 2,
+//   gamma = 1/beta - (2 - 1/beta) <ds|dh> / <dh|dh>,  <x|y> = sum x_i y_i / feq_i
+// (gamma = 2, i.e. BGK, when dh = 0).  In deviation variables n_i = h_i - heq_i.
+template <class L, class CT>
+__device__ __forceinline__ void kbc_relax(const CT *h, CT *hp, const Params<CT> &p, CT drho, CT rho, CT ux, CT uy,
+                                          CT uz, CT usq15) {
+    constexpr int Q = L::Q;
+    CT e[Q];
+    unroll<Q>([&](auto I) { e[I] = heq<L, I>(drho, rho, ux, uy, uz, usq15); });
+    CT P00 = 0, P11 = 0, P22 = 0, P01 = 0, P02 = 0, P12 = 0;
+    unroll<Q>([&](auto I) {
+        constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
+        const CT n = h[I] - e[I];
+        if constexpr (cx != 0) P00 += n;
+        if constexpr (cy != 0) P11 += n;
+        if constexpr (cz != 0) P22 += n;
+        if constexpr (cx * cy != 0) P01 += (CT)(cx * cy) * n;
+        if constexpr (cx * cz != 0) P02 += (CT)(cx * cz) * n;
+        if constexpr (cy * cz != 0) P12 += (CT)(cy * cz) * n;
+    });
+    const CT trD = (P00 + P11 + P22) * (CT)(1.0 / L::D);
+    CT sh = 0, hh = 0;
+    CT ds[Q];
+    unroll<Q>([&](auto I) {
+        constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
+        constexpr int nzc = (cx != 0) + (cy != 0) + (cz != 0);
+        CT v = 0;
+        if constexpr (nzc == 1) {
+            const CT Paa = (cx != 0) ? P00 : ((cy != 0) ? P11 : P22);
+            v = (CT)0.5 * (Paa - trD);
+        } else if constexpr (nzc == 2) {
+            const CT Pab = (cz == 0) ? P01 : ((cy == 0) ? P02 : P12);
+            constexpr int sgn = (cz == 0) ? cx * cy : ((cy == 0) ? cx * cz : cy * cz);
+            v = (CT)(0.25 * sgn) * Pab;
+        }
+        ds[I] = v;
+        const CT dh = (h[I] - e[I]) - v;
+        // entropic weights 1 / feq_i: the hardware reciprocal in FP32 (the
+        // weights only scale the two scalar products)
+        const CT feq = e[I] + (CT)weight<L>(I) * p.rho0;
+        CT inv_feq;
+        if constexpr (sizeof(CT) == 4) inv_feq = __builtin_amdgcn_rcpf(feq);
+        else inv_feq = (CT)1 / feq;
+        sh += v * dh * inv_feq;
+        hh += dh * dh * inv_feq;
+    });
+    const CT beta = (CT)0.5 * p.omega;
+    const CT ib = (CT)1 / beta;
+    const CT gamma = (hh > (CT)0) ? ib - ((CT)2 - ib) * sh / hh : (CT)2;
+    unroll<Q>([&](auto I) {
+        const CT dh = (h[I] - e[I]) - ds[I];
+        hp[I] = h[I] - beta * ((CT)2 * ds[I] + gamma * dh);
+    });
+}
+
+// Collision (eq. LBM-BGK; KB: the KBC collision above) of the deviations h ->
+// post-collision hp, returning the moments (u without the force).  FRC: add
+// the body force (fx, fy, fz) before the partial bounce-back mix
+// hp_i = (1 - s) h*_i + s h_opp(i).
+template <class L, bool FRC = false, bool KB = false, class CT>
 __device__ __forceinline__ void collide(const CT *h, CT *hp, const Params<CT> &p, CT s, bool has_s,
                                         CT &rho_out, CT &ux, CT &uy, CT &uz, CT fx = 0, CT fy = 0, CT fz = 0) {
     CT drho = 0, jx = 0, jy = 0, jz = 0;
@@ -460,10 +521,14 @@ __device__ __forceinline__ void collide(const CT *h, CT *hp, const Params<CT> &p
     uz = jz * inv;
     const CT usq15 = (CT)1.5 * (ux * ux + uy * uy + uz * uz);
     const CT om = p.omega;
-    unroll<L::Q>([&](auto I) {
-        const CT e = heq<L, I>(drho, rho, ux, uy, uz, usq15);
-        hp[I] = h[I] - om * (h[I] - e);
-    });
+    if constexpr (KB) {
+        kbc_relax<L>(h, hp, p, drho, rho, ux, uy, uz, usq15);
+    } else {
+        unroll<L::Q>([&](auto I) {
+            const CT e = heq<L, I>(drho, rho, ux, uy, uz, usq15);
+            hp[I] = h[I] - om * (h[I] - e);
+        });
+    }
     if constexpr (FRC) add_body_force<L>(hp, fx, fy, fz, rho, inv, ux, uy, uz);
     if (has_s) {
         CT t[L::Q];
