@@ -291,7 +291,7 @@ def channel_spheres_figures(torch, lbm, steps=50):
 
 
 def forced_channel_figures(torch, lbm, steps=100, adj_steps=40, K=10):
-    """Force-driven channel (the paper's turbulent-channel setup, Sec. 6.2):
+    """Force-driven channel (the paper's turbulent-channel setup, Sec. 4.4):
     D3Q19 FP32, walls 2h apart in y, periodic streamwise (6h) and spanwise (3h),
     h = 128 (768 x 256 x 384 cells), driven by F_x = Re_tau^2 nu^2 / h^3 at
     Re_tau = 180 through the exact-difference method; once as a uniform force,

@@ -233,7 +233,7 @@ int lbm_moments(lbm_ctx *ctx, void *rho, void *u, int dtype, double *sums_host);
 /*
  * Momentum-exchange force (Ladd) of the most recent step: the momentum the
  * fluid handed to the solid cells and to each wall face while streaming into
- * them -- the drag / lift sums of the paper's obstacle flows (Sec. 4.4).  For
+ * them -- the drag / lift sums of the paper's obstacle flows (Sec. 4.3).  For
  * every fluid cell x and direction i whose neighbour x + c_i is solid or
  * across a wall face, the link contributes (f°_i(x, t) + f_opp(i)(x, t+1)) c_i,
  * with f_opp(i)(x, t+1) = f°_i + 6 w_opp rho0 (c_opp . u_w).  In a closed domain
@@ -249,7 +249,7 @@ int lbm_moments(lbm_ctx *ctx, void *rho, void *u, int dtype, double *sums_host);
 int lbm_forces(lbm_ctx *ctx, double *out);
 
 /*
- * Body force by the exact-difference method (Sec. 6.2, after Kupershtokh, the
+ * Body force by the exact-difference method (Sec. 4.4 and 6.1, after Kupershtokh, the
  * forcing of the paper's turbulent channel and of its neural corrector): from
  * the next step on, every fluid cell's relaxed populations gain
  * feq_i(rho, u + eps F / rho) - feq_i(rho, u), before any partial bounce-back
@@ -273,9 +273,9 @@ int lbm_forces(lbm_ctx *ctx, double *out);
 int lbm_set_force(lbm_ctx *ctx, const double *force, const void *field, double eps);
 
 /*
- * Collision model for the following steps (Sec. 3.2 lists BGK and KBC; the
- * paper runs KBC on D2Q9 and D3Q27).  LBM_KBC (Karlin, Bosch & Chikatamarla
- * 2014): f - feq splits into a shear part ds -- the deviatoric non-equilibrium
+ * Collision model for the following steps (Sec. 2 lists BGK, MRT, cumulant,
+ * regularized and KBC collisions; Sec. 4 runs KBC on D2Q9 and D3Q27).
+ * LBM_KBC (Karlin, Bosch & Chikatamarla 2014): f - feq splits into a shear part ds -- the deviatoric non-equilibrium
  * momentum flux P, carried by the axis velocities ((P_aa - tr P / D) / 2 each)
  * and the face diagonals (c_a c_b P_ab / 4) -- and the rest dh; the step takes
  * f*_i = f_i - beta (2 ds_i + gamma dh_i), beta = 1 / (2 tau),
@@ -322,7 +322,7 @@ int lbm_backward(lbm_ctx *ctx, const void *dL_drho, const void *dL_du, int dtype
 
 /*
  * lbm_backward plus the gradients with respect to the body force of
- * lbm_set_force (Sec. 6.2: training a corrector force through unrolled steps):
+ * lbm_set_force (Sec. 6.1: training a corrector force through unrolled steps):
  *   dL_dfield : device pointer or NULL: D x N values of `dtype` (component-
  *               major, caller axes, the field's layout), overwritten with
  *               dL/dfield(x) = eps sum_t sum_i lambda_i dfeq_i/dm at

@@ -150,10 +150,10 @@ void orc_cell_moments(int q, const double *f, double *rho, double *u)
 
 /* eq. (LBM-BGK) with dt = 1: f* = f - (1/tau)(f - feq).  The force hook adds
  * 3 w_i (c_i . F) after relaxation (oracle test hook only).  A body force F
- * by the exact-difference method (Sec. 6.2, after Kupershtokh) adds
+ * by the exact-difference method (Sec. 4.4 and 6.1, after Kupershtokh) adds
  * feq_i(rho, u + F/rho) - feq_i(rho, u) to the relaxed populations. */
-/* KBC collision (Karlin, Bosch & Chikatamarla 2014; the paper's collision for
- * its D2Q9 / D3Q27 runs, Sec. 3.2).  f - feq splits into a shear part ds,
+/* KBC collision (Karlin, Bosch & Chikatamarla 2014; listed in Sec. 2, the
+ * paper's collision for its D2Q9 / D3Q27 runs of Sec. 4).  f - feq splits into a shear part ds,
  * built from the deviatoric non-equilibrium momentum flux on the axis and
  * face-diagonal velocities only (zero mass, momentum and trace), and the rest
  * dh:
@@ -814,7 +814,7 @@ int orc_adjoint_step(const orc_sim *S, const double *f, const double *a_next, do
 
 /*
  * Momentum-exchange force (Ladd 1994) of the step that produced f (= f(t+1)),
- * the drag / lift sums of the paper's obstacle flows (Sec. 4.4).  For every
+ * the drag / lift sums of the paper's obstacle flows (Sec. 4.3).  For every
  * fluid cell x and direction i whose neighbour x + c_i is a solid cell or
  * lies across a wall face, the post-collision population f°_i(x, t) left
  * along c_i and came back as f_opp(i)(x, t + 1) = f°_i + 6 w_opp rho0

@@ -412,7 +412,7 @@ __device__ __forceinline__ int zh_face_of(const Params<CT> &p, uint32_t e) {
     return (int)__builtin_ctz(z);
 }
 
-// Body force by the exact-difference method (Sec. 6.2, after Kupershtokh):
+// Body force by the exact-difference method (Sec. 4.4 and 6.1, after Kupershtokh):
 // hp_i += feq_i(rho, u + du) - feq_i(rho, u), du = F / rho, written as
 // w_i rho [3 c.du + 4.5 (c.du)(c.(u + u')) - 1.5 du.(u + u')] with
 // u' = u + du, which has no cancellation between two equilibria.

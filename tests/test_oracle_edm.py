@@ -1,5 +1,5 @@
 """Pins of the oracle's body force by the exact-difference method (paper
-Sec. 6.2, after Kupershtokh): the relaxed populations gain
+Sec. 4.4 and 6.1, after Kupershtokh): the relaxed populations gain
 feq_i(rho, u + F/rho) - feq_i(rho, u).
 
 * Uniform force on a uniform rest state, periodic box: BGK keeps an
