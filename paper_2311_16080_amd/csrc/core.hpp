@@ -113,11 +113,8 @@ template <>
 struct Store<bf16_t> {
     using CT = float;
     static constexpr bool scaled = true;
-    __device__ static uint16_t round(float v) {
-        uint32_t u = __float_as_uint(v);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
-        return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);                  // nearest even
-    }
+    // round to nearest even: gfx950's conversion instruction (v_cvt_pk_bf16_f32)
+    __device__ static uint16_t round(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
     __device__ static float ld(const bf16_t *p) { return __uint_as_float(((uint32_t)p->bits) << 16); }
     __device__ static void st(bf16_t *p, float v) { p->bits = round(v); }
     __device__ static float ldn(const bf16_t *p) {
