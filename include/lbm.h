@@ -262,7 +262,8 @@ int lbm_forces(lbm_ctx *ctx, double *out);
  *           FP16 / BF16 storage, double for FP64 storage.  Read by every later
  *           step: the caller keeps it allocated until the force is replaced
  *           or the context destroyed, and may update it between steps on the
- *           context's stream.
+ *           context's stream.  While a field is set, lbm_set_options may not
+ *           change the compute type (LBM_ESTATE).
  *   eps   : scale on both parts (the paper's epsilon; 1 for a plain force).
  * A zero force with no field (or eps = 0) switches the force off.  The taped
  * adjoint (lbm_backward, lbm_backward_force) differentiates through the force

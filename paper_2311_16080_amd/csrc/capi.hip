@@ -308,6 +308,9 @@ extern "C" int lbm_set_options(lbm_ctx *c, const lbm_options *o) {
     if (o->pattern != LBM_INPLACE && o->pattern != LBM_DOUBLE) return fail(LBM_EINVAL, "unknown pattern %d", o->pattern);
     if (!(o->rho0 > 0.0) || !std::isfinite(o->rho0)) return fail(LBM_EINVAL, "rho0 must be > 0");
     if (c->batch && o->pattern != LBM_INPLACE) return fail(LBM_EUNSUPPORTED, "batch contexts use the in-place pattern");
+    // a force field set earlier is typed by the compute type
+    if (c->force_field && o->compute != c->opt.compute)
+        return fail(LBM_ESTATE, "the compute type cannot change while a force field is set (lbm_set_force)");
     c->opt = *o;
     refresh_params(c);
     return LBM_OK;

@@ -127,3 +127,39 @@ def test_copy_probe_rejects_misaligned():
 def test_binding_raises_on_bad_create():
     with pytest.raises(lbm.LbmError):
         lbm.Sim("D3Q19", (8, 8, 8), tau=0.4)
+
+
+def test_force_collision_and_face_checks_without_device():
+    """lbm_set_force / lbm_set_collision validate and record on the host; a set
+    field pins the compute type; regularized face types are accepted."""
+    L = lbm.lib()
+    h = ctypes.c_void_p(L.lbm_create(lbm.D3Q19, 8, 8, 8, 0.7, None))
+    assert h
+    nan3 = (ctypes.c_double * 3)(float("nan"), 0.0, 0.0)
+    assert L.lbm_set_force(h, nan3, None, 1.0) == lbm.LBM_EINVAL
+    ok3 = (ctypes.c_double * 3)(1e-5, 0.0, 0.0)
+    assert L.lbm_set_force(h, ok3, None, float("inf")) == lbm.LBM_EINVAL
+    # a (never dereferenced) field pointer: the compute type is now fixed
+    assert L.lbm_set_force(h, ok3, ctypes.c_void_p(4096), 1.0) == lbm.LBM_OK
+    f64 = lbm.lbm_options(lbm.F64, lbm.F64, lbm.INPLACE, 0, 1.0)
+    assert L.lbm_set_options(h, ctypes.byref(f64)) == lbm.LBM_ESTATE
+    f16 = lbm.lbm_options(lbm.F16, lbm.F32, lbm.INPLACE, 0, 1.0)
+    assert L.lbm_set_options(h, ctypes.byref(f16)) == lbm.LBM_OK
+    assert L.lbm_set_force(h, None, None, 1.0) == lbm.LBM_OK          # off
+    assert L.lbm_set_options(h, ctypes.byref(f64)) == lbm.LBM_OK
+    assert L.lbm_set_collision(h, lbm.KBC) == lbm.LBM_EUNSUPPORTED      # D3Q19
+    assert L.lbm_set_collision(h, 3) == lbm.LBM_EINVAL
+    assert L.lbm_set_collision(h, lbm.BGK) == lbm.LBM_OK
+    L.lbm_destroy(h)
+    h = ctypes.c_void_p(L.lbm_create(lbm.D3Q27, 8, 8, 8, 0.7, None))
+    assert L.lbm_set_collision(h, lbm.KBC) == lbm.LBM_OK
+    L.lbm_destroy(h)
+    faces = [(lbm.REG_VELOCITY, (0.02, 0, 0)), (lbm.REG_PRESSURE, (0, 0, 0), 1.0), lbm.WALL, lbm.WALL, 0, 0]
+    h = L.lbm_create(lbm.D3Q19, 8, 8, 8, 0.7, _bc(faces))
+    assert h
+    L.lbm_destroy(ctypes.c_void_p(h))
+    bad = [(lbm.REG_PRESSURE, (0, 0, 0), 0.0), lbm.WALL, 0, 0, 0, 0]
+    assert not L.lbm_create(lbm.D3Q19, 8, 8, 8, 0.7, _bc(bad))
+    assert "density" in lbm.last_error()
+    assert not L.lbm_create(lbm.D3Q19, 8, 8, 8, 0.7, _bc([(7,), lbm.WALL, 0, 0, 0, 0]))
+    assert "unknown boundary type" in lbm.last_error()
