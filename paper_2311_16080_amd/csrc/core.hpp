@@ -463,21 +463,25 @@ __device__ __forceinline__ void kbc_relax(const CT *h, CT *hp, const Params<CT> 
         if constexpr (cy * cz != 0) P12 += (CT)(cy * cz) * n;
     });
     const CT trD = (P00 + P11 + P22) * (CT)(1.0 / L::D);
-    CT sh = 0, hh = 0;
-    CT ds[Q];
-    unroll<Q>([&](auto I) {
+    // shear part of direction I (recomputed where needed: a handful of operations
+    // instead of Q more live registers)
+    auto shear = [&](auto I) -> CT {
         constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
         constexpr int nzc = (cx != 0) + (cy != 0) + (cz != 0);
-        CT v = 0;
         if constexpr (nzc == 1) {
             const CT Paa = (cx != 0) ? P00 : ((cy != 0) ? P11 : P22);
-            v = (CT)0.5 * (Paa - trD);
+            return (CT)0.5 * (Paa - trD);
         } else if constexpr (nzc == 2) {
             const CT Pab = (cz == 0) ? P01 : ((cy == 0) ? P02 : P12);
             constexpr int sgn = (cz == 0) ? cx * cy : ((cy == 0) ? cx * cz : cy * cz);
-            v = (CT)(0.25 * sgn) * Pab;
+            return (CT)(0.25 * sgn) * Pab;
+        } else {
+            return (CT)0;
         }
-        ds[I] = v;
+    };
+    CT sh = 0, hh = 0;
+    unroll<Q>([&](auto I) {
+        const CT v = shear(I);
         const CT dh = (h[I] - e[I]) - v;
         // entropic weights 1 / feq_i: the hardware reciprocal in FP32 (the
         // weights only scale the two scalar products)
@@ -492,8 +496,9 @@ __device__ __forceinline__ void kbc_relax(const CT *h, CT *hp, const Params<CT> 
     const CT ib = (CT)1 / beta;
     const CT gamma = (hh > (CT)0) ? ib - ((CT)2 - ib) * sh / hh : (CT)2;
     unroll<Q>([&](auto I) {
-        const CT dh = (h[I] - e[I]) - ds[I];
-        hp[I] = h[I] - beta * ((CT)2 * ds[I] + gamma * dh);
+        const CT v = shear(I);
+        const CT dh = (h[I] - e[I]) - v;
+        hp[I] = h[I] - beta * ((CT)2 * v + gamma * dh);
     });
 }
 
