@@ -125,14 +125,16 @@ def compare(case: Case, g, o):
 
 
 def cone_oracle(q: int, shape, tau: float, faces, center, nsteps: int, init_seed: int, solid=None,
-                margin: int = 2, amp: float = 0.03):
+                margin: int = 2, amp: float = 0.03, force=None, collision: int = 0):
     """Oracle (rho, u[3]) at one cell after `nsteps` steps of a run on the full
     grid `shape`, computed on the cell's light cone only: a step moves
     information one cell, so a sub-box reaching nsteps + margin cells around
     the cell gives the full-grid result at its centre.  The sub-box keeps the
     grid's own faces where it reaches them, wraps around periodic axes, and
     has static walls on its cut faces.  The initial state is the seeded wave
-    field (inputs.wave_field, periodic on the full grid) on the sub-box."""
+    field (inputs.wave_field, periodic on the full grid) on the sub-box.
+    force: a uniform body force (exact-difference method); collision: the
+    oracle's collision model."""
     D = 2 if q == 9 else 3
     r = nsteps + margin
     lo, sub, of = [], [], []
@@ -160,7 +162,12 @@ def cone_oracle(q: int, shape, tau: float, faces, center, nsteps: int, init_seed
         for a in range(D):
             sol = np.take(sol, np.arange(lo[a], lo[a] + sub[a]), axis=a, mode="wrap")
         sol = np.ascontiguousarray(sol).reshape(osub).astype(np.uint8)
-    S = oracle.Sim(q=q, nx=osub[0], ny=osub[1], nz=osub[2], tau=tau, faces=of, solid=sol)
+    edm = None
+    if force is not None:
+        edm = np.zeros(osub + (3,))
+        edm[...] = np.asarray(list(force) + [0.0] * (3 - len(force)))
+    S = oracle.Sim(q=q, nx=osub[0], ny=osub[1], nz=osub[2], tau=tau, faces=of, solid=sol, edm=edm,
+                   collision=collision)
     rho, u = inputs.wave_field(tuple(shape), init_seed, lo=lo, sub=sub, amp=amp)
     f = S.equilibrium_state(rho=rho.reshape(osub), u=u.reshape(osub + (D,)))
     S.run(f, nsteps)
