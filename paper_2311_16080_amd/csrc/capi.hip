@@ -279,6 +279,8 @@ extern "C" lbm_ctx *lbm_create(int lattice, int nx, int ny, int nz, double tau, 
         if (pr && pr[0] >= '0' && pr[0] <= '2') c->pair = pr[0] - '0';
         const char *zr = std::getenv("LBM_ZROT");
         if (zr && (zr[0] == '0' || zr[0] == '1')) c->zrot = zr[0] - '0';
+        const char *wo = std::getenv("LBM_WALLS_ONLY");
+        if (wo && (wo[0] == '0' || wo[0] == '1')) c->walls_only = wo[0] - '0';
         const char *bl = std::getenv("LBM_BLOCK");
         if (bl) {
             const int v = std::atoi(bl);
@@ -477,6 +479,7 @@ Launch lbm::make_launch(lbm_ctx *c) {
     g.pgrid = g.pblock = 0;
     g.force = c->force_on ? 1 : 0;
     g.kbc = c->collision == LBM_KBC ? 1 : 0;
+    g.walls_only = c->walls_only;
     if (g.force || g.kbc) return g;   // these run on the one-cell-per-lane kernel
     // two cells per lane for 2-byte storage: rows of nZ % 128 == 0 cells, no
     // lane rotation or XCD remap (the pair kernel's row mapping is fixed)

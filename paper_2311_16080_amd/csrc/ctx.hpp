@@ -63,6 +63,7 @@ struct lbm_ctx {
     lbm::FaceTab<float> *ftf = nullptr;
 
     int collision = 0;                     // LBM_BGK / LBM_KBC
+    int walls_only = 1;                    // LBM_WALLS_ONLY = 0 / 1
 
     // body force (exact-difference method)
     bool force_on = false;

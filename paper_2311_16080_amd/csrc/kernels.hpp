@@ -29,6 +29,7 @@ struct Launch {
     unsigned pblock;
     int force;           // body force on (params carry it)
     int kbc;             // KBC collision
+    int walls_only;      // allow the walls-only step variant (LBM_WALLS_ONLY = 0 disables it, for measurement)
 };
 
 hipError_t launch_step(const Launch &g, int mode, bool has_s);
