@@ -431,7 +431,8 @@ def rollout(sim: "Sim", nsteps: int, K: int, s=None, tau=None, rho0=None, u0=Non
     checkpoint every K steps, returns (rho, u) of the final state.  Gradients
     flow to the solid fraction `s` (device tensor), `tau` (0-d tensor) and a
     body-force field `field` (device tensor (D, *shape), applied with scale eps
-    by the exact-difference method) through the library's adjoint."""
+    by the exact-difference method) through the library's adjoint.  A given
+    field stays set on `sim` afterwards (the backward pass needs it)."""
     torch = _torch()
     if tau is None:
         tau = torch.tensor(sim.tau, dtype=torch.float64)
