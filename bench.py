@@ -19,6 +19,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -57,24 +58,87 @@ def cavity_faces(lbm, U=0.05):
     return [(lbm.WALL,)] * 5 + [(lbm.WALL, (U, 0.0, 0.0))]
 
 
-def cpu_baseline(n: int, tau: float, target_s: float = 15.0):
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(n: int, tau: float, target_s: float = 10.0, n_one: int = 128):
     """FP64 oracle on the same cavity, timed on the host for a bounded number
-    of steps (about target_s seconds of work)."""
+    of steps (about target_s seconds of work): once with every OpenMP thread
+    the process may use (`value`, `cores`), once on one thread (a 128^3 cavity,
+    whose state is still far beyond the caches)."""
     import oracle
     faces = [oracle.Face(oracle.WALL) for _ in range(6)]
     faces[5] = oracle.Face(oracle.WALL, (0.05, 0.0, 0.0))
-    S = oracle.Sim(q=19, nx=n, ny=n, nz=n, tau=tau, faces=faces)
-    f = S.equilibrium_state()
-    t0 = time.perf_counter()
-    S.run(f, 1)
-    dt1 = time.perf_counter() - t0
-    k = max(1, min(50, int(target_s / max(dt1, 1e-3))))
-    t0 = time.perf_counter()
-    S.run(f, k)
-    dt = time.perf_counter() - t0
-    mlups = n ** 3 * k / dt / 1e6
-    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"D3Q19 FP64 cavity {n}^3, {k} steps after 1 warm-up step ({dt:.1f} s)"}
+
+    def timed(m, threads):
+        oracle.set_num_threads(threads)
+        S = oracle.Sim(q=19, nx=m, ny=m, nz=m, tau=tau, faces=faces)
+        f = S.equilibrium_state()
+        t0 = time.perf_counter()
+        S.run(f, 1)
+        dt1 = time.perf_counter() - t0
+        k = max(1, min(50, int(target_s / max(dt1, 1e-3))))
+        t0 = time.perf_counter()
+        S.run(f, k)
+        dt = time.perf_counter() - t0
+        return m ** 3 * k / dt / 1e6, k, dt, oracle.num_threads()
+
+    threads = oracle.num_threads()
+    v_all, k_all, dt_all, used = timed(n, threads)
+    v_one, k_one, dt_one, _ = timed(n_one, 1)
+    oracle.set_num_threads(threads)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
+    return {"value": round(v_all, 3), "unit": "MLUPS", "cores": used, "kind": "oracle",
+            "sample": f"D3Q19 FP64 cavity {n}^3, {k_all} steps after 1 warm-up step ({dt_all:.1f} s) on "
+                      f"{used} OpenMP threads; one-thread figure: {n_one}^3, {k_one} steps ({dt_one:.1f} s)",
+            "one_core_MLUPS": round(v_one, 3), "nproc": os.cpu_count(), "affinity_cpus": affinity,
+            "cpu_model": _cpu_model()}
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def _golden(name):
+    """Stored oracle results (written by tests/golden/make_golden.py), or None."""
+    path = os.path.join(GOLDEN, name)
+    return np.load(path) if os.path.exists(path) else None
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def cavity_error_vs_oracle(torch, lbm, storage, n=256, steps=1000):
+    """u after 1000 steps of the cavity from rest against the stored FP64
+    oracle run: rel-L2 over the whole planes y = n/2 and x = n/2."""
+    ref = _golden("cavity256_d3q19_1000.npz")
+    if ref is None or n != 256:
+        return None
+    sim = lbm.Sim("D3Q19", (n, n, n), 0.55, faces=cavity_faces(lbm), storage=storage)
+    sim.use_current_stream()
+    sim.init_equilibrium()
+    sim.step(steps)
+    _, u = sim.moments(dtype=torch.float64)
+    st = int(ref["stride"])
+    out = {"steps": steps}
+    py = torch.stack([u[a, ::st, n // 2, ::st] for a in range(3)], -1).cpu().numpy()
+    out["u_rel_l2_y128"] = _rel(py, ref["u_y128"])
+    if "u_x128" in ref.files:
+        px = torch.stack([u[a, n // 2, :, :] for a in range(3)], -1).cpu().numpy()
+        out["u_rel_l2_x128"] = _rel(px, ref["u_x128"])
+    del sim
+    return out
 
 
 class Timer:
@@ -112,6 +176,7 @@ def storage_variants(torch, lbm, n, tau, steps):
         out[st] = {"MLUPS": round(mlups, 1), "GBps": round(gbps, 1), "frac": round(gbps / PEAK_HBM_GBPS, 4),
                    "bytes_per_lattice_update": 2 * 19 * es, "steps": steps}
         del sim
+        out[st]["error_vs_oracle"] = cavity_error_vs_oracle(torch, lbm, st, n)
     return out
 
 
@@ -136,12 +201,33 @@ def adjoint_ratio(torch, lbm, name, make_sim, nsteps, K, loss):
     rho, u = sim.moments(dtype=torch.float32)
     g_rho, g_u = loss(rho, u)
     with Timer(torch) as B:
-        sim.backward(g_rho, g_u, want_s=getattr(sim, "_has_s", False))
+        ds, dtau, _ = sim.backward(g_rho, g_u, want_s=getattr(sim, "_has_s", False))
     sim.tape_free()
     del sim
-    return {"workload": name, "steps": nsteps, "K": K, "forward_ms": round(F.ms, 3),
-            "forward_taped_ms": round(R.ms, 3), "backward_ms": round(B.ms, 3),
-            "ratio": round(B.ms / F.ms, 3)}
+    out = {"workload": name, "steps": nsteps, "K": K, "forward_ms": round(F.ms, 3),
+           "forward_taped_ms": round(R.ms, 3), "backward_ms": round(B.ms, 3),
+           "ratio": round(B.ms / F.ms, 3), "dL_dtau": float(dtau[0])}
+    if ds is not None:
+        out["dL_ds"] = ds.double().cpu().numpy()
+    return out
+
+
+def c4_faces(lbm):
+    return [(lbm.ZOUHE_VELOCITY, (0.04, 0.0)), (lbm.EQ_OUTFLOW, (0.0, 0.0), 1.0), (lbm.WALL,), (lbm.WALL,),
+            (lbm.PERIODIC,), (lbm.PERIODIC,)]
+
+
+def c4_target(torch, lbm):
+    """u_T = u(500) of the channel with the solid fraction from seed 40 (FP64 run on the GPU)."""
+    from paper_2311_16080_amd import inputs
+    sim = lbm.Sim("D2Q9", (512, 256), 0.6, faces=c4_faces(lbm), storage="f64")
+    sim.use_current_stream()
+    sim.set_solid_fraction(inputs.smooth_solid_fraction(512, 256, seed=40))
+    sim.init_equilibrium()
+    sim.step(500)
+    _, u = sim.moments(dtype=torch.float32)
+    del sim
+    return u
 
 
 def adjoint_figures(torch, lbm):
@@ -149,19 +235,24 @@ def adjoint_figures(torch, lbm):
     res = []
 
     def c4():
-        sim = lbm.Sim("D2Q9", (512, 256), 0.6, faces=[(lbm.ZOUHE_VELOCITY, (0.04, 0.0)),
-                                                     (lbm.EQ_OUTFLOW, (0.0, 0.0), 1.0), (lbm.WALL,), (lbm.WALL,),
-                                                     (lbm.PERIODIC,), (lbm.PERIODIC,)], storage="f32")
+        sim = lbm.Sim("D2Q9", (512, 256), 0.6, faces=c4_faces(lbm), storage="f32")
         sim.set_solid_fraction(inputs.smooth_solid_fraction(512, 256, seed=4))
         sim._has_s = True
         return sim
 
+    tgt = c4_target(torch, lbm)
+
     def l2(rho, u):
-        tgt = torch.zeros_like(u)
         return None, 2.0 * (u - tgt)
 
-    res.append(adjoint_ratio(torch, lbm, "D2Q9 FP32 512x256 channel, partial bounce-back s field, u-mismatch loss",
-                             c4, 500, 50, l2))
+    r = adjoint_ratio(torch, lbm, "D2Q9 FP32 512x256 channel, partial bounce-back s field, u-mismatch loss "
+                                  "against the seed-40 run (C4)", c4, 500, 50, l2)
+    ref = _golden("c4_adjoint_d2q9_512x256.npz")
+    if ref is not None and "dL_ds" in r:
+        r["error_vs_oracle"] = {"dL_ds_rel_l2": _rel(r.pop("dL_ds"), ref["dlds"].astype(np.float64)),
+                                "dL_dtau_rel": abs(r["dL_dtau"] - float(ref["dtau"])) / abs(float(ref["dtau"]))}
+    r.pop("dL_ds", None)
+    res.append(r)
 
     def cav3():
         return lbm.Sim("D3Q19", (256, 256, 256), 0.55, faces=cavity_faces(lbm), storage="f32")
@@ -205,6 +296,22 @@ def batch_figures(torch, lbm, steps=2000):
     out["tile"] = tile
     out["persistent"] = pers
     out["effective_GBps"] = round(out["graph_MLUPS"] * 1e6 * 72 / 1e9, 1)
+    # both launch modes at the chosen tile, each captured as one graph of all steps
+    modes = {}
+    for mode in (1, 0):
+        bs.tuning(tile, mode)
+        bs.init_equilibrium()
+        bs.capture_graph(steps)
+        bs.graph_launch()
+        with Timer(torch) as M:
+            bs.graph_launch()
+        modes["persistent_one_launch" if mode else "one_launch_per_step"] = {
+            "MLUPS": round(N * steps / (M.ms / 1e3) / 1e6, 1), "graph_ms": round(M.ms, 2)}
+    out["launch_modes"] = modes
+    bs.tuning(tile, pers)
+    bs.init_equilibrium()
+    bs.capture_graph(steps)
+    bs.graph_launch()
     # unstable domains: non-finite or |u| above 0.3 anywhere
     rho, u = bs.moments(dtype=torch.float32)
     speed = torch.sqrt((u * u).sum(0))
@@ -256,6 +363,14 @@ def batch_figures(torch, lbm, steps=2000):
                       "ratio_vs_graph_forward": round(B.ms / G.ms, 3),
                       "dE_dtau_first4": [float(v) for v in dtau[:4]],
                       "dE_dU_first4": [float(duw[d, 3, 0]) for d in range(4)]}
+    ref = _golden("c5_gradients_d2q9.npz")
+    if ref is not None and int(ref["steps"]) == steps:
+        pick = [int(d) for d in ref["domains"]]
+        e_tau = max(abs(float(dtau[d]) - float(ref["dtau"][k])) / abs(float(ref["dtau"][k]))
+                    for k, d in enumerate(pick))
+        e_u = max(abs(float(duw[d, 3, 0]) - float(ref["dU"][k])) / abs(float(ref["dU"][k]))
+                  for k, d in enumerate(pick))
+        out["adjoint"]["error_vs_oracle"] = {"domains": pick, "dE_dtau_max_rel": e_tau, "dE_dU_max_rel": e_u}
     return out
 
 
@@ -287,6 +402,23 @@ def channel_spheres_figures(torch, lbm, steps=50):
            "sphere_generation_s": round(gen_s, 1), "forces_ms": round(FT.ms, 3),
            "sphere_force": [float(v) for v in Fs]}
     del sim
+    # the same generator at 256 x 128 x 128 (radii 2..8), 300 steps, against the stored oracle plane z = 64
+    ref = _golden("channel_spheres_d3q27_300.npz")
+    if ref is not None:
+        rs = (256, 128, 128)
+        sol = inputs.sphere_obstacles(*rs, seed=3, rmin=2.0, rmax=8.0, xlo=16, xhi=240, fraction=0.05)
+        sim = lbm.Sim("D3Q27", rs, 0.6, faces=faces, storage="f32", pattern="inplace")
+        sim.use_current_stream()
+        sim.set_solid(sol)
+        sim.init_equilibrium()
+        sim.step(int(ref["steps"]))
+        _, u = sim.moments(dtype=torch.float64)
+        st = int(ref["stride"])
+        pl = torch.stack([u[a, ::st, ::st, rs[2] // 2] for a in range(3)], -1).cpu().numpy()
+        m = ~ref["solid_z64"].astype(bool)
+        res["error_vs_oracle"] = {"shape": list(rs), "steps": int(ref["steps"]),
+                                  "u_rel_l2_z64": _rel(pl[m], ref["u_z64"][m])}
+        del sim
     return res
 
 
@@ -482,6 +614,9 @@ def main():
                      "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": traffic,
                      "bytes_per_lattice_update": 2 * Q * esize},
     }
+
+    if lat == "D3Q19" and n == 256:
+        out["error_vs_oracle"] = cavity_error_vs_oracle(torch, lbm, args.storage, n)
 
     if not args.no_copy:
         # achievable HBM copy bandwidth (bandwidth probe), same stream

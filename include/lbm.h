@@ -183,11 +183,19 @@ int lbm_set_options(lbm_ctx *ctx, const lbm_options *opt);
  */
 int lbm_set_params(lbm_ctx *ctx, double tau, const lbm_bc *bc);
 
-/* hip_stream: a hipStream_t (NULL = the null stream). */
+/*
+ * The HIP stream that orders every later call of this context (the paper
+ * leaves ordering and asynchronous dispatch of `step` to JAX, Sec. 3.1; here
+ * the caller names the stream, normally torch's current one).
+ * hip_stream: a hipStream_t (NULL = the null stream); not owned.  Drops a
+ * captured graph.  LBM_EINVAL for a NULL context.
+ */
 int lbm_set_stream(lbm_ctx *ctx, void *hip_stream);
 
 /*
- * Solid cells (interior obstacles; bounce-back at their faces).  flags: N
+ * Solid cells: the solid part of the boundary mask of Sec. 3.5 (interior
+ * obstacles; a fluid cell whose neighbour x - c_i is solid takes f_i by
+ * halfway bounce-back, Fig. "mask").  flags: N
  * bytes, nonzero = solid; host (on_device = 0) or device (1).  Copied.  NULL
  * clears.  Valid before or after init; solid cells report rho0, u = 0.
  */
@@ -289,7 +297,9 @@ int lbm_set_force(lbm_ctx *ctx, const double *force, const void *field, double e
 int lbm_set_collision(lbm_ctx *ctx, int model);
 
 /*
- * Start recording a tape for lbm_backward: a bit-exact checkpoint of the
+ * Start recording a tape for lbm_backward -- the in-memory checkpointing
+ * (Sec. 3.7) that differentiating unrolled steps needs (Sec. 3.6, Sec. 6.1):
+ * a bit-exact checkpoint of the
  * state now and every K >= 1 steps after it.  The segment between
  * checkpoints is recomputed during the backward pass.  LBM_ENOMEM if the
  * checkpoints for max_steps steps plus a K-state recompute ring do not fit.
@@ -301,6 +311,16 @@ int lbm_tape_end(lbm_ctx *ctx);
 
 /* Drop the tape and free its memory. */
 int lbm_tape_free(lbm_ctx *ctx);
+
+/*
+ * Identity of the context's current tape: a number that grows by one with
+ * every lbm_tape_begin on this context (the first tape is 1); 0 when no tape
+ * is held, -1 for a NULL context.  A caller that records a tape and runs its
+ * backward later (an autograd node, Sec. 6.1's unrolled training) keeps this
+ * number and checks it before lbm_backward: a different value means another
+ * recording replaced its tape.
+ */
+int64_t lbm_tape_id(const lbm_ctx *ctx);
 
 /*
  * Discrete adjoint of the recorded steps (the gradient the paper obtains from
@@ -315,8 +335,11 @@ int lbm_tape_free(lbm_ctx *ctx);
  *   dL_duw   : host double[n_domains * 6 * 3], gradient w.r.t. each face's
  *              wall velocity (LBM_WALL faces only; other entries 0).
  * The forward state is left unchanged.  Synchronises.  LBM_ESTATE without a
- * tape or if the state moved since the tape ended; LBM_EUNSUPPORTED when a
- * domain has regularized faces.
+ * tape, if the state moved since the tape ended, or if lbm_set_params,
+ * lbm_set_solid, lbm_set_solid_fraction, lbm_set_force or lbm_set_collision
+ * was called after the tape began (the recorded steps no longer match the
+ * parameters the adjoint would use); LBM_EUNSUPPORTED when a domain has
+ * regularized faces.
  */
 int lbm_backward(lbm_ctx *ctx, const void *dL_drho, const void *dL_du, int dtype,
                  float *dL_ds, double *dL_dtau, double *dL_duw);
@@ -340,7 +363,8 @@ int lbm_backward_force(lbm_ctx *ctx, const void *dL_drho, const void *dL_du, int
                        void *dL_dfield, double *dL_dforce);
 
 /*
- * Capture n_steps >= 1 steps into a HIP graph that lbm_graph_launch replays
+ * The compiled step loop (the paper JIT-compiles `step` with JAX, Sec. 3.1):
+ * capture n_steps >= 1 steps into a HIP graph that lbm_graph_launch replays
  * with one launch (batch and single contexts).  The graph reads the state at
  * launch time; it is invalidated by lbm_init_equilibrium / lbm_load /
  * lbm_set_* calls.

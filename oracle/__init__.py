@@ -48,7 +48,8 @@ class _Sim(ctypes.Structure):
     _fields_ = [("q", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("tau", ctypes.c_double), ("rho0", ctypes.c_double), ("face", _Face * 6),
                 ("solid", ctypes.c_void_p), ("s", ctypes.c_void_p), ("force", ctypes.c_double * 3),
-                ("edm", ctypes.c_void_p), ("collision", ctypes.c_int)]
+                ("edm", ctypes.c_void_p), ("collision", ctypes.c_int), ("qlink", ctypes.c_void_p),
+                ("bouzidi_order", ctypes.c_int)]
 
 
 _lib = None
@@ -73,9 +74,12 @@ def lib():
         L.orc_moments.argtypes = [P(_Sim), dp, dp, dp]
         L.orc_sums.argtypes = [P(_Sim), dp, dp]
         L.orc_forces.argtypes = [P(_Sim), dp, dp]
+        L.orc_step_forces.argtypes = [P(_Sim), dp, dp]
+        L.orc_step_forces.restype = ctypes.c_int
         L.orc_adjoint_step.argtypes = [P(_Sim), dp, dp, dp, ctypes.c_void_p, dp, dp, ctypes.c_void_p]
         L.orc_adjoint_step.restype = ctypes.c_int
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -136,6 +140,8 @@ class Sim:
     force: tuple = (0.0, 0.0, 0.0)
     edm: Optional[np.ndarray] = None       # (nx,ny,nz,3) body force, exact-difference method
     collision: int = 0                     # 0 BGK, 1 KBC (D2Q9 / D3Q27)
+    qlink: Optional[np.ndarray] = None     # (nx,ny,nz,q) curved-wall fractions of links into solids (0 = halfway)
+    bouzidi_order: int = 1                 # 1 linear, 2 quadratic interpolated bounce-back
 
     @property
     def shape(self):
@@ -181,6 +187,14 @@ class Sim:
         else:
             st.edm = None
         st.collision = int(self.collision)
+        if self.qlink is not None:
+            ql = np.ascontiguousarray(self.qlink, dtype=np.float64).reshape(-1)
+            assert ql.size == self.N * self.q
+            self._keep.append(ql)
+            st.qlink = ql.ctypes.data
+        else:
+            st.qlink = None
+        st.bouzidi_order = int(self.bouzidi_order)
         return st
 
     # --- state ---------------------------------------------------------------
@@ -232,6 +246,24 @@ class Sim:
         out = np.zeros(21)
         lib().orc_forces(ctypes.byref(st), _dp(np.ascontiguousarray(f)), _dp(out))
         return out[:3].copy(), out[3:].reshape(6, 3).copy()
+
+    def step_forces(self, f: np.ndarray):
+        """Advance f (in place) by one step; return the momentum-exchange force of
+        that step from the post-collision and new populations (Mei et al.):
+        (force on the solid cells [3], force on each wall face [6, 3])."""
+        assert f.shape == self.shape + (self.q,) and f.dtype == np.float64 and f.flags["C_CONTIGUOUS"]
+        st = self._struct()
+        out = np.zeros(21)
+        if lib().orc_step_forces(ctypes.byref(st), _dp(f), _dp(out)) != 0:
+            raise MemoryError("oracle allocation failed")
+        return out[:3].copy(), out[3:].reshape(6, 3).copy()
+
+    def links_to_qlink(self, cells, dirs, q):
+        """Dense (nx,ny,nz,q) wall-fraction array from a link list (flat cell
+        index, direction, fraction)."""
+        ql = np.zeros(self.N * self.q)
+        ql[np.asarray(cells, dtype=np.int64) * self.q + np.asarray(dirs, dtype=np.int64)] = np.asarray(q)
+        return ql.reshape(self.shape + (self.q,))
 
     def collide_cell(self, f_cell: np.ndarray) -> np.ndarray:
         st = self._struct()
@@ -312,3 +344,8 @@ class Sim:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the following oracle calls (timing only; results do not depend on it)."""
+    lib().orc_set_num_threads(int(n))

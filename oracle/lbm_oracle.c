@@ -58,6 +58,8 @@ typedef struct {
     double force[3];            /* body force, test hook only (Poiseuille pin) */
     const double *edm;          /* N*3 body force per cell, exact-difference method; NULL = none */
     int collision;              /* 0: BGK; 1: KBC entropic multi-relaxation (D2Q9, D3Q27) */
+    const double *qlink;        /* N*q wall fractions of curved links (0 = halfway); NULL = none */
+    int bouzidi_order;          /* 1: linear, 2: quadratic interpolated bounce-back */
 } orc_sim;
 
 /* ---------------------------------------------------------------------------
@@ -306,6 +308,68 @@ static orc_src classify(const orc_sim *S, const int x[3], const int *c)
     return r;
 }
 
+/*
+ * Interpolated bounce-back at a curved wall (Bouzidi, Firdaouss & Lallemand
+ * 2001; the paper's no-slip condition for curved geometries, Sec. 4.3).
+ * Link (x_b, i): x_b is fluid, x_b + c_i is solid, and the wall cuts the link
+ * at the fraction qv of its length from x_b (0 < qv <= 1).  The unknown after
+ * streaming is f_opp(i)(x_b, t+1).  Measure s along c_i with x_b at s = 0, the
+ * wall at s = qv and x_ff = x_b - c_i at s = -1, x_fff = x_b - 2 c_i at s = -2.
+ * A population moving along c_i covers one unit per step and turns around at
+ * the wall:
+ *   qv <  1/2: the value that reaches x_b after the turn started at
+ *              s_D = 2 qv - 1, between x_ff and x_b, so f_opp(i)(x_b, t+1) is
+ *              the post-collision field f*_i(., t) interpolated at s_D from
+ *              the nodes s = 0, -1 (linear) and -2 (quadratic);
+ *   qv >= 1/2: f*_i(x_b, t) turns around and lands at s_P = 2 qv - 1, between
+ *              x_b and the wall, so f_opp(i)(x_b, t+1) is the field of
+ *              opp(i)-populations at t+1 interpolated at s = 0 from the point
+ *              s_P (value f*_i(x_b, t)) and the nodes s = -1, -2, which hold
+ *              f_opp(i)(x_ff, t+1) = f*_opp(i)(x_b, t) and
+ *              f_opp(i)(x_fff, t+1) = f*_opp(i)(x_ff, t).
+ * Lagrange interpolation through those points gives
+ *   linear,    qv <  1/2: 2 qv f*_i(x_b) + (1 - 2 qv) f*_i(x_ff)
+ *   linear,    qv >= 1/2: f*_i(x_b) / (2 qv) + (2 qv - 1) / (2 qv) f*_opp(x_b)
+ *   quadratic, qv <  1/2: qv (1 + 2 qv) f*_i(x_b) + (1 - 4 qv^2) f*_i(x_ff)
+ *                         - qv (1 - 2 qv) f*_i(x_fff)
+ *   quadratic, qv >= 1/2: f*_i(x_b) / (qv (2 qv + 1)) + (2 qv - 1) / qv f*_opp(x_b)
+ *                         + (1 - 2 qv) / (1 + 2 qv) f*_opp(x_ff)
+ * (qv = 1/2 is halfway bounce-back in every case).  The walls are at rest.
+ * Where x_ff is not a fluid node the link falls back to halfway bounce-back;
+ * where the quadratic rule needs x_fff and it is not a fluid node, the linear
+ * rule is used.  fpost: post-collision populations of every cell.
+ */
+static double bouzidi_fill(const orc_sim *S, const int xb[3], int i, double qv, const double *fpost)
+{
+    const int q = S->q;
+    const int *c = cvec(q, i);
+    const int o = opposite(q, i);
+    const size_t kb = cell_index(S, xb);
+    const double A = fpost[kb * q + i];
+    const orc_src ff = classify(S, xb, c);          /* x_b - c_i */
+    if (ff.kind != SRC_FLUID) return A;
+    int xff[3];
+    xff[0] = (int)(ff.cell / ((size_t)S->ny * S->nz));
+    xff[1] = (int)((ff.cell / S->nz) % S->ny);
+    xff[2] = (int)(ff.cell % S->nz);
+    int order = S->bouzidi_order;
+    orc_src fff = {0};
+    if (order == 2) {
+        fff = classify(S, xff, c);                   /* x_b - 2 c_i */
+        if (fff.kind != SRC_FLUID) order = 1;
+    }
+    if (qv < 0.5) {
+        const double B = fpost[ff.cell * q + i];
+        if (order == 1) return 2.0 * qv * A + (1.0 - 2.0 * qv) * B;
+        const double C = fpost[fff.cell * q + i];
+        return qv * (1.0 + 2.0 * qv) * A + (1.0 - 4.0 * qv * qv) * B - qv * (1.0 - 2.0 * qv) * C;
+    }
+    const double D = fpost[kb * q + o];
+    if (order == 1) return A / (2.0 * qv) + (2.0 * qv - 1.0) / (2.0 * qv) * D;
+    const double E = fpost[ff.cell * q + o];
+    return A / (qv * (2.0 * qv + 1.0)) + (2.0 * qv - 1.0) / qv * D + (1.0 - 2.0 * qv) / (1.0 + 2.0 * qv) * E;
+}
+
 /* Is cell x on a wall face (a perimeter cell of an open face)? */
 static int on_wall_face(const orc_sim *S, const int x[3])
 {
@@ -503,8 +567,15 @@ static void step_impl(const orc_sim *S, const double *f, double *fn, double *fpo
                 out[i] = fpost[src.cell * q + i];
                 break;
             case SRC_WALL: {
+                const int o = opposite(q, i);
+                const double qv = S->qlink ? S->qlink[(size_t)k * q + o] : 0.0;
+                if (src.wall_face < 0 && qv > 0.0) {
+                    /* a solid cell with a curved-wall link along c_o = -c_i */
+                    out[i] = bouzidi_fill(S, x, o, qv, fpost);
+                    break;
+                }
                 double cu = c[0] * src.uw[0] + c[1] * src.uw[1] + c[2] * src.uw[2];
-                out[i] = fpost[(size_t)k * q + opposite(q, i)] + 6.0 * weight(q, i) * S->rho0 * cu;
+                out[i] = fpost[(size_t)k * q + o] + 6.0 * weight(q, i) * S->rho0 * cu;
                 break;
             }
             case SRC_OUTFLOW:
@@ -858,11 +929,71 @@ void orc_forces(const orc_sim *S, const double *f, double *out)
     for (int k = 0; k < 21; ++k) out[k] = s[k];
 }
 
+/*
+ * One step f(t) -> f(t+1), in place, and the momentum-exchange force of that
+ * step in the form of Mei, Yu, Shyy & Luo (2002), which the paper cites for
+ * its lift and drag (Sec. 4.3): over every link (x, i) from a fluid cell x to
+ * a solid cell or across a wall face, the fluid loses (f°_i(x, t) +
+ * f_opp(i)(x, t + 1)) c_i of momentum, where f° is the post-collision
+ * population and f_opp(i)(x, t + 1) whatever the boundary rule filled in
+ * (halfway or interpolated bounce-back).  out[21] as orc_forces.  With
+ * halfway bounce-back only, this equals orc_forces of the new state.
+ */
+int orc_step_forces(const orc_sim *S, double *f, double *out)
+{
+    const int q = S->q;
+    const long N = (long)S->nx * S->ny * S->nz;
+    const size_t bytes = (size_t)N * q * sizeof(double);
+    double *fn = (double *)malloc(bytes);
+    double *fpost = (double *)malloc(bytes);
+    double *vel = (double *)malloc((size_t)N * 3 * sizeof(double));
+    if (!fn || !fpost || !vel) { free(fn); free(fpost); free(vel); return -1; }
+    step_impl(S, f, fn, fpost, vel);
+    double s[21], comp[21];
+    for (int k = 0; k < 21; ++k) s[k] = comp[k] = 0.0;
+    int x[3];
+    for (x[0] = 0; x[0] < S->nx; ++x[0])
+        for (x[1] = 0; x[1] < S->ny; ++x[1])
+            for (x[2] = 0; x[2] < S->nz; ++x[2]) {
+                const size_t cell = cell_index(S, x);
+                if (S->solid && S->solid[cell]) continue;
+                for (int i = 1; i < q; ++i) {
+                    const int *c = cvec(q, i);
+                    int mc[3] = {-c[0], -c[1], -c[2]};
+                    const orc_src src = classify(S, x, mc);   /* the cell x + c_i */
+                    if (src.kind != SRC_WALL) continue;
+                    const double ex = fpost[cell * q + i] + fn[cell * q + opposite(q, i)];
+                    const int base = (src.wall_face >= 0) ? 3 + 3 * src.wall_face : 0;
+                    for (int a = 0; a < 3; ++a) {
+                        const double y = ex * c[a] - comp[base + a];
+                        const double t = s[base + a] + y;
+                        comp[base + a] = (t - s[base + a]) - y;
+                        s[base + a] = t;
+                    }
+                }
+            }
+    for (int k = 0; k < 21; ++k) out[k] = s[k];
+    memcpy(f, fn, bytes);
+    free(fn); free(fpost); free(vel);
+    return 0;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Threads the following calls use (timing of the oracle on one core and on
+ * all cores; the result does not depend on it). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }

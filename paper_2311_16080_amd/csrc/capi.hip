@@ -336,7 +336,7 @@ extern "C" int lbm_set_params(lbm_ctx *c, double tau, const lbm_bc *bc) {
         map_faces(c, bc);
     }
     drop_graph(c);
-    c->moved_since_tape = true;
+    tape_invalidate(c);
     if (c->A) {
         int rc = upload_faces(c);
         if (rc) return rc;
@@ -502,6 +502,7 @@ extern "C" int lbm_set_solid(lbm_ctx *c, const uint8_t *flags, int on_device) {
     int rc = ensure_device(c);
     if (rc) return rc;
     drop_graph(c);
+    tape_invalidate(c);
     if (!flags) {
         dev_free((void *&)c->flags);
         dev_free((void *&)c->nbm);
@@ -544,6 +545,7 @@ extern "C" int lbm_set_solid_fraction(lbm_ctx *c, const float *s, int on_device)
     int rc = ensure_device(c);
     if (rc) return rc;
     drop_graph(c);
+    tape_invalidate(c);
     if (!s) {
         dev_free((void *&)c->s);
         refresh_params(c);
@@ -707,6 +709,7 @@ extern "C" int lbm_set_collision(lbm_ctx *c, int model) {
         if (c->s) return fail(LBM_EUNSUPPORTED, "KBC does not combine with a partial bounce-back field");
     }
     drop_graph(c);
+    tape_invalidate(c);
     c->collision = model;
     return LBM_OK;
 }
@@ -723,6 +726,7 @@ extern "C" int lbm_set_force(lbm_ctx *c, const double *force, const void *field,
         }
     }
     drop_graph(c);
+    tape_invalidate(c);
     c->force_on = (field != nullptr && eps != 0.0) || u[0] != 0.0 || u[1] != 0.0 || u[2] != 0.0;
     for (int a = 0; a < 3; ++a) c->force_u[a] = u[a];
     c->force_field = c->force_on ? field : nullptr;

@@ -85,6 +85,7 @@ struct lbm_ctx {
     lbm::TapeState *tape = nullptr;
     bool tape_recording = false;
     bool moved_since_tape = true;
+    int64_t tape_serial = 0;         // id of the most recent tape (lbm_tape_id)
 
     // captured graph
     hipGraph_t graph = nullptr;
@@ -114,6 +115,8 @@ void drop_graph(lbm_ctx *c);
 // tape.hip
 int tape_after_step(lbm_ctx *c);
 void tape_release(lbm_ctx *c);
+// a parameter of the recorded steps changed: the tape no longer describes them
+void tape_invalidate(lbm_ctx *c);
 
 // batch.hip
 int batch_upload(lbm_ctx *c);

@@ -330,17 +330,25 @@ __device__ __forceinline__ bool moments_cell(const Params<typename Store<ST>::CT
     return true;
 }
 
-// Block sum of the five moment sums into partial[row * 5 ..]
+// Block sum of the five moment sums into partial[row * 5 ..]: a butterfly
+// within each wavefront, then the wavefront totals in wavefront order.  Any
+// block of whole wavefronts (64, 128, 192 or 256 lanes) is summed completely,
+// and the order is fixed, so the result is deterministic.
 __device__ __forceinline__ void block_sums(const double (&m)[5], double *partial, int64_t row) {
-    __shared__ double red[5][kMaxBlock];
-    const int t = (int)threadIdx.x;
-    unroll<5>([&](auto K) { red[K][t] = m[K]; });
+    __shared__ double red[5][kMaxBlock / 64];
+    const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+    unroll<5>([&](auto K) {
+        double v = m[K];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) red[K][wv] = v;
+    });
     __syncthreads();
-    for (int w = (int)blockDim.x / 2; w > 0; w >>= 1) {
-        if (t < w) unroll<5>([&](auto K) { red[K][t] += red[K][t + w]; });
-        __syncthreads();
+    if ((int)threadIdx.x < 5) {
+        const int nw = ((int)blockDim.x + 63) / 64;
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += red[threadIdx.x][w];
+        partial[row * 5 + threadIdx.x] = t;
     }
-    if (t == 0) unroll<5>([&](auto K) { partial[row * 5 + K] = red[K][0]; });
 }
 
 template <class L, class CT, class OT>

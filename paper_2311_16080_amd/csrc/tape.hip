@@ -18,6 +18,9 @@ using namespace lbm;
 
 namespace lbm {
 struct TapeState {
+    int64_t id = 0;           // lbm_tape_id of this tape
+    bool stale = false;       // a parameter changed after the tape began
+    bool had_s = false;       // a partial bounce-back field was set when it began
     int K = 0;
     int max_steps = 0;
     int64_t t_begin = 0, t_end = 0;
@@ -64,6 +67,11 @@ void lbm::tape_release(lbm_ctx *c) {
     }
     c->tape = nullptr;
     c->tape_recording = false;
+}
+
+void lbm::tape_invalidate(lbm_ctx *c) {
+    c->moved_since_tape = true;
+    if (c->tape) c->tape->stale = true;
 }
 
 static hipError_t checkpoint(lbm_ctx *c, int slot) {
@@ -124,6 +132,8 @@ extern "C" int lbm_tape_begin(lbm_ctx *c, int K, int max_steps) {
     TapeState *T = new (std::nothrow) TapeState();
     if (!T) return fail(LBM_ENOMEM, "host allocation failed");
     c->tape = T;
+    T->id = ++c->tape_serial;
+    T->had_s = c->s != nullptr;
     T->K = K;
     T->max_steps = max_steps;
     T->sbytes = state_bytes_of(c);
@@ -176,6 +186,11 @@ extern "C" int lbm_tape_end(lbm_ctx *c) {
     }
     c->tape_recording = false;
     return LBM_OK;
+}
+
+extern "C" int64_t lbm_tape_id(const lbm_ctx *c) {
+    if (!c) return -1;
+    return c->tape ? c->tape->id : 0;
 }
 
 extern "C" int lbm_tape_free(lbm_ctx *c) {
@@ -272,6 +287,9 @@ static int backward_impl(lbm_ctx *c, const void *dL_drho, const void *dL_du, int
     if (want_force && c->batch) return fail(LBM_EUNSUPPORTED, "body forces are not supported on batch contexts");
     if (c->tape_recording) lbm_tape_end(c);
     TapeState *T = c->tape;
+    if (T->stale || T->had_s != (c->s != nullptr))
+        return fail(LBM_ESTATE, "tau, a face, the solid cells, the solid fraction, the body force or the collision "
+                                "changed after the tape began; record a new tape");
     if (c->moved_since_tape || c->t != T->t_end) return fail(LBM_ESTATE, "the state moved since the tape ended");
     (void)hipSetDevice(c->device);
     const int64_t fblocks = (c->N + 255) / 256;
@@ -332,7 +350,7 @@ static int backward_impl(lbm_ctx *c, const void *dL_drho, const void *dL_du, int
             g.F = S[t - t0];
             g.An = T->abuf[cur];
             g.Ao = T->abuf[1 - cur];
-            g.ds = T->ds;
+            g.ds = c->s ? T->ds : nullptr;
             g.acc = T->acc;
             g.force = (c->force_on || want_force) ? 1 : 0;
             g.dF = want_force ? T->dF : nullptr;

@@ -88,15 +88,18 @@ def random_density(shape, seed: int, amp: float = 0.01, rho0: float = 1.0) -> np
 
 
 def sphere_obstacles(nx: int, ny: int, nz: int, seed: int = 3, rmin: float = 8.0, rmax: float = 32.0,
-                     xlo: int = 64, xhi: int = 960, fraction: float = 0.05, max_spheres: int = 100000) -> np.ndarray:
+                     xlo: int = 64, xhi: int = 960, fraction: float = 0.05, max_spheres: int = 100000,
+                     return_spheres: bool = False):
     """(nx, ny, nz) uint8 obstacle mask: spheres with centres uniform in
     [xlo, xhi) x [0, ny) x [0, nz) and radii uniform in [rmin, rmax], added
     until at least `fraction` of all cells are solid (overlaps allowed).
-    Rasterised in FP64: a cell is solid when its centre lies inside a sphere."""
+    Rasterised in FP64: a cell is solid when its centre lies inside a sphere.
+    return_spheres: also return the rasterised spheres as rows (cx, cy, cz, r)."""
     rng = np.random.default_rng(seed)
     solid = np.zeros((nx, ny, nz), dtype=np.uint8)
     target = fraction * nx * ny * nz
     count = 0
+    balls = []
     for _ in range(max_spheres):
         cx = rng.uniform(xlo, xhi)
         cy = rng.uniform(0, ny)
@@ -114,9 +117,81 @@ def sphere_obstacles(nx: int, ny: int, nz: int, seed: int = 3, rmin: float = 8.0
         block = solid[x0:x1, y0:y1, z0:z1]
         count += int(np.count_nonzero(inside & (block == 0)))
         block[inside] = 1
+        balls.append((cx, cy, cz, r))
         if count >= target:
             break
+    if return_spheres:
+        return solid, np.array(balls, dtype=np.float64).reshape(-1, 4)
     return solid
+
+
+def cylinder_obstacle(nx: int, ny: int, cx: float, cy: float, r: float) -> np.ndarray:
+    """(nx, ny) uint8 mask of one circular cylinder (the obstacle of the
+    paper's flow past a cylinder, Sec. 4.3): cell (i, j) is solid when its
+    centre lies within r of (cx, cy)."""
+    X = np.arange(nx, dtype=np.float64)[:, None]
+    Y = np.arange(ny, dtype=np.float64)[None, :]
+    return ((X - cx) ** 2 + (Y - cy) ** 2 <= r * r).astype(np.uint8)
+
+
+def ball_wall_fractions(solid: np.ndarray, balls: np.ndarray, c: np.ndarray):
+    """Curved-wall links of an obstacle mask made of balls (circles in 2-D,
+    spheres in 3-D): for every fluid cell x and every direction i >= 1 of the
+    caller's velocity set c (Q x D integer rows) whose neighbour x + c_i lies
+    in the grid and is solid, the fraction q in (0, 1] of the segment
+    x -> x + c_i at which it first enters one of the balls (rows (centre...,
+    r)).  Returns (cells, dirs, q): flat C-order cell indices, direction
+    indices and fractions, in cell-then-direction order.  Pure geometry in
+    FP64 (segment-sphere intersection)."""
+    solid = np.asarray(solid).astype(bool)
+    shape = solid.shape
+    D = solid.ndim
+    c = np.asarray(c, dtype=np.int64)[:, :D]
+    Q = c.shape[0]
+    N = solid.size
+    qarr = np.full(N * Q, np.inf)
+    coords = np.indices(shape).reshape(D, -1).T.astype(np.float64)   # cell centres, flat order
+    for row in np.asarray(balls, dtype=np.float64).reshape(-1, D + 1):
+        ctr, r = row[:D], row[D]
+        lo = [max(int(np.floor(ctr[a] - r)) - 2, 0) for a in range(D)]
+        hi = [min(int(np.ceil(ctr[a] + r)) + 3, shape[a]) for a in range(D)]
+        if any(lo[a] >= hi[a] for a in range(D)):
+            continue
+        box = np.zeros(shape, dtype=bool)
+        box[tuple(slice(lo[a], hi[a]) for a in range(D))] = True
+        cand = np.flatnonzero(box.reshape(-1) & ~solid.reshape(-1))
+        p0 = coords[cand] - ctr
+        c0 = np.sum(p0 * p0, axis=1) - r * r
+        for i in range(1, Q):
+            d = c[i].astype(np.float64)
+            a2 = float(d @ d)
+            b = p0 @ d
+            disc = b * b - a2 * c0
+            ok = disc >= 0.0
+            t = np.full(cand.size, np.inf)
+            t[ok] = (-b[ok] - np.sqrt(disc[ok])) / a2
+            hit = ok & (t > 0.0) & (t <= 1.0)
+            idx = cand[hit] * Q + i
+            qarr[idx] = np.minimum(qarr[idx], t[hit])
+    cells, dirs, qs = [], [], []
+    flat_solid = solid.reshape(-1)
+    for i in range(1, Q):
+        src = np.indices(shape).reshape(D, -1)
+        dst = src + c[i][:, None]
+        inb = np.all((dst >= 0) & (dst < np.array(shape)[:, None]), axis=0)
+        k = np.flatnonzero(inb & ~flat_solid)
+        dflat = np.ravel_multi_index(tuple(dst[:, k]), shape)
+        k = k[flat_solid[dflat]]
+        qv = qarr[k * Q + i]
+        qv = np.where(np.isfinite(qv), qv, 0.5)
+        cells.append(k)
+        dirs.append(np.full(k.size, i, dtype=np.int64))
+        qs.append(qv)
+    cells = np.concatenate(cells) if cells else np.zeros(0, np.int64)
+    dirs = np.concatenate(dirs) if dirs else np.zeros(0, np.int64)
+    qs = np.concatenate(qs) if qs else np.zeros(0)
+    order = np.lexsort((dirs, cells))
+    return cells[order], dirs[order], qs[order]
 
 
 def smooth_solid_fraction(nx: int, ny: int, seed: int = 4, sigma: float = 8.0, edge: int = 16) -> np.ndarray:

@@ -72,6 +72,7 @@ SIGNATURES = {
     "lbm_tape_begin": (_i, [_vp, _i, _i]),
     "lbm_tape_end": (_i, [_vp]),
     "lbm_tape_free": (_i, [_vp]),
+    "lbm_tape_id": (_i64, [_vp]),
     "lbm_backward": (_i, [_vp, _vp, _vp, _i, _vp, _dp, _dp]),
     "lbm_backward_force": (_i, [_vp, _vp, _vp, _i, _vp, _dp, _dp, _vp, _dp]),
     "lbm_capture_graph": (_i, [_vp, _i]),
@@ -337,6 +338,10 @@ class Sim:
     def tape_free(self):
         check(lib().lbm_tape_free(self.h))
 
+    def tape_id(self) -> int:
+        """Identity of the current tape (grows with every tape_begin; 0 = none)."""
+        return int(lib().lbm_tape_id(self.h))
+
     def backward(self, dL_drho=None, dL_du=None, want_s: bool = False, n_domains: int = 1):
         """Adjoint of the taped steps seeded by dL/drho, dL/du (device tensors).
         Returns (dL_ds tensor or None, dL_dtau [n_domains], dL_duw [n_domains, 6, 3])."""
@@ -407,6 +412,7 @@ class _Rollout:
                     sim.tape_end()
                     rho, u = sim.moments(dtype=torch.float64 if sim.storage == "f64" else torch.float32)
                     ctx.sim = sim
+                    ctx.tape_id = sim.tape_id()
                     ctx.has_s = s is not None
                     ctx.tau_dtype = tau.dtype
                     return rho, u
@@ -414,6 +420,9 @@ class _Rollout:
                 @staticmethod
                 def backward(ctx, g_rho, g_u):
                     sim = ctx.sim
+                    if sim.tape_id() != ctx.tape_id:
+                        raise LbmError(LBM_ESTATE, "another rollout on this Sim replaced the tape of this one "
+                                                   "before its backward pass; use one Sim per rollout in a graph")
                     g_field = None
                     if ctx.has_field:
                         ds, dtau, _, g_field, _ = sim.backward_force(g_rho, g_u, want_s=ctx.has_s)

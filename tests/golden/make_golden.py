@@ -8,8 +8,9 @@ library.  Run once (about 15-25 minutes on 8 cores):
 
 cavity256       -- D3Q19 lid-driven cavity 256^3, tau = 0.55, five static
                    halfway bounce-back walls, lid (+z) moving at u = (0.05, 0, 0),
-                   start at rest (f = w_i), 1000 steps.  Stored: u on the plane
-                   y = 128 at every other x and z, the field sums.
+                   start at rest (f = w_i), 1000 steps.  Stored: u and rho on
+                   the whole planes y = 128 and x = 128 (every cell), the field
+                   sums.
 c4_adjoint      -- D2Q9 channel 512 x 256, tau = 0.6, Zou-He inlet u = (0.04, 0),
                    equilibrium outflow, walls on +-y, solid fraction s from
                    seed 4 (float32-rounded, as the library takes it), start at
@@ -50,8 +51,9 @@ def cavity256(steps=1000, n=256):
         print(f"cavity256: {k + 100} steps, {time.time() - t0:.0f} s", flush=True)
     rho, u = S.moments(f)
     np.savez_compressed(os.path.join(HERE, "cavity256_d3q19_1000.npz"),
-                        u_y128=u[::2, n // 2, ::2, :], rho_y128=rho[::2, n // 2, ::2], sums=S.sums(f),
-                        steps=steps, stride=2)
+                        u_y128=u[:, n // 2, :, :], rho_y128=rho[:, n // 2, :],
+                        u_x128=u[n // 2, :, :, :], rho_x128=rho[n // 2, :, :], sums=S.sums(f),
+                        steps=steps, stride=1)
 
 
 def channel_spheres(steps=300, shape=(256, 128, 128)):

@@ -163,3 +163,15 @@ def test_force_collision_and_face_checks_without_device():
     assert "density" in lbm.last_error()
     assert not L.lbm_create(lbm.D3Q19, 8, 8, 8, 0.7, _bc([(7,), lbm.WALL, 0, 0, 0, 0]))
     assert "unknown boundary type" in lbm.last_error()
+
+
+def test_tape_id_without_device():
+    """lbm_tape_id: -1 for NULL, 0 while no tape is held (no device work)."""
+    L = lbm.lib()
+    assert L.lbm_tape_id(None) == -1
+    h = L.lbm_create(lbm.D2Q9, 8, 8, 0, 0.8, None)
+    assert h
+    try:
+        assert L.lbm_tape_id(h) == 0
+    finally:
+        L.lbm_destroy(h)

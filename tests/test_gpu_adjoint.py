@@ -182,3 +182,51 @@ def test_backward_without_tape_is_an_error():
     sim.step(3)
     with pytest.raises(lbm.LbmError):
         sim.backward(None, torch.zeros((3, 8, 9, 70), device="cuda"))
+
+
+_SETTERS = {
+    "params": lambda sim, s: sim.set_params(tau=0.61),
+    "solid": lambda sim, s: sim.set_solid(np.zeros(sim.shape, np.uint8)),
+    "solid_fraction_clear": lambda sim, s: sim.set_solid_fraction(None),
+    "solid_fraction_replace": lambda sim, s: sim.set_solid_fraction(s),
+    "force": lambda sim, s: sim.set_force([1e-5, 0.0]),
+    "collision": lambda sim, s: sim.set_collision("BGK"),
+}
+
+
+@pytest.mark.parametrize("when", ["after_tape_end", "while_recording"])
+@pytest.mark.parametrize("setter", sorted(_SETTERS))
+def test_backward_refuses_after_a_setter(setter, when):
+    """A parameter set after the tape began (tau, solid cells, the solid
+    fraction, the body force, the collision) makes the tape describe other
+    steps than the adjoint would differentiate: lbm_backward refuses it with
+    LBM_ESTATE and launches nothing."""
+    import torch
+    _announce(f"backward after {setter} ({when})")
+    shape = (24, 70)
+    faces = [(ZV, (0.03, 0.0)), (OUT, (0, 0, 0), 1.0), (W,), (W,), (P,), (P,)]
+    s = inputs.smooth_solid_fraction(*shape, seed=4, sigma=3, edge=4).astype(np.float32)
+    sim = lbm.Sim("D2Q9", shape, 0.6, faces=faces, storage="f32")
+    sim.set_solid_fraction(s)
+    sim.init_equilibrium()
+    sim.tape_begin(2, 6)
+    sim.step(3)
+    if when == "while_recording":
+        _SETTERS[setter](sim, s)
+    sim.step(3)
+    sim.tape_end()
+    if when == "after_tape_end":
+        _SETTERS[setter](sim, s)
+    g_u = torch.ones((2,) + shape, dtype=torch.float32, device="cuda")
+    with pytest.raises(lbm.LbmError) as err:
+        sim.backward(None, g_u, want_s=True)
+    assert err.value.code == lbm.LBM_ESTATE
+    sim.sync()
+    # a fresh tape of the current parameters differentiates again
+    sim.init_equilibrium()
+    sim.tape_begin(2, 4)
+    sim.step(4)
+    sim.tape_end()
+    ds, dtau, _ = sim.backward(None, g_u, want_s=True)
+    torch.cuda.synchronize()
+    assert np.isfinite(dtau[0])

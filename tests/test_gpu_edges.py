@@ -47,6 +47,31 @@ def test_edge_case_matches_oracle(name):
     du, drho = compare(case, g, o)
     print(f"[case] {name}: u rel-L2 {du:.3e}, max |drho| {drho:.3e}", flush=True)
     assert du <= 1e-12 and drho <= 1e-13
+    _assert_sums(g[2], o[2])
+
+
+def _assert_sums(sg, so):
+    """FP64 block sums (mass, momentum, kinetic energy) against the oracle's
+    Kahan sums over the fluid cells (eqs. density, velocity)."""
+    assert abs(sg[0] - so[0]) <= 1e-12 * abs(so[0]), (sg[0], so[0])
+    for a in (1, 2, 3):
+        assert abs(sg[a] - so[a]) <= 1e-12 * abs(so[0]), (a, sg[a], so[a])
+    assert abs(sg[4] - so[4]) <= 1e-10 * abs(so[4]) + 1e-300, (sg[4], so[4])
+
+
+@pytest.mark.parametrize("block", [64, 128, 192, 256])
+def test_moment_sums_at_every_block_size(block, monkeypatch):
+    """Rows of 300 cells launched with blocks of 64 / 128 / 192 / 256 lanes
+    (LBM_BLOCK): the moment sums cover every cell of every block, whatever the
+    block size."""
+    monkeypatch.setenv("LBM_BLOCK", str(block))
+    case = Case(19, (3, 4, 300), 0.7, [(W,)] * 5 + [(W, (0.04, 0.0, 0.0))], steps=9, init_seed=93)
+    _announce(f"moment sums, block {block}")
+    g = gpu_run(case)
+    o = oracle_run(case)
+    du, drho = compare(case, g, o)
+    assert du <= 1e-12 and drho <= 1e-13
+    _assert_sums(g[2], o[2])
 
 
 def test_zero_steps_change_nothing():
