@@ -122,6 +122,15 @@ typedef struct {
 
 typedef struct lbm_ctx lbm_ctx;
 
+/*
+ * Velocity set of a lattice (Sec. 3.2, Fig. "lattice"): c receives Q rows of
+ * 3 int32 components in caller axes (2-D: (cx, cy, 0)), w the Q weights
+ * (the textbook values by |c|^2; the paper does not print them).  Both are
+ * host pointers of the caller, either may be NULL.  Returns Q, or LBM_EINVAL
+ * for an unknown lattice.  No device work.
+ */
+int lbm_lattice_info(int lattice, int32_t *c, double *w);
+
 /* Thread-local text of the last error of this thread ("" if none). */
 const char *lbm_last_error(void);
 
@@ -172,7 +181,8 @@ int lbm_batch_config(const lbm_ctx *ctx, int *tile, int *persistent);
 /* Free everything the context owns (synchronises its stream).  NULL is a no-op. */
 void lbm_destroy(lbm_ctx *ctx);
 
-/* opt: host pointer.  LBM_ESTATE after the state exists. */
+/* opt: host pointer.  LBM_ESTATE after the state exists, or when the compute
+ * type would change while a force field or curved links are set. */
 int lbm_set_options(lbm_ctx *ctx, const lbm_options *opt);
 
 /*
@@ -200,6 +210,40 @@ int lbm_set_stream(lbm_ctx *ctx, void *hip_stream);
  * clears.  Valid before or after init; solid cells report rho0, u = 0.
  */
 int lbm_set_solid(lbm_ctx *ctx, const uint8_t *flags, int on_device);
+
+/*
+ * Curved walls: interpolated bounce-back (Bouzidi, Firdaouss & Lallemand
+ * 2001), the paper's no-slip condition for curved geometries (Sec. 4.3), on
+ * links from fluid cells into the solid cells of lbm_set_solid.  Link k: the
+ * fluid cell cell[k] (flat index in the caller's (x, y, z) order), the
+ * direction dir[k] (lbm_lattice_info order) whose neighbour cell + c_dir is a
+ * solid cell, and the fraction q[k] in (0, 1] of the link's length at which
+ * the wall cuts it.  After every step the population that comes back along
+ * -c_dir is the value the bounce geometry interpolates, with
+ * order = 1 (linear) or 2 (quadratic) Lagrange weights:
+ *   q < 1/2 : the post-collision field f*_dir at s = 2q - 1 from the cells
+ *             cell, cell - c_dir (and cell - 2 c_dir);
+ *   q >= 1/2: the returning field at the cell from the turned population
+ *             (at s = 2q - 1, value f*_dir(cell)) and f*_-dir at cell (and at
+ *             cell - c_dir).
+ * q = 1/2 is halfway bounce-back.  A link whose cell - c_dir is not a fluid
+ * cell keeps halfway bounce-back; a quadratic link whose cell - 2 c_dir is
+ * not one uses the linear weights.  Walls at rest.  lbm_forces then sums
+ * the momentum exchange of Mei, Yu, Shyy & Luo over these links,
+ * (f*_dir(cell, t) + f_-dir(cell, t+1)) c_dir.
+ *   n     : number of links (0 clears them; the pointers may then be NULL);
+ *   cell, dir, q : host arrays of n, copied (each (cell, dir) at most once);
+ *   order : 1 or 2.
+ * LBM_EINVAL for an out-of-range or solid cell, a direction whose neighbour
+ * (periodic faces wrap) is not a solid cell, q outside (0, 1], a repeated
+ * link, an unknown order, or n > 0 without solid cells; LBM_EUNSUPPORTED on
+ * batch contexts and for a link whose interpolation cells wrap onto its own
+ * cell (a periodic axis shorter than 3 cells).  lbm_set_solid drops the
+ * links; lbm_backward returns LBM_EUNSUPPORTED while links are set.  Drops a
+ * captured graph.
+ */
+int lbm_set_curved_links(lbm_ctx *ctx, int64_t n, const int64_t *cell, const int32_t *dir, const double *q,
+                         int order);
 
 /*
  * Partial bounce-back solid fraction s in [0, 1] per cell (gray LBM, Walsh,
@@ -239,12 +283,15 @@ int64_t lbm_time(const lbm_ctx *ctx);
 int lbm_moments(lbm_ctx *ctx, void *rho, void *u, int dtype, double *sums_host);
 
 /*
- * Momentum-exchange force (Ladd) of the most recent step: the momentum the
+ * Momentum-exchange force (Ladd; Mei et al. on curved links) of the most
+ * recent step: the momentum the
  * fluid handed to the solid cells and to each wall face while streaming into
  * them -- the drag / lift sums of the paper's obstacle flows (Sec. 4.3).  For
  * every fluid cell x and direction i whose neighbour x + c_i is solid or
  * across a wall face, the link contributes (f°_i(x, t) + f_opp(i)(x, t+1)) c_i,
- * with f_opp(i)(x, t+1) = f°_i + 6 w_opp rho0 (c_opp . u_w).  In a closed domain
+ * with f_opp(i)(x, t+1) = f°_i + 6 w_opp rho0 (c_opp . u_w) under halfway
+ * bounce-back and the interpolated value on curved links
+ * (lbm_set_curved_links).  In a closed domain
  * the fluid momentum changes over the step by exactly minus the sum of all
  * these forces.
  * out: host double[21], overwritten: out[0..2] force on the solid cells,
@@ -339,7 +386,7 @@ int64_t lbm_tape_id(const lbm_ctx *ctx);
  * lbm_set_solid, lbm_set_solid_fraction, lbm_set_force or lbm_set_collision
  * was called after the tape began (the recorded steps no longer match the
  * parameters the adjoint would use); LBM_EUNSUPPORTED when a domain has
- * regularized faces.
+ * regularized faces or curved links.
  */
 int lbm_backward(lbm_ctx *ctx, const void *dL_drho, const void *dL_du, int dtype,
                  float *dL_ds, double *dL_dtau, double *dL_duw);

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -40,7 +41,34 @@ int lbm::hip_fail(hipError_t e, const char *what) {
 
 extern "C" const char *lbm_last_error(void) { return g_err.c_str(); }
 
-extern "C" const char *lbm_version(void) { return "lbm-mi355x 0.1 (gfx950)"; }
+extern "C" const char *lbm_version(void) { return "lbm-mi355x 0.2 (gfx950)"; }
+
+template <class L>
+static int lattice_info_t(int32_t *c, double *w) {
+    for (int i = 0; i < L::Q; ++i) {
+        if (c) {
+            // internal (X, Y, Z) -> caller axes (2-D: (Y, Z) -> (x, y))
+            if (L::D == 3) {
+                for (int a = 0; a < 3; ++a) c[3 * i + a] = L::c[i][a];
+            } else {
+                c[3 * i + 0] = L::c[i][1];
+                c[3 * i + 1] = L::c[i][2];
+                c[3 * i + 2] = 0;
+            }
+        }
+        if (w) w[i] = weight<L>(i);
+    }
+    return L::Q;
+}
+
+extern "C" int lbm_lattice_info(int lattice, int32_t *c, double *w) {
+    switch (lattice) {
+        case LBM_D2Q9: return lattice_info_t<D2Q9>(c, w);
+        case LBM_D3Q19: return lattice_info_t<D3Q19>(c, w);
+        case LBM_D3Q27: return lattice_info_t<D3Q27>(c, w);
+    }
+    return fail(LBM_EINVAL, "unknown lattice %d", lattice);
+}
 
 // ---------------------------------------------------------------------------
 // validation and setup
@@ -313,6 +341,9 @@ extern "C" int lbm_set_options(lbm_ctx *c, const lbm_options *o) {
     // a force field set earlier is typed by the compute type
     if (c->force_field && o->compute != c->opt.compute)
         return fail(LBM_ESTATE, "the compute type cannot change while a force field is set (lbm_set_force)");
+    // the curved-link tables hold the wall fractions in the compute type
+    if (c->nlinks && o->compute != c->opt.compute)
+        return fail(LBM_ESTATE, "the compute type cannot change while curved links are set (lbm_set_curved_links)");
     c->opt = *o;
     refresh_params(c);
     return LBM_OK;
@@ -448,6 +479,10 @@ void lbm::free_all(lbm_ctx *c) {
     dev_free((void *&)c->ftd);
     dev_free((void *&)c->ftf);
     dev_free((void *&)c->frows);
+    dev_free(c->links);
+    c->nlinks = 0;
+    c->ltd = LinkTab<double>{};
+    c->ltf = LinkTab<float>{};
     batch_release(c);
 }
 
@@ -503,13 +538,25 @@ extern "C" int lbm_set_solid(lbm_ctx *c, const uint8_t *flags, int on_device) {
     if (rc) return rc;
     drop_graph(c);
     tape_invalidate(c);
+    // the curved links refer to the old mask
+    dev_free(c->links);
+    c->nlinks = 0;
+    c->ltd = LinkTab<double>{};
+    c->ltf = LinkTab<float>{};
+    dev_free((void *&)c->frows);
     if (!flags) {
         dev_free((void *&)c->flags);
         dev_free((void *&)c->nbm);
+        c->solid_host.clear();
         refresh_params(c);
         return LBM_OK;
     }
     const size_t N = (size_t)c->N;
+    try {
+        c->solid_host.assign(N, 0);
+    } catch (...) {
+        return fail(LBM_ENOMEM, "host copy of the solid mask");
+    }
     if (!c->flags) {
         rc = dev_alloc((void **)&c->flags, N, "solid flags");
         if (!rc) rc = dev_alloc((void **)&c->nbm, N * sizeof(uint32_t), "solid neighbour masks");
@@ -530,9 +577,158 @@ extern "C" int lbm_set_solid(lbm_ctx *c, const uint8_t *flags, int on_device) {
         e = launch_solid(c->lattice, g, static_cast<const uint8_t *>(tmp), c->flags, c->nbm);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(c->solid_host.data(), tmp, N, hipMemcpyDeviceToHost);
     dev_free(tmp);
-    if (e != hipSuccess) return hip_fail(e, "lbm_set_solid");
+    if (e != hipSuccess) {
+        c->solid_host.clear();
+        return hip_fail(e, "lbm_set_solid");
+    }
+    for (size_t k = 0; k < N; ++k) c->solid_host[k] = c->solid_host[k] ? 1 : 0;
     refresh_params(c);
+    return LBM_OK;
+}
+
+// One lattice neighbour y = x + d (internal axes) of cell x: false when it lies
+// across a face that is not periodic; periodic faces wrap.
+static bool neighbour_cell(const lbm_ctx *c, int64_t cell, const int d[3], int64_t *out) {
+    int x[3];
+    x[2] = (int)(cell % c->nZ);
+    x[1] = (int)((cell / c->nZ) % c->nY);
+    x[0] = (int)(cell / ((int64_t)c->nZ * c->nY));
+    const int n[3] = {c->nX, c->nY, c->nZ};
+    for (int a = 0; a < 3; ++a) {
+        x[a] += d[a];
+        if (x[a] < 0 || x[a] >= n[a]) {
+            const int f = 2 * a + (x[a] < 0 ? 0 : 1);
+            if (c->iface[f].type != LBM_PERIODIC) return false;
+            x[a] = (x[a] + n[a]) % n[a];
+        }
+    }
+    *out = ((int64_t)x[0] * c->nY + x[1]) * c->nZ + x[2];
+    return true;
+}
+
+template <class L>
+static void lattice_vec(int i, int d[3]) {
+    for (int a = 0; a < 3; ++a) d[a] = L::c[i][a];
+}
+
+template <class CT>
+static LinkTab<CT> link_views(void *base, int64_t n) {
+    LinkTab<CT> t{};
+    char *p = static_cast<char *>(base);
+    t.q = reinterpret_cast<const CT *>(p);
+    p += (size_t)n * sizeof(CT);
+    t.dlt = reinterpret_cast<CT *>(p);
+    p += (size_t)n * sizeof(CT);
+    t.cell = reinterpret_cast<const int32_t *>(p);
+    p += (size_t)n * 4;
+    t.cff = reinterpret_cast<const int32_t *>(p);
+    p += (size_t)n * 4;
+    t.cfff = reinterpret_cast<const int32_t *>(p);
+    p += (size_t)n * 4;
+    t.dir = reinterpret_cast<const uint8_t *>(p);
+    p += (size_t)n;
+    t.kind = reinterpret_cast<const uint8_t *>(p);
+    t.n = n;
+    return t;
+}
+
+extern "C" int lbm_set_curved_links(lbm_ctx *c, int64_t n, const int64_t *cell, const int32_t *dir, const double *q,
+                                    int order) {
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if (c->batch) return fail(LBM_EUNSUPPORTED, "curved links are not supported on batch contexts");
+    if (order != 1 && order != 2) return fail(LBM_EINVAL, "order must be 1 (linear) or 2 (quadratic)");
+    if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+    if (n > 0 && (!cell || !dir || !q)) return fail(LBM_EINVAL, "null link array");
+    if (n > 0 && c->solid_host.empty()) return fail(LBM_EINVAL, "curved links need solid cells (lbm_set_solid)");
+    if (n >= ((int64_t)1 << 31)) return fail(LBM_EINVAL, "too many links");
+    // validate everything before any change
+    struct Link { int64_t cell, ff, fff; double q; int dir, kind; };
+    std::vector<Link> keep;
+    std::vector<int64_t> keys;
+    try {
+        keep.reserve((size_t)n);
+        keys.reserve((size_t)n);
+    } catch (...) {
+        return fail(LBM_ENOMEM, "host link tables");
+    }
+    const int Q = c->Q;
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t x = cell[k];
+        const int i = dir[k];
+        if (x < 0 || x >= c->N) return fail(LBM_EINVAL, "link %lld: cell %lld out of range", (long long)k, (long long)x);
+        if (i < 1 || i >= Q) return fail(LBM_EINVAL, "link %lld: direction %d out of range", (long long)k, i);
+        if (!(q[k] > 0.0 && q[k] <= 1.0)) return fail(LBM_EINVAL, "link %lld: q = %g outside (0, 1]", (long long)k, q[k]);
+        if (c->solid_host[(size_t)x]) return fail(LBM_EINVAL, "link %lld: cell %lld is solid", (long long)k, (long long)x);
+        int d[3];
+        if (c->lattice == LBM_D2Q9) lattice_vec<D2Q9>(i, d);
+        else if (c->lattice == LBM_D3Q19) lattice_vec<D3Q19>(i, d);
+        else lattice_vec<D3Q27>(i, d);
+        int64_t y;
+        if (!neighbour_cell(c, x, d, &y) || !c->solid_host[(size_t)y])
+            return fail(LBM_EINVAL, "link %lld: the neighbour of cell %lld along direction %d is not a solid cell",
+                        (long long)k, (long long)x, i);
+        keys.push_back(x * Q + i);
+        const int md[3] = {-d[0], -d[1], -d[2]};
+        int64_t ff, fff;
+        // x - c_i must be a fluid cell, else the link keeps halfway bounce-back
+        if (!neighbour_cell(c, x, md, &ff) || c->solid_host[(size_t)ff]) continue;
+        int kind = (q[k] >= 0.5) ? 1 : 0;
+        if (order == 2 && neighbour_cell(c, ff, md, &fff) && !c->solid_host[(size_t)fff]) kind |= 2;
+        else fff = ff;
+        if (ff == x || fff == x)
+            return fail(LBM_EUNSUPPORTED, "link %lld: its interpolation cells wrap onto its own cell", (long long)k);
+        keep.push_back(Link{x, ff, fff, q[k], i, kind});
+    }
+    std::vector<int64_t> sorted(keys);
+    std::sort(sorted.begin(), sorted.end());
+    for (size_t k = 1; k < sorted.size(); ++k)
+        if (sorted[k] == sorted[k - 1])
+            return fail(LBM_EINVAL, "link (cell %lld, direction %d) given twice", (long long)(sorted[k] / Q),
+                        (int)(sorted[k] % Q));
+    int rc = ensure_device(c);
+    if (rc) return rc;
+    drop_graph(c);
+    tape_invalidate(c);
+    dev_free(c->links);
+    dev_free((void *&)c->frows);
+    c->nlinks = 0;
+    c->ltd = LinkTab<double>{};
+    c->ltf = LinkTab<float>{};
+    c->link_order = order;
+    const int64_t m = (int64_t)keep.size();
+    if (m == 0) return LBM_OK;
+    const size_t cs = (c->opt.storage == LBM_F64) ? 8 : 4;
+    const size_t bytes = (size_t)m * (2 * cs + 12 + 2);
+    std::vector<char> host(bytes);
+    char *p = host.data();
+    for (int64_t k = 0; k < m; ++k) {
+        if (cs == 8) reinterpret_cast<double *>(p)[k] = keep[k].q;
+        else reinterpret_cast<float *>(p)[k] = (float)keep[k].q;
+    }
+    std::memset(p + (size_t)m * cs, 0, (size_t)m * cs);
+    int32_t *ic = reinterpret_cast<int32_t *>(p + 2 * (size_t)m * cs);
+    for (int64_t k = 0; k < m; ++k) {
+        ic[k] = (int32_t)keep[k].cell;
+        ic[m + k] = (int32_t)keep[k].ff;
+        ic[2 * m + k] = (int32_t)keep[k].fff;
+    }
+    uint8_t *b8 = reinterpret_cast<uint8_t *>(ic + 3 * m);
+    for (int64_t k = 0; k < m; ++k) {
+        b8[k] = (uint8_t)keep[k].dir;
+        b8[m + k] = (uint8_t)keep[k].kind;
+    }
+    rc = dev_alloc(&c->links, bytes, "curved links");
+    if (rc) return rc;
+    hipError_t e = hipMemcpy(c->links, host.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        dev_free(c->links);
+        return hip_fail(e, "curved link upload");
+    }
+    c->nlinks = m;
+    c->ltd = link_views<double>(c->links, m);
+    c->ltf = link_views<float>(c->links, m);
     return LBM_OK;
 }
 
@@ -595,6 +791,12 @@ hipError_t lbm::forward_step(lbm_ctx *c) {
     else mode = 2;
     hipError_t e = launch_step(g, mode, c->s != nullptr);
     if (c->opt.pattern == LBM_DOUBLE) std::swap(c->A, c->B);
+    if (e == hipSuccess && c->nlinks) {
+        // interpolated bounce-back on the curved links, on the state just written
+        Launch b = make_launch(c);
+        const void *lt = (c->opt.storage == LBM_F64) ? (const void *)&c->ltd : (const void *)&c->ltf;
+        e = launch_bouzidi(b, lt, mode != 0);
+    }
     c->t += 1;
     return e;
 }
@@ -675,14 +877,21 @@ extern "C" int lbm_forces(lbm_ctx *c, double *out) {
     int rc = ensure_device(c);
     if (rc) return rc;
     constexpr int kSlots = 21;
+    // rows: one per step-kernel workgroup, one per 256 curved links, then the total
+    const int64_t lrows = (c->nlinks + 255) / 256;
+    const int64_t rows = c->grid + lrows;
     if (!c->frows) {
-        rc = dev_alloc((void **)&c->frows, ((size_t)c->grid + 1) * kSlots * sizeof(double), "force sums");
+        rc = dev_alloc((void **)&c->frows, ((size_t)rows + 1) * kSlots * sizeof(double), "force sums");
         if (rc) return rc;
     }
     refresh_params(c);
-    double *sum_dev = c->frows + (size_t)c->grid * kSlots;
+    double *sum_dev = c->frows + (size_t)rows * kSlots;
     hipError_t e = launch_forces(make_launch(c), c->frows);
-    if (e == hipSuccess) e = launch_rows_reduce(c->frows, c->grid, kSlots, sum_dev, c->stream);
+    if (e == hipSuccess && c->nlinks) {
+        const void *lt = (c->opt.storage == LBM_F64) ? (const void *)&c->ltd : (const void *)&c->ltf;
+        e = launch_link_forces(make_launch(c), lt, c->frows + (size_t)c->grid * kSlots);
+    }
+    if (e == hipSuccess) e = launch_rows_reduce(c->frows, rows, kSlots, sum_dev, c->stream);
     double m[kSlots];
     if (e == hipSuccess) e = hipMemcpyAsync(m, sum_dev, sizeof m, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

@@ -44,6 +44,22 @@ struct FaceTab {
     int pad[2];
 };
 
+// Curved-wall links (interpolated bounce-back), structure of arrays on the
+// device.  Link k: fluid cell cell[k], direction dir[k] (cell + c_dir solid),
+// wall fraction q[k]; cff[k] = cell - c_dir and cfff[k] = cell - 2 c_dir
+// (periodic wrap applied; cfff only for quadratic links); kind[k] bit 0:
+// q >= 1/2, bit 1: quadratic weights.  dlt[k] receives, each step,
+// f*_dir(cell, t) - f_-dir(cell, t + 1) in deviation units (the part of the
+// link's momentum exchange that halfway bounce-back would not have).
+template <class CT>
+struct LinkTab {
+    const CT *q;
+    CT *dlt;
+    const int32_t *cell, *cff, *cfff;
+    const uint8_t *dir, *kind;
+    int64_t n;
+};
+
 template <class CT>
 struct Params {
     int nX, nY, nZ;        // internal extents (Z contiguous)

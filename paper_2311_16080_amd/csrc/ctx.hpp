@@ -62,6 +62,14 @@ struct lbm_ctx {
     lbm::FaceTab<double> *ftd = nullptr;   // device face tables
     lbm::FaceTab<float> *ftf = nullptr;
 
+    // curved-wall links (interpolated bounce-back)
+    std::vector<uint8_t> solid_host;       // host copy of the solid mask (N bytes), empty without solids
+    int64_t nlinks = 0;
+    int link_order = 1;
+    void *links = nullptr;                 // device block: q, dlt (compute type), cell, cff, cfff (int32), dir, kind
+    lbm::LinkTab<double> ltd{};            // views of that block
+    lbm::LinkTab<float> ltf{};
+
     int collision = 0;                     // LBM_BGK / LBM_KBC
     int walls_only = 1;                    // LBM_WALLS_ONLY = 0 / 1
 

@@ -84,6 +84,14 @@ hipError_t launch_forces(const Launch &g, double *rows) {
     return dispatch(g, OP_FORCES, 0, false, nullptr, nullptr, nullptr, nullptr, rows, 0);
 }
 
+hipError_t launch_bouzidi(const Launch &g, const void *links, bool natural) {
+    return dispatch(g, OP_BOUZIDI, natural ? 1 : 0, false, links, nullptr, nullptr, nullptr, nullptr, 0);
+}
+
+hipError_t launch_link_forces(const Launch &g, const void *links, double *rows) {
+    return dispatch(g, OP_LINK_FORCES, 0, false, links, nullptr, nullptr, nullptr, rows, 0);
+}
+
 // out[k] = sum of rows[r * slots + k] over r, one block per slot, fixed order
 __global__ void __launch_bounds__(256) k_rows_reduce(const double *__restrict__ rows, int64_t nrows, int slots,
                                                      double *__restrict__ out) {

@@ -11,7 +11,7 @@ namespace lbm {
 
 enum : int { LAT_D2Q9 = 0, LAT_D3Q19 = 1, LAT_D3Q27 = 2 };
 enum : int { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
-enum : int { OP_STEP = 0, OP_INIT = 1, OP_MOMENTS = 2, OP_FORCES = 3 };
+enum : int { OP_STEP = 0, OP_INIT = 1, OP_MOMENTS = 2, OP_FORCES = 3, OP_BOUZIDI = 4, OP_LINK_FORCES = 5 };
 
 // One launch: lattice, storage, a Params<CT> block, buffers, shape.
 struct Launch {
@@ -43,5 +43,12 @@ hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 // their fixed-order sum into out[21]
 hipError_t launch_forces(const Launch &g, double *rows);
 hipError_t launch_rows_reduce(const double *rows, int64_t nrows, int slots, double *out, hipStream_t s);
+// interpolated bounce-back on the curved links after a step (links: LinkTab<CT>
+// of the storage's compute type; natural: the state is in natural slot order,
+// i.e. after an odd in-place step or a push step)
+hipError_t launch_bouzidi(const Launch &g, const void *links, bool natural);
+// one row of 21 FP64 sums per 256 links (slots 0..2: the curved links' share of
+// the force on the solids), written to rows
+hipError_t launch_link_forces(const Launch &g, const void *links, double *rows);
 
 }  // namespace lbm

@@ -660,6 +660,130 @@ hipError_t forces_t(const Launch &g, double *rows) {
     return hipGetLastError();
 }
 
+// Interpolated bounce-back (Bouzidi, Firdaouss & Lallemand 2001) on the curved
+// links, after the step kernel has written halfway bounce-back.  With s along
+// c_i (cell x_b at 0, wall at q, x_ff = x_b - c_i at -1, x_fff at -2):
+//   q <  1/2: f_opp(x_b, t+1) = the post-collision field f*_i at s = 2q - 1
+//             (Lagrange weights through s = 0, -1 (, -2));
+//   q >= 1/2: f_opp(x_b, t+1) = the opp-field at t+1 at s = 0 through the
+//             turned f*_i(x_b) at s = 2q - 1 and f*_opp(x_b), f*_opp(x_ff)
+//             at s = -1, -2.
+// Every value needed is in the state after the step:
+//   f*_i(x_b)    the halfway value, own slot opp (either layout);
+//   f*_i(x_ff)   = f_i(x_b, t+1):  natural: slot i of x_b;    else slot opp of x_ff
+//   f*_i(x_fff)  = f_i(x_ff, t+1): natural: slot i of x_ff;   else slot opp of x_fff
+//   f*_opp(x_b)  = f_opp(x_ff, t+1): natural: slot opp of x_ff; else slot i of x_b
+//   f*_opp(x_ff) = f_opp(x_fff, t+1): natural: slot opp of x_fff; else slot i of x_ff
+// (else = after an in-place even step, where f_j(y, t+1) sits in slot opp(j)
+// of y - c_j).  None of these slots is the halfway slot of another link (the
+// link list holds only links whose x_ff -- and x_fff for quadratic weights --
+// are fluid), so the links are independent.  The interpolation is linear with
+// weights summing to one and w_i = w_opp, so it runs on the stored values
+// directly (FP16 / BF16: on h / w).
+template <class L, class ST>
+__global__ void __launch_bounds__(256) k_bouzidi(const Params<typename Store<ST>::CT> p, ST *__restrict__ A,
+                                                 const LinkTab<typename Store<ST>::CT> lt, int natural) {
+    using CT = typename Store<ST>::CT;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= lt.n) return;
+    const int i = lt.dir[k];
+    const int kind = lt.kind[k];
+    const int64_t xb = lt.cell[k], xf = lt.cff[k];
+    int o = 0;
+    CT w = 0;
+    unroll<L::Q>([&](auto I) {
+        if ((int)I == i) {
+            o = opp<L>(I);
+            w = (CT)weight<L>(I);
+        }
+    });
+    const int64_t P = p.plane;
+    auto ld = [&](int d, int64_t cell) -> CT { return Store<ST>::ld(A + (int64_t)d * P + cell); };
+    const CT q = lt.q[k];
+    const CT a = ld(o, xb);
+    CT r;
+    if (!(kind & 1)) {
+        const CT b = natural ? ld(i, xb) : ld(o, xf);
+        if (!(kind & 2)) {
+            r = (CT)2 * q * a + ((CT)1 - (CT)2 * q) * b;
+        } else {
+            const int64_t x3 = lt.cfff[k];
+            const CT c = natural ? ld(i, xf) : ld(o, x3);
+            r = q * ((CT)1 + (CT)2 * q) * a + ((CT)1 - (CT)4 * q * q) * b - q * ((CT)1 - (CT)2 * q) * c;
+        }
+    } else {
+        const CT d = natural ? ld(o, xf) : ld(i, xb);
+        if (!(kind & 2)) {
+            r = a / ((CT)2 * q) + ((CT)2 * q - (CT)1) / ((CT)2 * q) * d;
+        } else {
+            const int64_t x3 = lt.cfff[k];
+            const CT e = natural ? ld(o, x3) : ld(i, xf);
+            r = a / (q * ((CT)2 * q + (CT)1)) + ((CT)2 * q - (CT)1) / q * d + ((CT)1 - (CT)2 * q) / ((CT)1 + (CT)2 * q) * e;
+        }
+    }
+    Store<ST>::st(A + (int64_t)o * P + xb, r);
+    lt.dlt[k] = Store<ST>::scaled ? (a - r) * w : (a - r);
+}
+
+// The curved links' share of the momentum exchange on the solids: over the
+// links, (f*_i + f_opp(t+1)) c_i = 2 f_opp(t+1) c_i (what k_forces counts from
+// the state) + dlt c_i.  One row of kForceSlots FP64 sums per block (slots
+// 0..2, internal axes), wavefront sums then wavefronts in order.
+template <class L, class CT>
+__global__ void __launch_bounds__(256) k_link_forces(const LinkTab<CT> lt, double *__restrict__ rows) {
+    __shared__ double red[3][4];
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (k < lt.n) {
+        const int i = lt.dir[k];
+        const double d = (double)lt.dlt[k];
+        unroll<L::Q>([&](auto I) {
+            if ((int)I == i) {
+                v[0] = d * L::c[I][0];
+                v[1] = d * L::c[I][1];
+                v[2] = d * L::c[I][2];
+            }
+        });
+    }
+    const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+    for (int a = 0; a < 3; ++a) {
+        double t = v[a];
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+        if (lane == 0) red[a][wv] = t;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < kForceSlots) {
+        double t = 0.0;
+        if (threadIdx.x < 3) {
+            const int nw = ((int)blockDim.x + 63) / 64;
+            for (int w = 0; w < nw; ++w) t += red[threadIdx.x][w];
+        }
+        rows[(int64_t)blockIdx.x * kForceSlots + threadIdx.x] = t;
+    }
+}
+
+template <class L, class ST>
+hipError_t bouzidi_t(const Launch &g, const void *links, bool natural) {
+    using CT = typename Store<ST>::CT;
+    const Params<CT> &p = *static_cast<const Params<CT> *>(g.params);
+    const LinkTab<CT> &lt = *static_cast<const LinkTab<CT> *>(links);
+    if (lt.n <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)((lt.n + 255) / 256);
+    hipLaunchKernelGGL((k_bouzidi<L, ST>), dim3(nb), dim3(256), 0, g.stream, p, static_cast<ST *>(g.A), lt,
+                       natural ? 1 : 0);
+    return hipGetLastError();
+}
+
+template <class L, class ST>
+hipError_t link_forces_t(const Launch &g, const void *links, double *rows) {
+    using CT = typename Store<ST>::CT;
+    const LinkTab<CT> &lt = *static_cast<const LinkTab<CT> *>(links);
+    if (lt.n <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)((lt.n + 255) / 256);
+    hipLaunchKernelGGL((k_link_forces<L, CT>), dim3(nb), dim3(256), 0, g.stream, lt, rows);
+    return hipGetLastError();
+}
+
 // Launches for one (lattice, storage) pair; instantiated in kernels_<lat>_<st>.hip.
 template <class L, class ST>
 hipError_t dispatch_one(const Launch &g, int op, int a0, bool b0, const void *p0, const void *p1, void *q0, void *q1,
@@ -668,6 +792,8 @@ hipError_t dispatch_one(const Launch &g, int op, int a0, bool b0, const void *p0
     if (op == OP_INIT) return init_t<L, ST>(g, p0, p1, a0, N);
     if (op == OP_MOMENTS) return moments_t<L, ST>(g, b0, q0, q1, a0, partial, N);
     if (op == OP_FORCES) return forces_t<L, ST>(g, partial);
+    if (op == OP_BOUZIDI) return bouzidi_t<L, ST>(g, p0, a0 != 0);
+    if (op == OP_LINK_FORCES) return link_forces_t<L, ST>(g, p0, partial);
     return hipErrorInvalidValue;
 }
 

@@ -283,6 +283,7 @@ static int backward_impl(lbm_ctx *c, const void *dL_drho, const void *dL_du, int
         return fail(LBM_EINVAL, "dtype must be LBM_F64 or LBM_F32");
     if (!c->tape) return fail(LBM_ESTATE, "no tape recorded");
     if (has_regularized_face(c)) return fail(LBM_EUNSUPPORTED, "the adjoint of regularized faces is not implemented");
+    if (c->nlinks) return fail(LBM_EUNSUPPORTED, "the adjoint of interpolated bounce-back is not implemented");
     if (c->collision != LBM_BGK) return fail(LBM_EUNSUPPORTED, "the adjoint covers the BGK collision only");
     if (want_force && c->batch) return fail(LBM_EUNSUPPORTED, "body forces are not supported on batch contexts");
     if (c->tape_recording) lbm_tape_end(c);

@@ -51,6 +51,8 @@ _ip, _dp = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
 SIGNATURES = {
     "lbm_last_error": (ctypes.c_char_p, []),
     "lbm_version": (ctypes.c_char_p, []),
+    "lbm_lattice_info": (_i, [_i, ctypes.POINTER(ctypes.c_int32), _dp]),
+    "lbm_set_curved_links": (_i, [_vp, _i64, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32), _dp, _i]),
     "lbm_create": (_vp, [_i, _i, _i, _i, _d, ctypes.POINTER(lbm_bc)]),
     "lbm_create_batch": (_vp, [_i, _i, _ip, _ip, _ip, _dp, ctypes.POINTER(lbm_bc)]),
     "lbm_batch_offsets": (_i, [_vp, ctypes.POINTER(ctypes.c_int64)]),
@@ -123,6 +125,18 @@ def last_error() -> str:
 def check(rc: int) -> None:
     if rc != LBM_OK:
         raise LbmError(rc, last_error())
+
+
+def lattice_info(lattice):
+    """(c [Q, 3] int, w [Q] float64) of the library's velocity set, caller axes."""
+    lat = LATTICES[lattice] if isinstance(lattice, str) else int(lattice)
+    Q = Q_OF[lat]
+    c = (ctypes.c_int32 * (3 * Q))()
+    w = (ctypes.c_double * Q)()
+    n = lib().lbm_lattice_info(lat, c, w)
+    if n != Q:
+        raise LbmError(n, last_error())
+    return np.array(list(c), dtype=np.int64).reshape(Q, 3), np.array(list(w))
 
 
 def make_bc(faces) -> lbm_bc:
@@ -218,6 +232,21 @@ class Sim:
         else:
             m = np.ascontiguousarray(np.asarray(mask).reshape(self.shape), dtype=np.uint8)
             check(lib().lbm_set_solid(self.h, m.ctypes.data_as(ctypes.c_void_p), 0))
+
+    def set_curved_links(self, cells, dirs, q, order: int = 1):
+        """Interpolated bounce-back on links (cells[k], dirs[k]) into solid cells
+        cut by the wall at fraction q[k] (host arrays; flat caller-order cells,
+        lattice_info direction order); order 1 linear, 2 quadratic.  Empty
+        arrays clear the links."""
+        cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int64).reshape(-1))
+        dirs = np.ascontiguousarray(np.asarray(dirs, dtype=np.int32).reshape(-1))
+        q = np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(-1))
+        if not (cells.size == dirs.size == q.size):
+            raise ValueError("cells, dirs and q must have the same length")
+        P = ctypes.POINTER
+        check(lib().lbm_set_curved_links(self.h, int(cells.size), cells.ctypes.data_as(P(ctypes.c_int64)),
+                                         dirs.ctypes.data_as(P(ctypes.c_int32)),
+                                         q.ctypes.data_as(P(ctypes.c_double)), int(order)))
 
     def set_solid_fraction(self, s):
         torch = _torch()

@@ -27,6 +27,8 @@ class Case:
     init_seed: Optional[int] = None    # random (rho, u) init; None = rest
     init_u: Optional[np.ndarray] = None  # explicit velocity (*shape, D)
     amp: float = 0.03
+    links: Optional[tuple] = None      # curved-wall links (cells, dirs, q), flat caller order
+    bz_order: int = 1                  # interpolated bounce-back: 1 linear, 2 quadratic
 
     @property
     def D(self):
@@ -64,7 +66,9 @@ def oracle_run(case: Case, steps: Optional[int] = None):
     # the C-ABI takes the solid fraction as float32: both sides get the same rounded values
     sv = None if case.s is None else case.s.reshape(case.oshape).astype(np.float32).astype(np.float64)
     S = oracle.Sim(q=case.q, nx=case.oshape[0], ny=case.oshape[1], nz=case.oshape[2], tau=case.tau,
-                   faces=faces, solid=sol, s=sv)
+                   faces=faces, solid=sol, s=sv, bouzidi_order=case.bz_order)
+    if case.links is not None:
+        S.qlink = S.links_to_qlink(*case.links)
     rho, u = case.init_fields()
     if u is not None:
         u = u.reshape(case.oshape + (case.D,))
@@ -82,6 +86,8 @@ def gpu_sim(case: Case):
                   pattern=case.pattern)
     if case.solid is not None:
         sim.set_solid(case.solid)
+    if case.links is not None:
+        sim.set_curved_links(*case.links, order=case.bz_order)
     if case.s is not None:
         sim.set_solid_fraction(case.s.astype(np.float32))
     rho, u = case.init_fields()

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2311_16080_amd import lbm
@@ -175,3 +176,28 @@ def test_tape_id_without_device():
         assert L.lbm_tape_id(h) == 0
     finally:
         L.lbm_destroy(h)
+
+
+@pytest.mark.parametrize("lat,q", [(lbm.D2Q9, 9), (lbm.D3Q19, 19), (lbm.D3Q27, 27)])
+def test_lattice_info_matches_the_figure(lat, q):
+    """lbm_lattice_info (no device work) reports the paper's vector order
+    (tests/golden/lattice_vectors.txt) and weights that sum to one with
+    sum_i w_i c_ia c_ib = delta_ab / 3 in exact rationals."""
+    from fractions import Fraction
+    c, w = lbm.lattice_info(lat)
+    assert c.shape == (q, 3)
+    rows = []
+    with open(os.path.join(ROOT, "tests", "golden", "lattice_vectors.txt")) as fh:
+        for line in fh:
+            v = line.split()
+            if v and not v[0].startswith("#") and int(v[0]) == q:
+                rows.append([int(x) for x in v[1:4]])
+    ref = np.array(rows)
+    assert ref.shape == (q, 3)
+    assert np.array_equal(c, ref)
+    W = [Fraction(x).limit_denominator(1000) for x in w]
+    assert sum(W) == 1
+    for a in range(3 if q != 9 else 2):
+        for b in range(3 if q != 9 else 2):
+            assert sum(W[i] * int(c[i, a]) * int(c[i, b]) for i in range(q)) == (Fraction(1, 3) if a == b else 0)
+    assert lbm.lib().lbm_lattice_info(7, None, None) == lbm.LBM_EINVAL
