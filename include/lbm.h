@@ -304,6 +304,23 @@ int lbm_moments(lbm_ctx *ctx, void *rho, void *u, int dtype, double *sums_host);
 int lbm_forces(lbm_ctx *ctx, double *out);
 
 /*
+ * lbm_forces for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same 21 FP64 sums
+ * (same layout, caller axes), written to the caller's device buffer out_dev
+ * (21 doubles) on the context's stream, with no allocation and no
+ * synchronisation; the caller reads it after the stream's work.  The per-block
+ * partial sums go to a fixed scratch array of 3.4 MB that each GPU holds for
+ * the life of the process (rows of up to 16384 x 4096 step-kernel workgroups
+ * plus curved-link blocks; larger grids get LBM_EINVAL -- use lbm_forces).
+ * The scratch is shared by every call on a GPU: calls that overlap on one GPU
+ * (other streams, other threads) race and must be ordered by the caller.  The
+ * partial sums are added in a fixed order (per pass of 16384 rows, then the
+ * passes), so the result is deterministic; it differs from lbm_forces only in
+ * that summation order.  Errors as lbm_forces; LBM_EINVAL for a NULL out_dev.
+ */
+int lbm_forces_noalloc(lbm_ctx *ctx, double *out_dev);
+
+/*
  * Body force by the exact-difference method (Sec. 4.4 and 6.1, after Kupershtokh, the
  * forcing of the paper's turbulent channel and of its neural corrector): from
  * the next step on, every fluid cell's relaxed populations gain

@@ -28,7 +28,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
-SOURCES = ["kernels.hip", "kernels_d2q9_f64.hip", "kernels_d2q9_f32.hip", "kernels_d2q9_f16.hip", "kernels_d2q9_bf16.hip", "kernels_d3q19_f64.hip", "kernels_d3q19_f32.hip", "kernels_d3q19_f16.hip", "kernels_d3q19_bf16.hip", "kernels_d3q27_f64.hip", "kernels_d3q27_f32.hip", "kernels_d3q27_f16.hip", "kernels_d3q27_bf16.hip", "capi.hip", "graph.hip", "tape.hip", "batch.hip", "adjoint.hip", "batch_kernels.hip"]
+SOURCES = ["kernels.hip", "kernels_d2q9_f64.hip", "kernels_d2q9_f32.hip", "kernels_d2q9_f16.hip", "kernels_d2q9_bf16.hip", "kernels_d3q19_f64.hip", "kernels_d3q19_f32.hip", "kernels_d3q19_f16.hip", "kernels_d3q19_bf16.hip", "kernels_d3q27_f64.hip", "kernels_d3q27_f32.hip", "kernels_d3q27_f16.hip", "kernels_d3q27_bf16.hip", "capi.hip", "graph.hip", "tape.hip", "batch.hip", "adjoint.hip", "batch_kernels.hip", "noalloc.hip"]
 
 
 def _compile(src: str) -> str:

@@ -80,16 +80,16 @@ hipError_t launch_reduce(const double *partial, const int64_t *begin, const int6
     return hipGetLastError();
 }
 
-hipError_t launch_forces(const Launch &g, double *rows) {
-    return dispatch(g, OP_FORCES, 0, false, nullptr, nullptr, nullptr, nullptr, rows, 0);
+hipError_t launch_forces(const Launch &g, double *rows, int64_t b0, int64_t nb) {
+    return dispatch(g, OP_FORCES, 0, false, nullptr, nullptr, nullptr, nullptr, rows, (b0 << 32) | nb);
 }
 
 hipError_t launch_bouzidi(const Launch &g, const void *links, bool natural) {
     return dispatch(g, OP_BOUZIDI, natural ? 1 : 0, false, links, nullptr, nullptr, nullptr, nullptr, 0);
 }
 
-hipError_t launch_link_forces(const Launch &g, const void *links, double *rows) {
-    return dispatch(g, OP_LINK_FORCES, 0, false, links, nullptr, nullptr, nullptr, rows, 0);
+hipError_t launch_link_forces(const Launch &g, const void *links, double *rows, int64_t r0, int64_t nr) {
+    return dispatch(g, OP_LINK_FORCES, 0, false, links, nullptr, nullptr, nullptr, rows, (r0 << 32) | nr);
 }
 
 // out[k] = sum of rows[r * slots + k] over r, one block per slot, fixed order

@@ -39,16 +39,18 @@ hipError_t launch_reduce(const double *partial, const int64_t *begin, const int6
                          hipStream_t s);
 hipError_t launch_solid(int lattice, const Launch &g, const uint8_t *solid, uint8_t *flags, uint32_t *nbm);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
-// momentum-exchange force rows (grid x 21 FP64) of the current state, then
-// their fixed-order sum into out[21]
-hipError_t launch_forces(const Launch &g, double *rows);
+// momentum-exchange force rows (one row of 21 FP64 per step-kernel workgroup)
+// of the current state for workgroups [b0, b0 + nb) (nb = 0: b0 to the end;
+// b0, nb < 2^31), written from rows[0]; then their fixed-order sum into out[21]
+hipError_t launch_forces(const Launch &g, double *rows, int64_t b0 = 0, int64_t nb = 0);
 hipError_t launch_rows_reduce(const double *rows, int64_t nrows, int slots, double *out, hipStream_t s);
 // interpolated bounce-back on the curved links after a step (links: LinkTab<CT>
 // of the storage's compute type; natural: the state is in natural slot order,
 // i.e. after an odd in-place step or a push step)
 hipError_t launch_bouzidi(const Launch &g, const void *links, bool natural);
 // one row of 21 FP64 sums per 256 links (slots 0..2: the curved links' share of
-// the force on the solids), written to rows
-hipError_t launch_link_forces(const Launch &g, const void *links, double *rows);
+// the force on the solids) for row blocks [r0, r0 + nr) (nr = 0: to the end),
+// written from rows[0]
+hipError_t launch_link_forces(const Launch &g, const void *links, double *rows, int64_t r0 = 0, int64_t nr = 0);
 
 }  // namespace lbm

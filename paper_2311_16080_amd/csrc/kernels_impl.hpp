@@ -32,10 +32,10 @@ namespace lbm {
 // Optionally (LBM_ZROT=1) lanes are rotated by p.zrot = 32 within a row of
 // >= 64 cells, so the row's two end cells share one wavefront; since the wall
 // path made boundary wavefronts cheap, aligned rows measure as fast or faster.
+// block_cell_at: the same for block b of a G-block covering (a launch that
+// covers blocks [b0, b0 + gridDim.x) of it).
 template <class CT>
-__device__ __forceinline__ bool block_cell(const Params<CT> &p, int &X, int &Y, int &Z) {
-    const int G = (int)gridDim.x;
-    int b = (int)blockIdx.x;
+__device__ __forceinline__ bool block_cell_at(const Params<CT> &p, int b, int G, int &X, int &Y, int &Z) {
     if (p.xcd_remap && (G & 7) == 0) b = (b & 7) * (G >> 3) + (b >> 3);
     const int zc = b % p.zblocks;
     const int r = b / p.zblocks;
@@ -44,6 +44,10 @@ __device__ __forceinline__ bool block_cell(const Params<CT> &p, int &X, int &Y, 
     const int lin = zc * (int)blockDim.x + (int)threadIdx.x;
     Z = (lin >= p.zrot) ? lin - p.zrot : lin - p.zrot + p.nZ;
     return lin < p.nZ;
+}
+template <class CT>
+__device__ __forceinline__ bool block_cell(const Params<CT> &p, int &X, int &Y, int &Z) {
+    return block_cell_at(p, (int)blockIdx.x, (int)gridDim.x, X, Y, Z);
 }
 
 // One cell of one step.  p: the domain's parameters; A (and B for the push
@@ -578,9 +582,11 @@ hipError_t moments_t(const Launch &g, bool odd, void *rho, void *u, int out_f64,
 // wall faces counts for the lowest-index one).
 constexpr int kForceSlots = 21;
 
+// This launch covers blocks [b0, b0 + gridDim.x) of the step grid of G blocks
+// and writes its rows at rows[0 ..).
 template <class L, class ST>
 __global__ void __launch_bounds__(kMaxBlock) k_forces(const Params<typename Store<ST>::CT> p, const ST *__restrict__ A,
-                                                      double *__restrict__ rows) {
+                                                      double *__restrict__ rows, int64_t b0, int64_t G) {
     constexpr int Q = L::Q;
     __shared__ double red[kForceSlots][kMaxBlock / 64];
     int X, Y, Z;
@@ -588,7 +594,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_forces(const Params<typename Stor
 #pragma unroll
     for (int k = 0; k < kForceSlots; ++k) part[k] = 0.0;
     bool links = false;
-    if (block_cell(p, X, Y, Z)) {
+    if (block_cell_at(p, (int)(b0 + (int64_t)blockIdx.x), (int)G, X, Y, Z)) {
         const int64_t cell = ((int64_t)X * p.nY + Y) * p.nZ + Z;
         uint32_t nbm = 0;
         bool solid = false;
@@ -651,12 +657,15 @@ __global__ void __launch_bounds__(kMaxBlock) k_forces(const Params<typename Stor
     }
 }
 
+// blocks [b0, b0 + nb) of the step grid (nb = 0: all of it)
 template <class L, class ST>
-hipError_t forces_t(const Launch &g, double *rows) {
+hipError_t forces_t(const Launch &g, double *rows, int64_t b0, int64_t nb) {
     using CT = typename Store<ST>::CT;
     const Params<CT> &p = *static_cast<const Params<CT> *>(g.params);
-    hipLaunchKernelGGL((k_forces<L, ST>), dim3(g.grid), dim3(g.block), 0, g.stream, p, static_cast<const ST *>(g.A),
-                       rows);
+    if (nb <= 0) nb = (int64_t)g.grid - b0;
+    if (nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_forces<L, ST>), dim3((unsigned)nb), dim3(g.block), 0, g.stream, p,
+                       static_cast<const ST *>(g.A), rows, b0, (int64_t)g.grid);
     return hipGetLastError();
 }
 
@@ -729,10 +738,12 @@ __global__ void __launch_bounds__(256) k_bouzidi(const Params<typename Store<ST>
 // links, (f*_i + f_opp(t+1)) c_i = 2 f_opp(t+1) c_i (what k_forces counts from
 // the state) + dlt c_i.  One row of kForceSlots FP64 sums per block (slots
 // 0..2, internal axes), wavefront sums then wavefronts in order.
+// This launch covers links [l0, ..) (l0 a multiple of 256) and writes its
+// rows at rows[0 ..).
 template <class L, class CT>
-__global__ void __launch_bounds__(256) k_link_forces(const LinkTab<CT> lt, double *__restrict__ rows) {
+__global__ void __launch_bounds__(256) k_link_forces(const LinkTab<CT> lt, double *__restrict__ rows, int64_t l0) {
     __shared__ double red[3][4];
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = l0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double v[3] = {0.0, 0.0, 0.0};
     if (k < lt.n) {
         const int i = lt.dir[k];
@@ -774,13 +785,15 @@ hipError_t bouzidi_t(const Launch &g, const void *links, bool natural) {
     return hipGetLastError();
 }
 
+// row blocks [r0, r0 + nr) of 256 links each (nr = 0: all)
 template <class L, class ST>
-hipError_t link_forces_t(const Launch &g, const void *links, double *rows) {
+hipError_t link_forces_t(const Launch &g, const void *links, double *rows, int64_t r0, int64_t nr) {
     using CT = typename Store<ST>::CT;
     const LinkTab<CT> &lt = *static_cast<const LinkTab<CT> *>(links);
-    if (lt.n <= 0) return hipSuccess;
-    const unsigned nb = (unsigned)((lt.n + 255) / 256);
-    hipLaunchKernelGGL((k_link_forces<L, CT>), dim3(nb), dim3(256), 0, g.stream, lt, rows);
+    const int64_t all = (lt.n + 255) / 256;
+    if (nr <= 0) nr = all - r0;
+    if (lt.n <= 0 || nr <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_link_forces<L, CT>), dim3((unsigned)nr), dim3(256), 0, g.stream, lt, rows, r0 * 256);
     return hipGetLastError();
 }
 
@@ -791,9 +804,10 @@ hipError_t dispatch_one(const Launch &g, int op, int a0, bool b0, const void *p0
     if (op == OP_STEP) return step_t<L, ST>(g, a0, b0);
     if (op == OP_INIT) return init_t<L, ST>(g, p0, p1, a0, N);
     if (op == OP_MOMENTS) return moments_t<L, ST>(g, b0, q0, q1, a0, partial, N);
-    if (op == OP_FORCES) return forces_t<L, ST>(g, partial);
+    // OP_FORCES / OP_LINK_FORCES: N = first block (row) << 32 | count of this launch
+    if (op == OP_FORCES) return forces_t<L, ST>(g, partial, N >> 32, N & 0xffffffff);
     if (op == OP_BOUZIDI) return bouzidi_t<L, ST>(g, p0, a0 != 0);
-    if (op == OP_LINK_FORCES) return link_forces_t<L, ST>(g, p0, partial);
+    if (op == OP_LINK_FORCES) return link_forces_t<L, ST>(g, p0, partial, N >> 32, N & 0xffffffff);
     return hipErrorInvalidValue;
 }
 

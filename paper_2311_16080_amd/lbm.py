@@ -69,6 +69,7 @@ SIGNATURES = {
     "lbm_time": (_i64, [_vp]),
     "lbm_moments": (_i, [_vp, _vp, _vp, _i, _dp]),
     "lbm_forces": (_i, [_vp, _dp]),
+    "lbm_forces_noalloc": (_i, [_vp, _vp]),
     "lbm_set_force": (_i, [_vp, _dp, _vp, ctypes.c_double]),
     "lbm_set_collision": (_i, [_vp, _i]),
     "lbm_tape_begin": (_i, [_vp, _i, _i]),
