@@ -32,6 +32,16 @@ namespace lbm {
 
 template <class CT>
 __device__ __forceinline__ bool adj_block_cell(const Params<CT> &p, int &X, int &Y, int &Z) {
+    if (p.flat) {
+        // consecutive cells of the whole grid (rows not a multiple of 64 cells)
+        const uint32_t cell = (uint32_t)blockIdx.x * blockDim.x + threadIdx.x;
+        const uint32_t nz = (uint32_t)p.nZ, ny = (uint32_t)p.nY;
+        const uint32_t r = cell / nz;
+        Z = (int)(cell - r * nz);
+        Y = (int)(r % ny);
+        X = (int)(r / ny);
+        return X < p.nX;
+    }
     const int zc = (int)blockIdx.x % p.zblocks;
     const int r = (int)blockIdx.x / p.zblocks;
     Y = r % p.nY;

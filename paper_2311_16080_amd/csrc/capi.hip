@@ -192,7 +192,8 @@ static void fill_params(Params<CT> &p, const lbm_ctx *c) {
     p.xcd_remap = c->xcd_remap;
     // measured: with the wall path, aligned rows (no rotation) are as fast or
     // faster on every lattice; the rotation stays available for measurement
-    p.zrot = (c->zrot > 0 && c->nZ >= 64) ? 32 : 0;
+    p.zrot = (c->zrot > 0 && c->nZ >= 64 && !c->flat) ? 32 : 0;
+    p.flat = c->flat;
     p.ft = face_table<CT>(c);
     p.flags = c->flags;
     p.nbm = c->nbm;
@@ -266,6 +267,17 @@ static void setup_shape(lbm_ctx *c, int lattice, int nx, int ny, int nz, double 
     // faster than 256, whose second block per row is half idle, and 7% faster
     // than 192)
     const int r64 = (c->nZ + 63) / 64 * 64;
+    // rows whose length is not a multiple of 64 cells: blocks of 256 consecutive
+    // cells of the whole grid instead of row chunks (aligned, fully occupied
+    // wavefronts; measured on 256 x 256 x 300: row chunks start misaligned in
+    // every row and leave 22% of the lanes idle)
+    c->flat = (c->flat_req >= 0) ? c->flat_req : ((c->nZ % 64) != 0 ? 1 : 0);
+    if (c->flat) {
+        c->block = c->block_req > 0 ? c->block_req : 256;
+        c->zblocks = 1;
+        c->grid = (c->N + c->block - 1) / c->block;
+        return;
+    }
     int blk = r64;
     if (c->block_req > 0) {
         if (blk > c->block_req) blk = c->block_req;
@@ -309,6 +321,8 @@ extern "C" lbm_ctx *lbm_create(int lattice, int nx, int ny, int nz, double tau, 
         if (zr && (zr[0] == '0' || zr[0] == '1')) c->zrot = zr[0] - '0';
         const char *wo = std::getenv("LBM_WALLS_ONLY");
         if (wo && (wo[0] == '0' || wo[0] == '1')) c->walls_only = wo[0] - '0';
+        const char *fl = std::getenv("LBM_FLAT");
+        if (fl && (fl[0] == '0' || fl[0] == '1')) c->flat_req = fl[0] - '0';
         const char *bl = std::getenv("LBM_BLOCK");
         if (bl) {
             const int v = std::atoi(bl);

@@ -78,7 +78,7 @@ struct Params {
     int zh_pending;        // the state read needs the Zou-He closure (t > 0)
     int xcd_remap;         // give each XCD a contiguous range of rows
     int zrot;              // lane rotation within a Z row (block_cell)
-    int pad1;
+    int flat;              // lanes cover consecutive cells of the whole grid (rows not a multiple of 64 cells)
     const uint8_t *flags;  // N bytes or null: bit0 solid, bit1 a neighbour is solid
     const uint32_t *nbm;   // N words: bit k set when x - c_k is a solid cell
     const float *s;        // N or null: partial bounce-back solid fraction

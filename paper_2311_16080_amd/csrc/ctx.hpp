@@ -46,6 +46,8 @@ struct lbm_ctx {
     int zrot = 0;                    // LBM_ZROT = 0 / 1: rotate lanes within a Z row by 32
     int pair = 1;                    // LBM_PAIR = 0 / 1 / 2: two cells per lane for FP16 / BF16 storage (0 never, 1 even steps, 2 all in-place steps)
     int block_req = 0;               // LBM_BLOCK = 64 / 128 / 192 / 256 (threads per block, along Z); 0: by row length
+    int flat = 0;                    // blocks cover consecutive cells of the grid (rows not a multiple of 64 cells)
+    int flat_req = -1;               // LBM_FLAT = 0 / 1 forces the row / flat mapping (measurement); -1: by row length
 
     // device
     int device = -1;

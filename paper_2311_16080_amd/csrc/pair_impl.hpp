@@ -18,10 +18,13 @@
 // to storage), so both paths give bitwise-equal states.
 //
 // Measured on the D3Q19 FP16 256^3 cavity: the even (local) step drops from
-// 305 to 224 us.  The odd step needs ~133 VGPRs (3 waves per SIMD; forcing 4
-// spills) and runs slower than one cell per lane (400-590 vs 288 us), so by
-// default only even steps use this kernel (LBM_PAIR=2 selects it for odd
-// steps too, for measurement).
+// 305 to 224 us (222 us for the variant without the per-cell fallback that
+// walls-only domains without solids use).  Two cells per lane measured slower
+// than one for the odd step, both with wavefront shifts (~134 VGPRs, 400-590
+// us) and with the Z-shifted planes staged through LDS behind block barriers
+// (~400 us at 3 or 4 waves per SIMD), against 277 us with one cell per lane,
+// so by default only even steps use this kernel (LBM_PAIR=2 selects it for
+// odd steps too, for measurement).
 #pragma once
 
 namespace lbm {
@@ -82,7 +85,11 @@ __device__ __forceinline__ float wall_term(const Params<float> &p, uint32_t cr, 
     return hpi;
 }
 
-template <class L, class ST, int MODE, bool HAS_S>
+// NOFB: the domain has no solid cells and walls on every lattice face (the host
+// checks), so the per-cell fallback is never needed and is left out -- it
+// would otherwise set the kernel's register allocation (109 vs 64 VGPRs for
+// the D3Q19 FP16 even step).
+template <class L, class ST, int MODE, bool HAS_S, bool NOFB = false>
 __device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict__ A, int X, int Y, int z0,
                                           int pending) {
     constexpr int Q = L::Q;
@@ -97,7 +104,7 @@ __device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict
     const uint32_t e1 = edge_bits(p, X, Y, z0 + 1);
     // walls, and in the local even step periodic faces too (no neighbour addresses)
     const uint32_t sel_faces = p.wallmask | (MODE == 0 ? p.permask : 0u);
-    if (!__all(plain && ((e0 | e1) & kFaces & ~sel_faces) == 0)) {
+    if (!NOFB && !__all(plain && ((e0 | e1) & kFaces & ~sel_faces) == 0)) {
         // (the even step's select path takes periodic faces too)
         constexpr int XF = (HAS_S ? 1 : 0) | (MODE == 0 ? 4 : 0);
         step_cell<L, ST, MODE, XF, 1>(p, A, nullptr, X, Y, z0, pending);
@@ -215,13 +222,13 @@ __device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict
 }
 
 // one lane per cell pair; grid: rows x (nZ / 2 / blockDim.x)
-template <class L, class ST, int MODE, bool HAS_S>
+template <class L, class ST, int MODE, bool HAS_S, bool NOFB = false>
 __global__ void __launch_bounds__(kMaxBlock) k_step_pair(const Params<float> p, ST *__restrict__ A) {
     const int per_row = (p.nZ >> 1) / (int)blockDim.x;
     const int b = (int)blockIdx.x;
     const int r = b / per_row;
     const int z0 = 2 * ((b - r * per_row) * (int)blockDim.x + (int)threadIdx.x);
-    step_pair<L, ST, MODE, HAS_S>(p, A, r / p.nY, r % p.nY, z0, p.zh_pending);
+    step_pair<L, ST, MODE, HAS_S, NOFB>(p, A, r / p.nY, r % p.nY, z0, p.zh_pending);
 }
 
 }  // namespace lbm

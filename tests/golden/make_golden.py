@@ -9,8 +9,10 @@ library.  Run once (about 15-25 minutes on 8 cores):
 cavity256       -- D3Q19 lid-driven cavity 256^3, tau = 0.55, five static
                    halfway bounce-back walls, lid (+z) moving at u = (0.05, 0, 0),
                    start at rest (f = w_i), 1000 steps.  Stored: u and rho on
-                   the whole planes y = 128 and x = 128 (every cell), the field
-                   sums.
+                   the whole planes y = 128 and x = 128 (every cell); u at a
+                   uniform random sample of 262144 cells (flat indices from
+                   numpy's default_rng(7), stored with the values), whose
+                   rel-L2 estimates the whole field's; the field sums.
 c4_adjoint      -- D2Q9 channel 512 x 256, tau = 0.6, Zou-He inlet u = (0.04, 0),
                    equilibrium outflow, walls on +-y, solid fraction s from
                    seed 4 (float32-rounded, as the library takes it), start at
@@ -40,6 +42,9 @@ import oracle  # noqa: E402
 from paper_2311_16080_amd import inputs  # noqa: E402
 
 
+CAVITY_SAMPLE = 262144
+
+
 def cavity256(steps=1000, n=256):
     faces = [oracle.Face(oracle.WALL) for _ in range(6)]
     faces[5] = oracle.Face(oracle.WALL, (0.05, 0.0, 0.0))
@@ -50,9 +55,11 @@ def cavity256(steps=1000, n=256):
         S.run(f, min(100, steps - k))
         print(f"cavity256: {k + 100} steps, {time.time() - t0:.0f} s", flush=True)
     rho, u = S.moments(f)
+    idx = np.sort(np.random.default_rng(7).choice(n ** 3, size=CAVITY_SAMPLE, replace=False))
     np.savez_compressed(os.path.join(HERE, "cavity256_d3q19_1000.npz"),
                         u_y128=u[:, n // 2, :, :], rho_y128=rho[:, n // 2, :],
-                        u_x128=u[n // 2, :, :, :], rho_x128=rho[n // 2, :, :], sums=S.sums(f),
+                        u_x128=u[n // 2, :, :, :], rho_x128=rho[n // 2, :, :],
+                        sample_cells=idx, u_sample=u.reshape(-1, 3)[idx], sums=S.sums(f),
                         steps=steps, stride=1)
 
 

@@ -149,3 +149,27 @@ def test_batch_of_tiny_domains_matches_oracle():
         ug = np.stack([bs.domain(u, d)[k].cpu().numpy() for k in range(2)], -1)
         assert np.max(np.abs(rg - ro[..., 0])) <= 1e-13, d
         assert np.max(np.abs(ug - uo[..., 0, :2])) <= 1e-13, d
+
+
+@pytest.mark.parametrize("q,shape,faces", [
+    (19, (7, 6, 300), [(ZV, (0.03, 0, 0)), (OUT, (0, 0, 0), 1.0), (W,), (W, (0.02, 0, 0)), (W,), (W,)]),
+    (9, (33, 65), [(W,), (W,), (P,), (P,), (P,), (P,)]),
+    (27, (5, 6, 70), [(W,)] * 5 + [(W, (0.05, 0.0, 0.0))]),
+    (19, (4, 3, 1), [(W,), (W, (0, 0.02, 0.0)), (W,), (W,), (P,), (P,)]),
+])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_flat_and_row_lane_mappings_agree_bitwise(q, shape, faces, storage, monkeypatch):
+    """Rows whose length is not a multiple of 64 cells run with blocks of
+    consecutive cells of the whole grid (LBM_FLAT=1, the default there); the
+    row-chunk mapping (LBM_FLAT=0) runs the same per-cell arithmetic, so the
+    moments agree bit for bit after even and odd step counts."""
+    _announce(f"flat vs row lanes q={q} {shape} {storage}")
+    out = {}
+    for flat in ("0", "1"):
+        monkeypatch.setenv("LBM_FLAT", flat)
+        for steps in (8, 9):
+            g = gpu_run(Case(q, shape, 0.6, faces, steps=steps, storage=storage, init_seed=95))
+            out[(flat, steps)] = (g[0], g[1])
+    for steps in (8, 9):
+        a, b = out[("0", steps)], out[("1", steps)]
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), steps

@@ -213,6 +213,10 @@ PAIR_CASES = {
     "channel_zouhe_d3q19": (19, (20, 6, 128), [(ZV, (0.03, 0, 0)), (OUT, (0, 0, 0), 1.0), (W,), (W,), (W,), (W,)]),
     "cavity_d2q9": (9, (40, 256), [(W,), (W,), (W,), (W, (0.08, 0.0)), (P,), (P,)]),
     "spheres_d3q27": (27, (24, 12, 128), [(ZV, (0.03, 0, 0)), (OUT, (0, 0, 0), 1.0), (W,), (W,), (W,), (W,)]),
+    # rows of several blocks (768 cells: two blocks of 192 lanes; 1024: two of 256)
+    "cavity_d3q19_rows768": (19, (4, 5, 768), [(W,), (W, (0, 0.02, 0.01)), (W,), (W,), (W,), (W, (0.05, 0.01, 0))]),
+    "cavity_d3q27_rows1024": (27, (3, 4, 1024), [(W,)] * 5 + [(W, (0.04, 0.02, 0.0))]),
+    "pbb_d2q9": (9, (24, 256), [(W,), (W,), (W,), (W, (0.06, 0.0)), (P,), (P,)]),
 }
 
 
@@ -224,12 +228,14 @@ def test_pair_kernel_matches_one_cell_per_lane_bitwise(name, storage, monkeypatc
     _announce(f"pair kernel {name} {storage}")
     q, shape, faces = PAIR_CASES[name]
     solid = spheres(shape) if name.startswith("spheres") else None
+    sfrac = inputs.smooth_solid_fraction(*shape, seed=4, sigma=3, edge=4) if name.startswith("pbb") else None
     res = {}
-    for pair in ("0", "1", "2"):       # never / even steps / even and odd steps
+    # never / even steps / even and odd steps
+    for pair in ("0", "1", "2"):
         monkeypatch.setenv("LBM_PAIR", pair)
         for steps in (7, 8):
             res[(pair, steps)] = gpu_run(Case(q, shape, 0.6, faces, steps=steps, storage=storage, init_seed=55,
-                                              solid=solid))
+                                              solid=solid, s=sfrac))
     for pair in ("1", "2"):
         for steps in (7, 8):
             a, b = res[("0", steps)], res[(pair, steps)]
