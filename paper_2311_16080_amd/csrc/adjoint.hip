@@ -120,7 +120,11 @@ __device__ __forceinline__ void zouhe_transpose(CT *a, const Params<CT> &p, int 
 }
 
 // Adjoint step at time t for one fluid cell.  F: natural state f(t) (storage
-// type ST); An: a(t+1) (CT planes); Ao: a(t).  ds: per-cell dL/ds accumulator
+// type ST, the forward path's tiled layout); An: a(t+1); Ao: a(t).  The
+// adjoint populations are compute-type planes, a_i(x) at i * plane + x: the
+// gather over 19 or 27 neighbours then needs one address per cell plus
+// per-direction constants, where the tiled index would hold a 64-bit address
+// per direction and spill at the register budget the step runs at.  ds: per-cell dL/ds accumulator
 // (HAS_S).  FRC: the body force is on; dF (or null): per-cell dL/dF
 // accumulators, 3 planes of N (internal axes).  Returns
 // sum_i lambda_i (f_i - feq_i), the cell's dL/dtau * tau^2.
@@ -149,7 +153,7 @@ __device__ __forceinline__ typename Store<ST>::CT adjoint_cell(const Params<type
     const uint32_t e = edge_bits(p, X, Y, Z);
     const uint32_t irr = irregular_mask<L>(e, nbm);
     CT h[Q];
-    unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(F, P, cell); });
+    unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(F, cell); });
     const int zf = zh_face_of(p, e);
     if (zf >= 0 && pending) zouhe<L>(h, p, zf);
     CT drho = 0, jx = 0, jy = 0, jz = 0;
@@ -398,6 +402,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_adj_walls(const Params<CT> p1, co
         const int X = (ax == 0) ? fixed : i;
         const int Y = (ax == 0) ? i : ((ax == 1) ? fixed : j);
         const int Z = (ax == 2) ? fixed : j;
+        const int64_t P = p.plane;
         const int64_t cell = ((int64_t)X * p.nY + Y) * p.nZ + Z;
         uint32_t nbm = 0;
         bool solid = false;
@@ -412,7 +417,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_adj_walls(const Params<CT> p1, co
                 if ((irr >> K) & 1u) {
                     const Nb ns = classify_src<L>(p, X, Y, Z, K, nbm);
                     if (ns.kind == NB_WALL && ns.face == f) {
-                        const double v = (double)A[(int64_t)K * p.plane + cell] * 6.0 * weight<L>(K) * (double)p.rho0;
+                        const double v = (double)A[(int64_t)K * P + cell] * 6.0 * weight<L>(K) * (double)p.rho0;
                         g0 += v * L::c[K][0];
                         g1 += v * L::c[K][1];
                         g2 += v * L::c[K][2];
@@ -451,15 +456,15 @@ __device__ __forceinline__ void seed_cell(const Params<typename Store<ST>::CT> &
                                           int64_t gcell, int64_t N) {
     using CT = typename Store<ST>::CT;
     constexpr int Q = L::Q;
-    const int64_t cell = ((int64_t)X * p.nY + Y) * p.nZ + Z;
     const int64_t P = p.plane;
+    const int64_t cell = ((int64_t)X * p.nY + Y) * p.nZ + Z;
     if (p.flags && (p.flags[cell] & 1)) {
         unroll<Q>([&](auto I) { Ao[(int64_t)I * P + cell] = (CT)0; });
         return;
     }
     const uint32_t e = edge_bits(p, X, Y, Z);
     CT h[Q];
-    unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(F, P, cell); });
+    unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(F, cell); });
     const int zf = zh_face_of(p, e);
     if (zf >= 0 && pending) zouhe<L>(h, p, zf);
     CT drho = 0, jx = 0, jy = 0, jz = 0;
@@ -511,7 +516,6 @@ __device__ __forceinline__ void materialize_cell(const Params<typename Store<ST>
                                                  ST *__restrict__ D, int X, int Y, int Z) {
     constexpr int Q = L::Q;
     const int64_t cell = ((int64_t)X * p.nY + Y) * p.nZ + Z;
-    const int64_t P = p.plane;
     uint32_t nbm = 0;
     if (p.flags) {
         const uint8_t fl = p.flags[cell];
@@ -525,12 +529,12 @@ __device__ __forceinline__ void materialize_cell(const Params<typename Store<ST>
         ST v;
         if (!((irr >> I) & 1u)) {
             const int64_t src = cell - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
-            v = A[(int64_t)O * P + src];
+            v = A[pidx<Q>(O, src)];
         } else {
             const Nb nb = classify_src<L>(p, X, Y, Z, I, nbm);
-            v = (nb.kind == NB_FLUID) ? A[(int64_t)O * P + nb.cell] : A[(int64_t)I * P + cell];
+            v = (nb.kind == NB_FLUID) ? A[pidx<Q>(O, nb.cell)] : A[pidx<Q>(I, cell)];
         }
-        D[(int64_t)I * P + cell] = v;  // opposite slots share the storage scale
+        D[pidx<Q>(I, cell)] = v;  // opposite slots share the storage scale
     });
 }
 

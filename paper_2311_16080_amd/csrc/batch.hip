@@ -74,7 +74,7 @@ static void domain_params(Params<CT> &p, const lbm_ctx *c, const Domain &D, cons
     p.sX = D.nY * D.nZ;
     p.sY = D.nZ;
     p.zblocks = 1;
-    p.plane = (D.N + 63) / 64 * 64;
+    p.plane = tiled_cells(D.N);
     p.omega = (CT)(1.0 / D.tau);
     p.rho0 = (CT)c->opt.rho0;
     for (int f = 0; f < 6; ++f) {
@@ -149,6 +149,18 @@ static int upload_tiles(lbm_ctx *c, int B) {
     S->coop_grid = per_cu * cus;
     if (S->coop_grid > S->ntiles) S->coop_grid = S->ntiles;
     return LBM_OK;
+}
+
+// Each domain's state: Q sub-planes of its cells rounded up to whole tiles of
+// the population layout (core.hpp, pidx), domains back to back.
+void lbm::batch_layout(lbm_ctx *c) {
+    BatchState *S = c->bs;
+    int64_t so = 0;
+    for (int d = 0; d < c->ndomains; ++d) {
+        S->stoff[d] = so;
+        so += (int64_t)c->Q * tiled_cells(c->dom[d].N);
+    }
+    c->plane = so / c->Q;  // Q * plane = total state elements
 }
 
 int lbm::batch_upload(lbm_ctx *c) {
@@ -419,7 +431,7 @@ extern "C" lbm_ctx *lbm_create_batch(int lattice, int n, const int *nx, const in
     BatchState *S = c->bs;
     S->stoff.resize(n);
     S->cell0.resize(n);
-    int64_t so = 0, c0 = 0;
+    int64_t c0 = 0;
     std::string key = "L" + std::to_string(lattice) + "n" + std::to_string(n);
     uint64_t hsh = 1469598103934665603ull;
     for (int d = 0; d < n; ++d) {
@@ -440,14 +452,12 @@ extern "C" lbm_ctx *lbm_create_batch(int lattice, int n, const int *nx, const in
         D.tau = tau[d];
         D.cell0 = c0;
         map_domain_faces(D, c->D, bcs ? &bcs[d] : nullptr);
-        S->stoff[d] = so;
         S->cell0[d] = c0;
-        so += (int64_t)c->Q * ((D.N + 63) / 64 * 64);
         c0 += D.N;
         for (int64_t v : {(int64_t)D.nx, (int64_t)D.ny, (int64_t)D.nz}) hsh = (hsh ^ (uint64_t)v) * 1099511628211ull;
     }
     c->N = c0;
-    c->plane = so / c->Q;  // Q * plane = total state elements
+    batch_layout(c);
     c->nx = c->ny = c->nz = 0;
     S->B = 128;
     build_tiles(c, 64);    // partial-sum rows sized for the smallest tile

@@ -81,7 +81,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_init_batch(const BatchDev b, ST *
     }
     const CT usq15 = (CT)1.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     ST *Ad = A + b.stoff[d];
-    unroll<L::Q>([&](auto I) { sth<L, ST, I>(Ad, p.plane, c, heq<L, I>(rho - p.rho0, rho, u[0], u[1], u[2], usq15)); });
+    unroll<L::Q>([&](auto I) { sth<L, ST, I>(Ad, c, heq<L, I>(rho - p.rho0, rho, u[0], u[1], u[2], usq15)); });
 }
 
 template <class L, class ST, class OT, bool ODD>

@@ -255,11 +255,9 @@ static void setup_shape(lbm_ctx *c, int lattice, int nx, int ny, int nz, double 
         c->nZ = ny;
     }
     c->N = (int64_t)c->nX * c->nY * c->nZ;
-    // plane stride: rounded to 1024 elements plus one extra 1024-element pad, so
-    // the Q planes of a large power-of-two grid do not sit at power-of-two
-    // distances from each other (measured: otherwise fewer HBM channels serve
-    // the Q concurrent streams of each lane)
-    c->plane = (c->N + 1023) / 1024 * 1024 + 1024;
+    // values per direction: the cells rounded up to whole tiles of the
+    // population layout (core.hpp, pidx)
+    c->plane = tiled_cells(c->N);
     c->tau = tau;
     // threads per block along Z: LBM_BLOCK if set, else the size among 256 /
     // 128 / 192 that launches the fewest lanes per row (ties: in that order;

@@ -130,6 +130,7 @@ void tape_invalidate(lbm_ctx *c);
 
 // batch.hip
 int batch_upload(lbm_ctx *c);
+void batch_layout(lbm_ctx *c);   // per-domain state offsets
 void batch_release(lbm_ctx *c);
 hipError_t batch_init(lbm_ctx *c, const void *rho, const void *u, bool f64);
 hipError_t batch_step(lbm_ctx *c);

@@ -102,7 +102,6 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
     if constexpr (FRC) load_body_force(p, cell, fx, fy, fz);   // issued with the population loads
     const uint32_t e = edge_bits(p, X, Y, Z);
     const uint32_t irr = irregular_mask<L>(e, nbm);
-    const int64_t P = p.plane;
 
     // Wavefronts of interior cells only (no face, no solid neighbour): plain
     // loads and stores, no per-direction boundary tests.
@@ -112,10 +111,10 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
             unroll<Q>([&](auto I) {
                 constexpr int O = opp<L>(I);
                 const int64_t src = cell - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
-                h[I] = ldh<L, ST, O, (L::c[I][2] == 0) ? NTA : NTZL>(A, P, src);
+                h[I] = ldh<L, ST, O, (L::c[I][2] == 0) ? NTA : NTZL>(A, src);
             });
         } else {
-            unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I, NTA>(A, P, cell); });
+            unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I, NTA>(A, cell); });
         }
         CT hp[Q];
         CT rho, ux, uy, uz;
@@ -126,10 +125,10 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
         unroll<Q>([&](auto I) {
             constexpr int O = opp<L>(I);
             if constexpr (MODE == 0) {
-                sth<L, ST, O, NTA>(W, P, cell, hp[I]);
+                sth<L, ST, O, NTA>(W, cell, hp[I]);
             } else {
                 const int64_t dst = cell + ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
-                sth<L, ST, I, (L::c[I][2] == 0) ? NTA : NTZS>(W, P, dst, hp[I]);
+                sth<L, ST, I, (L::c[I][2] == 0) ? NTA : NTZS>(W, dst, hp[I]);
             }
         });
         return;
@@ -153,12 +152,12 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
                 constexpr int O = opp<L>(I);
                 // x - c_i is across a wall or solid
                 const bool wall = ((we & src_face_bits<L>(I)) | (nbm & (1u << I))) != 0;
-                const ST *nb = pop_ptr<L, O>(A, P, cell + src_off<L, I>(p, zw));
-                const ST *ptr = wall ? pop_ptr<L, I>(A, P, cell) : nb;
+                const ST *nb = pop_ptr<L, O>(A, cell + src_off<L, I>(p, zw));
+                const ST *ptr = wall ? pop_ptr<L, I>(A, cell) : nb;
                 h[I] = ldp<L, ST, O, (L::c[I][2] == 0) ? NTA : NTZL>(ptr);  // w_O = w_I
             });
         } else {
-            unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I, NTA>(A, P, cell); });
+            unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I, NTA>(A, cell); });
         }
         CT hp[Q];
         CT rho, ux, uy, uz;
@@ -172,10 +171,10 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
             constexpr bool NTW = (MODE == 0 || L::c[I][2] == 0) ? NTA : NTZS;
             const uint32_t cr = we & fb;
             const bool wall = (cr | (nbm & (1u << O))) != 0;  // x + c_i is across a wall or solid
-            ST *own = pop_ptr<L, O>(W, P, cell);
+            ST *own = pop_ptr<L, O>(W, cell);
             ST *ptr = own;
             if constexpr (MODE != 0)
-                ptr = wall ? own : pop_ptr<L, I>(W, P, cell + src_off<L, O>(p, zw));  // x + c_i = x - c_opp(i)
+                ptr = wall ? own : pop_ptr<L, I>(W, cell + src_off<L, O>(p, zw));  // x + c_i = x - c_opp(i)
             CT v = hp[I];
             if (cr && !(cr & p.staticmask)) {
                 // moving wall: the lowest-index face crossed (static walls win);
@@ -204,15 +203,15 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
             constexpr int O = opp<L>(I);
             const ST *ptr;
             if (!((irr >> I) & 1u)) {
-                ptr = pop_ptr<L, O>(A, P, cell - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]));
+                ptr = pop_ptr<L, O>(A, cell - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]));
             } else {
                 const Nb nb = classify_src<L>(p, X, Y, Z, I, nbm);
-                ptr = (nb.kind == NB_FLUID) ? pop_ptr<L, O>(A, P, nb.cell) : pop_ptr<L, I>(A, P, cell);
+                ptr = (nb.kind == NB_FLUID) ? pop_ptr<L, O>(A, nb.cell) : pop_ptr<L, I>(A, cell);
             }
             h[I] = ldp<L, ST, O, (L::c[I][2] == 0) ? NTA : NTZL>(ptr);  // w_O = w_I
         });
     } else {
-        unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I, NTA>(A, P, cell); });
+        unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I, NTA>(A, cell); });
     }
 
     const int zf = zh_face_of(p, e);
@@ -232,15 +231,15 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
         ST *ptr;
         CT v = hp[I];
         if (!((irr >> O) & 1u)) {
-            if constexpr (MODE == 0) ptr = pop_ptr<L, O>(W, P, cell);
-            else ptr = pop_ptr<L, I>(W, P, cell + ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]));
+            if constexpr (MODE == 0) ptr = pop_ptr<L, O>(W, cell);
+            else ptr = pop_ptr<L, I>(W, cell + ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]));
         } else {
             const Nb nb = classify_src<L>(p, X, Y, Z, O, nbm);   // the cell x + c_i
             if (nb.kind == NB_FLUID) {
-                if constexpr (MODE == 0) ptr = pop_ptr<L, O>(W, P, cell);
-                else ptr = pop_ptr<L, I>(W, P, nb.cell);
+                if constexpr (MODE == 0) ptr = pop_ptr<L, O>(W, cell);
+                else ptr = pop_ptr<L, I>(W, nb.cell);
             } else {
-                ptr = pop_ptr<L, O>(W, P, cell);
+                ptr = pop_ptr<L, O>(W, cell);
                 v = fill_value<L, I>(p, nb, hp[I], perim, rho, ux, uy, uz);
             }
         }
@@ -289,7 +288,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_init(const Params<typename Store<
     const CT drho = rho - p.rho0;
     unroll<L::Q>([&](auto I) {
         CT v = solid ? (CT)0 : heq<L, I>(drho, rho, u[0], u[1], u[2], usq15);
-        sth<L, ST, I>(A, p.plane, cell, v);
+        sth<L, ST, I>(A, cell, v);
     });
 }
 
@@ -321,14 +320,14 @@ __device__ __forceinline__ bool moments_cell(const Params<typename Store<ST>::CT
             constexpr int O = opp<L>(I);
             if (!((irr >> I) & 1u)) {
                 const int64_t src = cell - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
-                h[I] = ldh<L, ST, O>(A, p.plane, src);
+                h[I] = ldh<L, ST, O>(A, src);
             } else {
                 const Nb nb = classify_src<L>(p, X, Y, Z, I, nbm);
-                h[I] = (nb.kind == NB_FLUID) ? ldh<L, ST, O>(A, p.plane, nb.cell) : ldh<L, ST, I>(A, p.plane, cell);
+                h[I] = (nb.kind == NB_FLUID) ? ldh<L, ST, O>(A, nb.cell) : ldh<L, ST, I>(A, cell);
             }
         });
     } else {
-        unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(A, p.plane, cell); });
+        unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(A, cell); });
     }
     const int zf = zh_face_of(p, e);
     if (zf >= 0 && (ODD || pending)) zouhe<L>(h, p, zf);
@@ -636,7 +635,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_forces(const Params<typename Stor
                     const bool wall = cr != 0;
                     if (wall || ((nbm >> O) & 1u)) {
                         links = true;
-                        const double back = (double)ldh<L, ST, O>(A, p.plane, cell) + weight<L>(O) * (double)p.rho0;
+                        const double back = (double)ldh<L, ST, O>(A, cell) + weight<L>(O) * (double)p.rho0;
                         double term = 0.0;
                         int base = 0;
                         if (wall) {
@@ -730,8 +729,7 @@ __global__ void __launch_bounds__(256) k_bouzidi(const Params<typename Store<ST>
             w = (CT)weight<L>(I);
         }
     });
-    const int64_t P = p.plane;
-    auto ld = [&](int d, int64_t cell) -> CT { return Store<ST>::ld(A + (int64_t)d * P + cell); };
+    auto ld = [&](int d, int64_t cell) -> CT { return Store<ST>::ld(A + pidx<L::Q>(d, cell)); };
     const CT q = lt.q[k];
     const CT a = ld(o, xb);
     CT r;
@@ -754,7 +752,7 @@ __global__ void __launch_bounds__(256) k_bouzidi(const Params<typename Store<ST>
             r = a / (q * ((CT)2 * q + (CT)1)) + ((CT)2 * q - (CT)1) / q * d + ((CT)1 - (CT)2 * q) / ((CT)1 + (CT)2 * q) * e;
         }
     }
-    Store<ST>::st(A + (int64_t)o * P + xb, r);
+    Store<ST>::st(A + pidx<L::Q>(o, xb), r);
     lt.dlt[k] = Store<ST>::scaled ? (a - r) * w : (a - r);
 }
 

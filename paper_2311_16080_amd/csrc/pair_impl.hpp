@@ -95,7 +95,6 @@ __device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict
     constexpr int Q = L::Q;
     constexpr uint32_t kFaces = all_face_bits<L>();
     constexpr uint32_t kXY = 0xFu;  // faces of the X and Y axes
-    const int64_t P = p.plane;
     const int64_t row = ((int64_t)X * p.nY + Y) * p.nZ;
     const int64_t cell0 = row + z0;
     bool plain = true;
@@ -121,28 +120,28 @@ __device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict
         constexpr int O = opp<L>(I);
         constexpr int cz = L::c[I][2];
         if constexpr (MODE == 0) {
-            u[I] = ld32<true>(W + (((int64_t)I * P + cell0) >> 1));
+            u[I] = ld32<true>(W + (pidx<Q>(I, cell0) >> 1));
         } else {
             // Addresses are selected, not branched on, so the loads of all
             // directions stay in flight together.  A source row across an X / Y
             // wall means both cells bounce back (own slot I).
             const bool wxy = (exy & src_face_bits<L>(I)) != 0;
             const int64_t rs = row - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY);
-            const int64_t own = (int64_t)I * P + cell0;
-            const int64_t src = (int64_t)O * P + rs + z0;
+            const int64_t own = pidx<Q>(I, cell0);
+            const int64_t src = pidx<Q>(O, rs + z0);
             const uint32_t a = ld32<cz == 0>(W + ((wxy ? own : src) >> 1));
             if constexpr (cz == 1) {
                 // cell z0 needs element z0 - 1: the previous lane's high half; lane 0
                 // loads it (previous wavefront, or own slot I at the z = 0 wall), the
                 // other lanes reload an element of their own pair
-                const int64_t ea = (lane != 0 || wxy) ? own : (z0 == 0 ? own : src - 1);
+                const int64_t ea = (lane != 0 || wxy) ? own : (z0 == 0 ? own : pidx<Q>(O, rs + z0 - 1));
                 const uint32_t ex = (uint32_t)H[ea] << 16;
                 const uint32_t sh = __builtin_amdgcn_alignbit(a, wave_shr1(a, ex), 16);
                 u[I] = wxy ? a : sh;
             } else if constexpr (cz == -1) {
                 // cell z0 + 1 needs element z0 + 2: the next lane's low half; lane 63
                 // loads it (next wavefront, or own slot I at the z = nZ - 1 wall)
-                const int64_t ea = (lane != 63 || wxy) ? own : (z0 + 2 == p.nZ ? own + 1 : src + 2);
+                const int64_t ea = (lane != 63 || wxy) ? own : (z0 + 2 == p.nZ ? pidx<Q>(I, cell0 + 1) : pidx<Q>(O, rs + z0 + 2));
                 const uint32_t ex = (uint32_t)H[ea];
                 const uint32_t sh = __builtin_amdgcn_alignbit(wave_shl1(a, ex), a, 16);
                 u[I] = wxy ? a : sh;
@@ -183,37 +182,34 @@ __device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict
         constexpr uint32_t fb = src_face_bits<L>(O);  // faces x + c_i can lie across
         const uint32_t v = out[I];
         if constexpr (MODE == 0) {
-            st32<true>(W + (((int64_t)O * P + cell0) >> 1), v);
+            st32<true>(W + (pidx<Q>(O, cell0) >> 1), v);
         } else if (exy & fb) {
             // destination row across an X / Y wall: both values bounce into own slot O
-            st32<true>(W + (((int64_t)O * P + cell0) >> 1), v);
+            st32<true>(W + (pidx<Q>(O, cell0) >> 1), v);
         } else {
             const int64_t rd = row + ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY);
             if constexpr (cz == 0) {
-                st32<true>(W + (((int64_t)I * P + rd + z0) >> 1), v);
+                st32<true>(W + (pidx<Q>(I, rd + z0) >> 1), v);
             } else if constexpr (cz == 1) {
                 // values go to z0 + 1, z0 + 2: the pair (z0, z0 + 1) takes the previous
                 // lane's second value and this lane's first
                 const uint32_t pv = __builtin_amdgcn_alignbit(v, wave_shr1(v, 0u), 16);
-                if (lane != 0) st32<false>(W + (((int64_t)I * P + rd + z0) >> 1), pv);
+                if (lane != 0) st32<false>(W + (pidx<Q>(I, rd + z0) >> 1), pv);
                 if (lane == 0 || lane == 63) {
                     // lane 0: its first value; lane 63: its second value, into the next
                     // wavefront's first element, or bounced off the z = nZ - 1 wall
-                    const int64_t at = lane == 0 ? (int64_t)I * P + rd + z0 + 1
-                                                 : (z0 + 2 == p.nZ ? (int64_t)O * P + cell0 + 1
-                                                                   : (int64_t)I * P + rd + z0 + 2);
+                    const int64_t at = lane == 0 ? pidx<Q>(I, rd + z0 + 1) : (z0 + 2 == p.nZ ? pidx<Q>(O, cell0 + 1) : pidx<Q>(I, rd + z0 + 2));
                     H[at] = (uint16_t)(lane == 0 ? v : v >> 16);
                 }
             } else {
                 // values go to z0 - 1, z0: the pair (z0, z0 + 1) takes this lane's second
                 // value and the next lane's first
                 const uint32_t pv = __builtin_amdgcn_alignbit(wave_shl1(v, 0u), v, 16);
-                if (lane != 63) st32<false>(W + (((int64_t)I * P + rd + z0) >> 1), pv);
+                if (lane != 63) st32<false>(W + (pidx<Q>(I, rd + z0) >> 1), pv);
                 if (lane == 0 || lane == 63) {
                     // lane 63: its second value; lane 0: its first value, into the previous
                     // wavefront's last element, or bounced off the z = 0 wall
-                    const int64_t at = lane == 63 ? (int64_t)I * P + rd + z0
-                                                  : (z0 == 0 ? (int64_t)O * P + cell0 : (int64_t)I * P + rd + z0 - 1);
+                    const int64_t at = lane == 63 ? pidx<Q>(I, rd + z0) : (z0 == 0 ? pidx<Q>(O, cell0) : pidx<Q>(I, rd + z0 - 1));
                     H[at] = (uint16_t)(lane == 63 ? v >> 16 : v);
                 }
             }
