@@ -347,7 +347,8 @@ extern "C" int lbm_set_options(lbm_ctx *c, const lbm_options *o) {
     if (o->compute != LBM_F64 && o->compute != LBM_F32) return fail(LBM_EINVAL, "unknown compute type %d", o->compute);
     if ((o->storage == LBM_F64) != (o->compute == LBM_F64))
         return fail(LBM_EUNSUPPORTED, "F64 compute goes with F64 storage only; F32/F16/BF16 storage computes in F32");
-    if (o->pattern != LBM_INPLACE && o->pattern != LBM_DOUBLE) return fail(LBM_EINVAL, "unknown pattern %d", o->pattern);
+    if (o->pattern != LBM_INPLACE && o->pattern != LBM_DOUBLE && o->pattern != LBM_PULL)
+        return fail(LBM_EINVAL, "unknown pattern %d", o->pattern);
     if (!(o->rho0 > 0.0) || !std::isfinite(o->rho0)) return fail(LBM_EINVAL, "rho0 must be > 0");
     if (c->batch && o->pattern != LBM_INPLACE) return fail(LBM_EUNSUPPORTED, "batch contexts use the in-place pattern");
     // a force field set earlier is typed by the compute type
@@ -432,7 +433,7 @@ static int ensure_state(lbm_ctx *c) {
     const size_t bytes = (size_t)c->Q * (size_t)c->plane * storage_size(c->opt.storage);
     rc = dev_alloc(&c->A, bytes, "population state");
     if (rc) return rc;
-    if (c->opt.pattern == LBM_DOUBLE) {
+    if (c->opt.pattern != LBM_INPLACE) {
         rc = dev_alloc(&c->B, bytes, "second population buffer");
         if (rc) {
             dev_free(c->A);
@@ -798,16 +799,14 @@ hipError_t lbm::forward_step(lbm_ctx *c) {
     }
     c->pd.zh_pending = c->pf.zh_pending = c->t > 0 ? 1 : 0;
     Launch g = make_launch(c);
-    int mode;
-    if (c->opt.pattern == LBM_INPLACE) mode = (int)(c->t & 1);
-    else mode = 2;
+    const int mode = step_mode(c);
     hipError_t e = launch_step(g, mode, c->s != nullptr);
-    if (c->opt.pattern == LBM_DOUBLE) std::swap(c->A, c->B);
+    if (mode >= 2) std::swap(c->A, c->B);
     if (e == hipSuccess && c->nlinks) {
         // interpolated bounce-back on the curved links, on the state just written
         Launch b = make_launch(c);
         const void *lt = (c->opt.storage == LBM_F64) ? (const void *)&c->ltd : (const void *)&c->ltf;
-        e = launch_bouzidi(b, lt, mode != 0);
+        e = launch_bouzidi(b, lt, mode == 1 || mode == 2);
     }
     c->t += 1;
     return e;
@@ -850,7 +849,7 @@ extern "C" int lbm_moments(lbm_ctx *c, void *rho, void *u, int dtype, double *su
     if (rc) return rc;
     refresh_params(c);
     hipError_t e;
-    const bool odd = (c->opt.pattern == LBM_INPLACE) && (c->t & 1);
+    const bool odd = swapped_at(c, c->t);
     if (c->batch) e = batch_moments(c, odd, rho, u, dtype == LBM_F64, c->partial);
     else e = launch_moments(make_launch(c), odd, rho, u, dtype == LBM_F64, c->partial, c->N);
     if (e == hipSuccess) e = launch_reduce(c->partial, c->rbeg, c->rend, c->sums_dev, c->ndomains, c->stream);

@@ -119,6 +119,21 @@ void free_all(lbm_ctx *c);
 Launch make_launch(lbm_ctx *c);
 hipError_t forward_step(lbm_ctx *c);
 
+// Kernel mode of the step taken from time t: 0 / 1 the in-place even / odd
+// step, 2 the push step, 3 the pull step (LBM_PULL starts from a natural state
+// with the local even step).
+inline int step_mode_at(const lbm_ctx *c, int64_t t) {
+    if (c->opt.pattern == LBM_INPLACE) return (int)(t & 1);
+    if (c->opt.pattern == LBM_PULL) return t > 0 ? 3 : 0;
+    return 2;
+}
+inline int step_mode(const lbm_ctx *c) { return step_mode_at(c, c->t); }
+// The state at time t holds f*_i(x) in slot opp(i) of x (what the in-place
+// even step and the pull step leave) rather than the natural f_i(x) in slot i.
+inline bool swapped_at(const lbm_ctx *c, int64_t t) {
+    return (c->opt.pattern == LBM_INPLACE && (t & 1)) || (c->opt.pattern == LBM_PULL && t > 0);
+}
+
 // graph.hip
 void drop_graph(lbm_ctx *c);
 

@@ -111,13 +111,18 @@ extern "C" int lbm_graph_launch(lbm_ctx *c) {
         for (const lbm_face &F : D.iface)
             zh = zh || F.type == LBM_ZOUHE_VELOCITY || F.type == LBM_ZOUHE_PRESSURE || F.type == LBM_REG_VELOCITY ||
                  F.type == LBM_REG_PRESSURE;
-    if (!same_buffers || (c->opt.pattern == LBM_INPLACE && !same_parity) || (zh && ((c->t > 0) != (c->graph_t0 > 0))))
+    // the pull pattern's first step after an init is the local one
+    const bool first = (c->t > 0) != (c->graph_t0 > 0);
+    if (!same_buffers || (c->opt.pattern == LBM_INPLACE && !same_parity) || ((zh || c->opt.pattern == LBM_PULL) && first))
         return fail(LBM_ESTATE, "the state's step parity / buffers differ from those at capture");
     (void)hipSetDevice(c->device);
     hipError_t e = hipGraphLaunch(c->graph_exec, c->stream);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     c->t += c->graph_steps;
-    if (c->opt.pattern == LBM_DOUBLE && (c->graph_steps & 1)) std::swap(c->A, c->B);
+    // buffer swaps of the replayed steps (push and pull steps swap)
+    int swaps = 0;
+    for (int64_t k = 0; k < c->graph_steps; ++k) swaps += step_mode_at(c, c->graph_t0 + k) >= 2 ? 1 : 0;
+    if (swaps & 1) std::swap(c->A, c->B);
     c->moved_since_tape = true;
     refresh_params(c);
     return LBM_OK;

@@ -6,7 +6,8 @@
 //
 //   k_step      fused stream + collide + boundary fill, one pass per step
 //               (MODE 0: in-place even step, MODE 1: in-place odd step,
-//                MODE 2: double-buffer push step)
+//                MODE 2: double-buffer push step, MODE 3: double-buffer
+//                pull step)
 //   k_init      f = feq(rho, u) in the storage format          (eq. feq)
 //   k_moments   rho, u of the current state + FP64 block sums  (eqs. density, velocity)
 //   k_reduce    fixed-order reduction of the block sums
@@ -86,6 +87,13 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
     constexpr bool PZ = (XF & 4) != 0;
     constexpr bool KB = (XF & 8) != 0;   // KBC collision
     constexpr bool WALLS_ONLY = (XF & 16) != 0;   // every lattice face is a wall
+    // Reads gather from the neighbours (in-place odd step, pull step) or read
+    // the cell's own slots (even step, push step); writes go to the cell's own
+    // opposite slots (even step, pull step) or to the neighbours.  The pull
+    // step reads A and writes B: A holds what an in-place even step leaves
+    // (f*_i(x) in slot opp(i) of x), and so does B afterwards.
+    constexpr bool GATHER = (MODE == 1 || MODE == 3);
+    constexpr bool LOCAL_W = (MODE == 0 || MODE == 3);
     constexpr bool NTA = (NT >= 1);
     constexpr bool NTZL = (NT == 2) || (NT == 4);
     constexpr bool NTZS = (NT == 2) || (NT == 3);
@@ -107,7 +115,7 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
     // loads and stores, no per-direction boundary tests.
     if (__all(irr == 0)) {
         CT h[Q];
-        if constexpr (MODE == 1) {
+        if constexpr (GATHER) {
             unroll<Q>([&](auto I) {
                 constexpr int O = opp<L>(I);
                 const int64_t src = cell - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
@@ -121,10 +129,10 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
         CT s = 0;
         if constexpr (HAS_S) s = (CT)p.s[cell];
         collide<L, FRC, KB>(h, hp, p, s, HAS_S, rho, ux, uy, uz, fx, fy, fz);
-        ST *W = (MODE == 2) ? B : A;
+        ST *W = (MODE >= 2) ? B : A;
         unroll<Q>([&](auto I) {
             constexpr int O = opp<L>(I);
-            if constexpr (MODE == 0) {
+            if constexpr (LOCAL_W) {
                 sth<L, ST, O, NTA>(W, cell, hp[I]);
             } else {
                 const int64_t dst = cell + ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
@@ -147,7 +155,7 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
         // wall faces of this cell (without PZ, e's lattice faces are all walls here)
         const uint32_t we = PZ ? (e & p.wallmask) : e;
         CT h[Q];
-        if constexpr (MODE == 1) {
+        if constexpr (GATHER) {
             unroll<Q>([&](auto I) {
                 constexpr int O = opp<L>(I);
                 // x - c_i is across a wall or solid
@@ -164,16 +172,16 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
         CT s = 0;
         if constexpr (HAS_S) s = (CT)p.s[cell];
         collide<L, FRC, KB>(h, hp, p, s, HAS_S, rho, ux, uy, uz, fx, fy, fz);
-        ST *W = (MODE == 2) ? B : A;
+        ST *W = (MODE >= 2) ? B : A;
         unroll<Q>([&](auto I) {
             constexpr int O = opp<L>(I);
             constexpr uint32_t fb = src_face_bits<L>(O);     // faces x + c_i can lie across
-            constexpr bool NTW = (MODE == 0 || L::c[I][2] == 0) ? NTA : NTZS;
+            constexpr bool NTW = (LOCAL_W || L::c[I][2] == 0) ? NTA : NTZS;
             const uint32_t cr = we & fb;
             const bool wall = (cr | (nbm & (1u << O))) != 0;  // x + c_i is across a wall or solid
             ST *own = pop_ptr<L, O>(W, cell);
             ST *ptr = own;
-            if constexpr (MODE != 0)
+            if constexpr (!LOCAL_W)
                 ptr = wall ? own : pop_ptr<L, I>(W, cell + src_off<L, O>(p, zw));  // x + c_i = x - c_opp(i)
             CT v = hp[I];
             if (cr && !(cr & p.staticmask)) {
@@ -198,7 +206,7 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
     // for a boundary fill, the value) is chosen per lane, so wavefronts that
     // hold a few boundary cells do not run extra memory instructions.
     CT h[Q];
-    if constexpr (MODE == 1) {
+    if constexpr (GATHER) {
         unroll<Q>([&](auto I) {
             constexpr int O = opp<L>(I);
             const ST *ptr;
@@ -215,7 +223,7 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
     }
 
     const int zf = zh_face_of(p, e);
-    if (zf >= 0 && (MODE == 1 || pending)) zouhe<L>(h, p, zf);
+    if (zf >= 0 && (GATHER || pending)) zouhe<L>(h, p, zf);
 
     CT hp[Q];
     CT rho, ux, uy, uz;
@@ -224,19 +232,19 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
     collide<L, FRC, KB>(h, hp, p, s, HAS_S, rho, ux, uy, uz, fx, fy, fz);
     const bool perim = (e & p.wallmask) != 0;
 
-    ST *W = (MODE == 2) ? B : A;
+    ST *W = (MODE >= 2) ? B : A;
     unroll<Q>([&](auto I) {
         constexpr int O = opp<L>(I);
-        constexpr bool NTW = (MODE == 0 || L::c[I][2] == 0) ? NTA : NTZS;
+        constexpr bool NTW = (LOCAL_W || L::c[I][2] == 0) ? NTA : NTZS;
         ST *ptr;
         CT v = hp[I];
         if (!((irr >> O) & 1u)) {
-            if constexpr (MODE == 0) ptr = pop_ptr<L, O>(W, cell);
+            if constexpr (LOCAL_W) ptr = pop_ptr<L, O>(W, cell);
             else ptr = pop_ptr<L, I>(W, cell + ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]));
         } else {
             const Nb nb = classify_src<L>(p, X, Y, Z, O, nbm);   // the cell x + c_i
             if (nb.kind == NB_FLUID) {
-                if constexpr (MODE == 0) ptr = pop_ptr<L, O>(W, cell);
+                if constexpr (LOCAL_W) ptr = pop_ptr<L, O>(W, cell);
                 else ptr = pop_ptr<L, I>(W, nb.cell);
             } else {
                 ptr = pop_ptr<L, O>(W, cell);
@@ -455,25 +463,23 @@ hipError_t step_t(const Launch &g, int mode, bool has_s) {
         // two cells per lane (walls and, in the even step, periodic faces on its
         // own path); not with a body force or the KBC collision.  pair 1: even
         // steps; 2: even and odd steps (measurement).
-        if (!g.force && !g.kbc && g.pair && mode != 2) {
-            // no solid cells and walls on every lattice face: the even-step variant
-            // without the per-cell fallback (99 vs 109 VGPRs for D3Q19; 2% faster)
+        if (!g.force && !g.kbc && g.pair && mode < 2 && (mode == 0 || g.pair == 2)) {
+            // no solid cells and walls on every lattice face: the variant without
+            // the per-cell fallback (D3Q19 even step 99 vs 109 VGPRs; 2% faster)
             const bool walls = !p.flags && (p.wallmask & all_face_bits<L>()) == all_face_bits<L>();
-            if (mode == 0 && walls) {
-                if (has_s) hipLaunchKernelGGL((k_step_pair<L, ST, 0, true, true>), dim3(g.pgrid), dim3(g.pblock), 0, g.stream, p, A);
-                else hipLaunchKernelGGL((k_step_pair<L, ST, 0, false, true>), dim3(g.pgrid), dim3(g.pblock), 0, g.stream, p, A);
-                return hipGetLastError();
-            }
-            if (mode == 0 || g.pair == 2) {
-#define LBM_PAIR_CASE(M, S) \
-    if (mode == M && has_s == S) hipLaunchKernelGGL((k_step_pair<L, ST, M, S>), dim3(g.pgrid), dim3(g.pblock), 0, g.stream, p, A);
-                LBM_PAIR_CASE(0, false)
-                LBM_PAIR_CASE(1, false)
-                LBM_PAIR_CASE(0, true)
-                LBM_PAIR_CASE(1, true)
+#define LBM_PAIR_CASE(M, S, NF)                                                                                     \
+    if (mode == M && has_s == S && walls == NF)                                                                     \
+        hipLaunchKernelGGL((k_step_pair<L, ST, M, S, NF>), dim3(g.pgrid), dim3(g.pblock), 0, g.stream, p, A);
+            LBM_PAIR_CASE(0, false, false)
+            LBM_PAIR_CASE(1, false, false)
+            LBM_PAIR_CASE(0, true, false)
+            LBM_PAIR_CASE(1, true, false)
+            LBM_PAIR_CASE(0, false, true)
+            LBM_PAIR_CASE(1, false, true)
+            LBM_PAIR_CASE(0, true, true)
+            LBM_PAIR_CASE(1, true, true)
 #undef LBM_PAIR_CASE
-                return hipGetLastError();
-            }
+            return hipGetLastError();
         }
     }
     // walls on every lattice face, nothing else: the variant without the general
@@ -488,8 +494,10 @@ hipError_t step_t(const Launch &g, int mode, bool has_s) {
                 hipLaunchKernelGGL((k_step<L, ST, 0, 16, NTD0>), dim3(g.grid), dim3(g.block), 0, g.stream, p, A, B);
             else if (mode == 1)
                 hipLaunchKernelGGL((k_step<L, ST, 1, 16, NTD0>), dim3(g.grid), dim3(g.block), 0, g.stream, p, A, B);
-            else
+            else if (mode == 2)
                 hipLaunchKernelGGL((k_step<L, ST, 2, 16, NTD0>), dim3(g.grid), dim3(g.block), 0, g.stream, p, A, B);
+            else
+                hipLaunchKernelGGL((k_step<L, ST, 3, 16, NTD0>), dim3(g.grid), dim3(g.block), 0, g.stream, p, A, B);
             return hipGetLastError();
         }
     }
@@ -525,6 +533,12 @@ hipError_t step_t(const Launch &g, int mode, bool has_s) {
         LBM_XF_CASE(2, 5)
         LBM_XF_CASE(2, 6)
         LBM_XF_CASE(2, 7)
+        LBM_XF_CASE(3, 2)
+        LBM_XF_CASE(3, 3)
+        LBM_XF_CASE(3, 4)
+        LBM_XF_CASE(3, 5)
+        LBM_XF_CASE(3, 6)
+        LBM_XF_CASE(3, 7)
         if constexpr (L::Q != 19) {
             LBM_XF_CASE(0, 8)
             LBM_XF_CASE(0, 10)
@@ -538,6 +552,10 @@ hipError_t step_t(const Launch &g, int mode, bool has_s) {
             LBM_XF_CASE(2, 10)
             LBM_XF_CASE(2, 12)
             LBM_XF_CASE(2, 14)
+            LBM_XF_CASE(3, 8)
+            LBM_XF_CASE(3, 10)
+            LBM_XF_CASE(3, 12)
+            LBM_XF_CASE(3, 14)
         }
 #undef LBM_XF_CASE
         return hipErrorInvalidValue;
@@ -560,6 +578,17 @@ hipError_t step_t(const Launch &g, int mode, bool has_s) {
     LBM_STEP_CASE(1, true)
     LBM_STEP_CASE(2, true)
 #undef LBM_STEP_CASE
+    // pull step: the default memory hints, or plain accesses (LBM_NT=0)
+    if (mode == 3) {
+        if (g.nt == 0) {
+            if (has_s) hipLaunchKernelGGL((k_step<L, ST, 3, 1, 0>), dim3(g.grid), dim3(g.block), 0, g.stream, p, A, B);
+            else hipLaunchKernelGGL((k_step<L, ST, 3, 0, 0>), dim3(g.grid), dim3(g.block), 0, g.stream, p, A, B);
+        } else {
+            if (has_s) hipLaunchKernelGGL((k_step<L, ST, 3, 1, 1>), dim3(g.grid), dim3(g.block), 0, g.stream, p, A, B);
+            else hipLaunchKernelGGL((k_step<L, ST, 3, 0, 1>), dim3(g.grid), dim3(g.block), 0, g.stream, p, A, B);
+        }
+        return hipGetLastError();
+    }
     return hipErrorInvalidValue;
 }
 

@@ -4,13 +4,13 @@
 // With one cell per lane a 2-byte population moves 128 B per wavefront
 // instruction, and the kernel runs out of memory instructions long before it
 // runs out of bandwidth.  Here lane t of a Z row owns the cell pair
-// (z0, z0 + 1) = (2t, 2t + 1): every population plane is read and written as
-// aligned 32-bit pairs.  Z-shifted planes (the odd step) are realigned across
-// lanes with wavefront-wide DPP shifts; the one element that crosses into the
-// neighbouring wavefront, or into a Z wall, goes through a single-lane 2-byte
-// access.  Rows of nZ % 128 == 0 cells only, so no wavefront straddles two
-// rows: lane 0 of a row's first wavefront holds z = 0, lane 63 of its last
-// wavefront holds z = nZ - 1.
+// (z0, z0 + 1) = (2t, 2t + 1): every population plane of the local even step
+// is read and written as aligned 32-bit pairs.  In the odd step the Z-shifted
+// planes are read and written as 32-bit pairs at 2-byte-aligned addresses; a
+// pair that would leave the row (Z wall) or straddle a 4096-cell tile goes
+// through 16-bit accesses.  Rows of nZ % 128 == 0 cells only, so no wavefront
+// straddles two rows: lane 0 of a row's first wavefront holds z = 0, lane 63
+// of its last wavefront holds z = nZ - 1.
 //
 // Wavefronts whose cells meet only wall faces take this path; anything else
 // (solid cells, periodic / open faces) runs step_cell once per cell of the
@@ -18,13 +18,15 @@
 // to storage), so both paths give bitwise-equal states.
 //
 // Measured on the D3Q19 FP16 256^3 cavity: the even (local) step drops from
-// 305 to 224 us (222 us for the variant without the per-cell fallback that
-// walls-only domains without solids use).  Two cells per lane measured slower
-// than one for the odd step, both with wavefront shifts (~134 VGPRs, 400-590
-// us) and with the Z-shifted planes staged through LDS behind block barriers
-// (~400 us at 3 or 4 waves per SIMD), against 277 us with one cell per lane,
-// so by default only even steps use this kernel (LBM_PAIR=2 selects it for
-// odd steps too, for measurement).
+// 305 to 224 us (202 us for the variant without the per-cell fallback that
+// walls-only domains without solids use).  For the odd step two cells per lane
+// measured slower than one: 330 us with the 2-byte-aligned 32-bit accesses
+// (a plain copy at a 2-byte offset runs 8% below an aligned one, and the
+// odd-step pattern with 10 of 19 planes at that offset 28% below), 400-590 us
+// with wavefront-wide DPP shifts (~134 VGPRs), ~400 us with the Z-shifted planes
+// staged through LDS behind block barriers, against 290 us with one cell per
+// lane; so by default only even steps use this kernel (LBM_PAIR=2 selects it
+// for odd steps too, for measurement).
 #pragma once
 
 namespace lbm {
@@ -63,13 +65,26 @@ __device__ __forceinline__ void st32(uint32_t *p, uint32_t v) {
     else *p = v;
 }
 
-// wavefront-wide shifts: lane t receives lane t - 1 (shr) / t + 1 (shl); the
-// lane without a source receives `edge`
-__device__ __forceinline__ uint32_t wave_shr1(uint32_t v, uint32_t edge) {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x138, 0xf, 0xf, false);
+// 32-bit access at a 2-byte-aligned address: gfx9 runs global memory in
+// unaligned mode, and the compiler emits one dword access for it
+typedef uint32_t u32_a2 __attribute__((aligned(2)));
+__device__ __forceinline__ uint32_t ld32u(const uint16_t *p) { return *reinterpret_cast<const u32_a2 *>(p); }
+__device__ __forceinline__ void st32u(uint16_t *p, uint32_t v) { *reinterpret_cast<u32_a2 *>(p) = v; }
+
+// The Z-shifted pair of source row rs that the pair (z0, z0 + 1) reads in the
+// odd step -- (z0 - 1, z0) for c_z = 1, (z0 + 1, z0 + 2) for c_z = -1 -- leaves
+// the row (Z wall) or straddles a tile boundary, so it is not one 32-bit access
+template <int CZ>
+__device__ __forceinline__ bool src_pair_edge(const Params<float> &p, int64_t rs, int z0) {
+    if constexpr (CZ == 1) return z0 == 0 || ((rs + z0) & (kTile - 1)) == 0;
+    else return z0 + 2 == p.nZ || ((rs + z0 + 2) & (kTile - 1)) == 0;
 }
-__device__ __forceinline__ uint32_t wave_shl1(uint32_t v, uint32_t edge) {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x130, 0xf, 0xf, false);
+// the same for the pair of destination row rd that the odd step writes:
+// (z0 + 1, z0 + 2) for c_z = 1, (z0 - 1, z0) for c_z = -1
+template <int CZ>
+__device__ __forceinline__ bool dst_pair_edge(const Params<float> &p, int64_t rd, int z0) {
+    if constexpr (CZ == 1) return z0 + 2 == p.nZ || ((rd + z0 + 2) & (kTile - 1)) == 0;
+    else return z0 == 0 || ((rd + z0) & (kTile - 1)) == 0;
 }
 
 // moving-wall term of the population bounced into slot O (= opp(I)) of a
@@ -110,7 +125,6 @@ __device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict
         step_cell<L, ST, MODE, XF, 1>(p, A, nullptr, X, Y, z0 + 1, pending);
         return;
     }
-    const int lane = (int)threadIdx.x & 63;
     uint32_t *W = reinterpret_cast<uint32_t *>(A);            // pairs: element index / 2
     uint16_t *H = reinterpret_cast<uint16_t *>(A);
     const uint32_t exy = e0 & kXY;                              // X / Y faces: the same for the whole row
@@ -124,32 +138,46 @@ __device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict
         } else {
             // Addresses are selected, not branched on, so the loads of all
             // directions stay in flight together.  A source row across an X / Y
-            // wall means both cells bounce back (own slot I).
+            // wall means both cells bounce back (own slot I).  Z-shifted planes are
+            // read as one 32-bit access at a 2-byte-aligned address (elements
+            // z0 - 1, z0 for c_z = 1; z0 + 1, z0 + 2 for c_z = -1); a pair that
+            // would cross the row's end (Z wall) or a tile boundary is read aligned
+            // here and completed below.
             const bool wxy = (exy & src_face_bits<L>(I)) != 0;
             const int64_t rs = row - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY);
             const int64_t own = pidx<Q>(I, cell0);
             const int64_t src = pidx<Q>(O, rs + z0);
-            const uint32_t a = ld32<cz == 0>(W + ((wxy ? own : src) >> 1));
-            if constexpr (cz == 1) {
-                // cell z0 needs element z0 - 1: the previous lane's high half; lane 0
-                // loads it (previous wavefront, or own slot I at the z = 0 wall), the
-                // other lanes reload an element of their own pair
-                const int64_t ea = (lane != 0 || wxy) ? own : (z0 == 0 ? own : pidx<Q>(O, rs + z0 - 1));
-                const uint32_t ex = (uint32_t)H[ea] << 16;
-                const uint32_t sh = __builtin_amdgcn_alignbit(a, wave_shr1(a, ex), 16);
-                u[I] = wxy ? a : sh;
-            } else if constexpr (cz == -1) {
-                // cell z0 + 1 needs element z0 + 2: the next lane's low half; lane 63
-                // loads it (next wavefront, or own slot I at the z = nZ - 1 wall)
-                const int64_t ea = (lane != 63 || wxy) ? own : (z0 + 2 == p.nZ ? pidx<Q>(I, cell0 + 1) : pidx<Q>(O, rs + z0 + 2));
-                const uint32_t ex = (uint32_t)H[ea];
-                const uint32_t sh = __builtin_amdgcn_alignbit(wave_shl1(a, ex), a, 16);
-                u[I] = wxy ? a : sh;
+            if constexpr (cz == 0) {
+                u[I] = ld32<true>(W + ((wxy ? own : src) >> 1));
             } else {
-                u[I] = a;
+                const bool edge = src_pair_edge<cz>(p, rs, z0);
+                u[I] = ld32u(H + (wxy ? own : (edge ? src : src - cz)));
             }
         }
     });
+    if constexpr (MODE != 0) {
+        unroll<Q>([&](auto I) {
+            constexpr int O = opp<L>(I);
+            constexpr int cz = L::c[I][2];
+            if constexpr (cz != 0) {
+                const bool wxy = (exy & src_face_bits<L>(I)) != 0;
+                const int64_t rs = row - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY);
+                if (!wxy && src_pair_edge<cz>(p, rs, z0)) {
+                    if constexpr (cz == 1) {
+                        // low half: element z0 - 1 (end of the previous tile), or own
+                        // slot I at the z = 0 wall
+                        const int64_t at = z0 == 0 ? pidx<Q>(I, cell0) : pidx<Q>(O, rs + z0 - 1);
+                        u[I] = (u[I] << 16) | (uint32_t)H[at];
+                    } else {
+                        // high half: element z0 + 2 (start of the next tile), or own
+                        // slot I of cell z0 + 1 at the z = nZ - 1 wall
+                        const int64_t at = z0 + 2 == p.nZ ? pidx<Q>(I, cell0 + 1) : pidx<Q>(O, rs + z0 + 2);
+                        u[I] = (u[I] >> 16) | ((uint32_t)H[at] << 16);
+                    }
+                }
+            }
+        });
+    }
     // ---- collide the two cells one after the other (step_cell's arithmetic) -------------
     // out[i] packs the value each cell writes for direction i: the post-collision
     // value, or, where x + c_i lies across a wall, the bounced value with the
@@ -188,30 +216,24 @@ __device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict
             st32<true>(W + (pidx<Q>(O, cell0) >> 1), v);
         } else {
             const int64_t rd = row + ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY);
+            const int64_t dst = pidx<Q>(I, rd + z0);
             if constexpr (cz == 0) {
-                st32<true>(W + (pidx<Q>(I, rd + z0) >> 1), v);
+                st32<true>(W + (dst >> 1), v);
+            } else if (!dst_pair_edge<cz>(p, rd, z0)) {
+                // one 32-bit store at a 2-byte-aligned address: elements z0 + 1, z0 + 2
+                // (c_z = 1) or z0 - 1, z0 (c_z = -1)
+                st32u(H + dst + cz, v);
             } else if constexpr (cz == 1) {
-                // values go to z0 + 1, z0 + 2: the pair (z0, z0 + 1) takes the previous
-                // lane's second value and this lane's first
-                const uint32_t pv = __builtin_amdgcn_alignbit(v, wave_shr1(v, 0u), 16);
-                if (lane != 0) st32<false>(W + (pidx<Q>(I, rd + z0) >> 1), pv);
-                if (lane == 0 || lane == 63) {
-                    // lane 0: its first value; lane 63: its second value, into the next
-                    // wavefront's first element, or bounced off the z = nZ - 1 wall
-                    const int64_t at = lane == 0 ? pidx<Q>(I, rd + z0 + 1) : (z0 + 2 == p.nZ ? pidx<Q>(O, cell0 + 1) : pidx<Q>(I, rd + z0 + 2));
-                    H[at] = (uint16_t)(lane == 0 ? v : v >> 16);
-                }
+                // cell z0's value to element z0 + 1; cell z0 + 1's to element z0 + 2
+                // (start of the next tile), or bounced into its own slot O off the
+                // z = nZ - 1 wall
+                H[dst + 1] = (uint16_t)v;
+                H[z0 + 2 == p.nZ ? pidx<Q>(O, cell0 + 1) : pidx<Q>(I, rd + z0 + 2)] = (uint16_t)(v >> 16);
             } else {
-                // values go to z0 - 1, z0: the pair (z0, z0 + 1) takes this lane's second
-                // value and the next lane's first
-                const uint32_t pv = __builtin_amdgcn_alignbit(wave_shl1(v, 0u), v, 16);
-                if (lane != 63) st32<false>(W + (pidx<Q>(I, rd + z0) >> 1), pv);
-                if (lane == 0 || lane == 63) {
-                    // lane 63: its second value; lane 0: its first value, into the previous
-                    // wavefront's last element, or bounced off the z = 0 wall
-                    const int64_t at = lane == 63 ? pidx<Q>(I, rd + z0) : (z0 == 0 ? pidx<Q>(O, cell0) : pidx<Q>(I, rd + z0 - 1));
-                    H[at] = (uint16_t)(lane == 63 ? v >> 16 : v);
-                }
+                // cell z0 + 1's value to element z0; cell z0's to element z0 - 1 (end of
+                // the previous tile), or bounced into its own slot O off the z = 0 wall
+                H[dst] = (uint16_t)(v >> 16);
+                H[z0 == 0 ? pidx<Q>(O, cell0) : pidx<Q>(I, rd + z0 - 1)] = (uint16_t)v;
             }
         }
     });

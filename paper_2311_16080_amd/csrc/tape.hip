@@ -235,7 +235,7 @@ struct Backward {
     // a natural-order view of a state image taken at time t: the image itself
     // when it is in natural order, else materialized into dst
     hipError_t natural(const void *img, int64_t t, void *dst, const void **out) {
-        if (c->opt.pattern == LBM_INPLACE && (t & 1)) {
+        if (swapped_at(c, t)) {
             AdjLaunch g = launch(ADJ_MATERIALIZE, t);
             g.F = img;
             g.D = dst;

@@ -22,11 +22,11 @@ D2Q9, D3Q19, D3Q27 = 0, 1, 2
 PERIODIC, WALL, ZOUHE_VELOCITY, ZOUHE_PRESSURE, EQ_OUTFLOW, REG_VELOCITY, REG_PRESSURE = 0, 1, 2, 3, 4, 5, 6
 BGK, KBC = 0, 1
 F64, F32, F16, BF16 = 0, 1, 2, 3
-INPLACE, DOUBLE = 0, 1
+INPLACE, DOUBLE, PULL = 0, 1, 2
 
 LATTICES = {"D2Q9": D2Q9, "D3Q19": D3Q19, "D3Q27": D3Q27}
 STORAGE = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
-PATTERNS = {"inplace": INPLACE, "double": DOUBLE}
+PATTERNS = {"inplace": INPLACE, "double": DOUBLE, "pull": PULL}
 Q_OF = {D2Q9: 9, D3Q19: 19, D3Q27: 27}
 D_OF = {D2Q9: 2, D3Q19: 3, D3Q27: 3}
 

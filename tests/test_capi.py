@@ -94,6 +94,8 @@ def test_create_and_options_without_device():
     assert L.lbm_set_options(h, ctypes.byref(bad)) == lbm.LBM_EINVAL
     bad = lbm.lbm_options(lbm.F32, lbm.F32, lbm.INPLACE, 0, -1.0)
     assert L.lbm_set_options(h, ctypes.byref(bad)) == lbm.LBM_EINVAL
+    ok = lbm.lbm_options(lbm.F32, lbm.F32, lbm.PULL, 0, 1.0)
+    assert L.lbm_set_options(h, ctypes.byref(ok)) == lbm.LBM_OK
     ok = lbm.lbm_options(lbm.BF16, lbm.F32, lbm.DOUBLE, 0, 1.0)
     assert L.lbm_set_options(h, ctypes.byref(ok)) == lbm.LBM_OK
     # state-dependent calls before init

@@ -8,6 +8,7 @@ arithmetic: <= 1e-4.  The oracle adjoint itself is pinned by finite
 differences and dense-Jacobian transposes in test_oracle_adjoint.py.
 """
 import sys
+from dataclasses import replace
 
 import numpy as np
 import pytest
@@ -108,6 +109,10 @@ ADJ_CASES = {
     "spheres3d_d3q27_f64_K4": (spheres3d("f64"), 4, 1, 1e-10),
     "zperiodic3d_f64_K5": (zperiodic3d("f64"), 5, 1, 1e-10),
     "zperiodic3d_f32_K7": (zperiodic3d("f32"), 7, 0, 1e-4),
+    # the pull pattern: the tape's checkpoints hold the gathered layout
+    "channel2d_pbb_f64_K5_pull": (replace(channel2d("f64"), pattern="pull"), 5, 0, 1e-10),
+    "cavity3d_f64_K6_oddstart_pull": (replace(cavity3d("f64"), pattern="pull"), 6, 3, 1e-10),
+    "spheres3d_d3q27_f32_K4_pull": (replace(spheres3d("f32"), pattern="pull"), 4, 1, 1e-4),
 }
 
 

@@ -111,12 +111,12 @@ def test_force_matches_oracle(name, storage):
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_force_with_solid_fraction_and_double_buffer(storage):
     """Partial bounce-back field (the force goes in before the mix) and the
-    double-buffer pattern (its own step kernel)."""
+    double-buffer patterns (push and pull: their own step kernels)."""
     rng = np.random.default_rng(7)
     shape = (10, 12, 66)
     s = (rng.random(shape) * (rng.random(shape) < 0.3)).astype(np.float64)
     utol, rtol = TOL[storage]
-    for pattern in ("inplace", "double"):
+    for pattern in ("inplace", "double", "pull"):
         case = Case(19, shape, 0.7, [(W,), (W, (0, 0.02, 0)), (P,), (P,), (P,), (P,)], steps=15, storage=storage,
                     pattern=pattern, init_seed=210, s=s)
         fld, uni = _field(case, 310)

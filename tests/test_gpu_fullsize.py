@@ -118,18 +118,19 @@ def _channel_faces():
     return [(ZV, (0.04, 0.0, 0.0)), (OUT, (0.0, 0.0, 0.0), 1.0), (W,), (W,), (W,), (W,)]
 
 
+@pytest.mark.parametrize("pattern", ["inplace", "pull"])
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
-def test_channel_spheres_reduced_300_steps_vs_oracle(storage, tol):
+def test_channel_spheres_reduced_300_steps_vs_oracle(storage, tol, pattern):
     path = os.path.join(GOLDEN, "channel_spheres_d3q27_300.npz")
     if not os.path.exists(path):
         pytest.skip("run tests/golden/make_golden.py channel_spheres first")
-    _announce(f"channel spheres 256x128x128 {storage} 300 steps")
+    _announce(f"channel spheres 256x128x128 {storage} {pattern} 300 steps")
     import torch
     ref = np.load(path)
     shape = (256, 128, 128)
     solid = inputs.sphere_obstacles(*shape, seed=3, rmin=2.0, rmax=8.0, xlo=16, xhi=240, fraction=0.05)
     assert np.array_equal(solid[::2, ::2, 64], ref["solid_z64"])
-    sim = lbm.Sim("D3Q27", shape, 0.6, faces=_channel_faces(), storage=storage)
+    sim = lbm.Sim("D3Q27", shape, 0.6, faces=_channel_faces(), storage=storage, pattern=pattern)
     sim.set_solid(solid)
     sim.init_equilibrium()
     sim.step(300)
@@ -142,16 +143,18 @@ def test_channel_spheres_reduced_300_steps_vs_oracle(storage, tol):
     assert e <= tol and er <= tol
 
 
-def test_channel_spheres_full_size_light_cone_samples():
-    """1024 x 512 x 512 D3Q27 FP32, the benchmarked grid and launch: sampled
-    cells after 6 steps from a seeded wave field vs the oracle on their light
-    cones (inlet, outlet, walls, edges, cells next to spheres, random)."""
-    _announce("channel spheres 1024x512x512 f32 light-cone samples")
+@pytest.mark.parametrize("pattern", ["inplace", "pull"])
+def test_channel_spheres_full_size_light_cone_samples(pattern):
+    """1024 x 512 x 512 D3Q27 FP32, the benchmarked grid and launch (both
+    patterns): sampled cells after 6 steps from a seeded wave field vs the
+    oracle on their light cones (inlet, outlet, walls, edges, cells next to
+    spheres, random)."""
+    _announce(f"channel spheres 1024x512x512 f32 {pattern} light-cone samples")
     import torch
     shape = (1024, 512, 512)
     steps, seed, amp = 6, 31, 0.03
     solid = inputs.sphere_obstacles(*shape, seed=3)
-    sim = lbm.Sim("D3Q27", shape, 0.6, faces=_channel_faces(), storage="f32", pattern="inplace")
+    sim = lbm.Sim("D3Q27", shape, 0.6, faces=_channel_faces(), storage="f32", pattern=pattern)
     sim.set_solid(solid)
     rho0, u0 = inputs.wave_field(shape, seed, amp=amp, xp=torch, device="cuda")
     sim.init_equilibrium(rho0, u0.permute(3, 0, 1, 2).contiguous())
@@ -178,7 +181,10 @@ def test_channel_spheres_full_size_light_cone_samples():
         u_g = np.array([float(u[a][c]) for a in range(3)])
         worst_u = max(worst_u, float(np.max(np.abs(u_g - u_o))))
         worst_r = max(worst_r, abs(r_g - r_o))
-    print(f"[case] full-size channel: max |du| {worst_u:.3e} (u scale {amp}), max |drho| {worst_r:.3e}", flush=True)
+    print(f"[case] full-size channel {pattern}: max |du| {worst_u:.3e} (u scale {amp}), max |drho| {worst_r:.3e}",
+          flush=True)
+    del sim, rho, u
+    torch.cuda.empty_cache()
     assert worst_u <= 1e-5 * amp * 10 and worst_r <= 1e-6
 
 

@@ -126,14 +126,15 @@ def test_kbc_double_buffer_equals_in_place():
     import torch
     base = CASES["d3q27_lid_box"]
     out = []
-    for pattern in ("inplace", "double"):
+    for pattern in ("inplace", "double", "pull"):
         case = Case(base.q, base.shape, base.tau, base.faces, steps=11, storage="f32", pattern=pattern,
                     init_seed=base.init_seed)
         sim = gpu_sim(case)
         sim.set_collision("KBC")
         sim.step(11)
         out.append(sim.moments())
-    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+    for o in out[1:]:
+        assert torch.equal(out[0][0], o[0]) and torch.equal(out[0][1], o[1])
 
 
 def test_kbc_refusals():

@@ -13,7 +13,7 @@ import sys
 import numpy as np
 import pytest
 
-from cases import Case, compare, gpu_run, oracle_run
+from cases import Case, compare, gpu_run, gpu_sim, oracle_run
 from paper_2311_16080_amd import inputs, lbm
 
 pytestmark = pytest.mark.gpu
@@ -85,6 +85,18 @@ CASES = {
                                  storage="f32"),
     "zouhe_pres_pres_d2q9_f64_y_axis": Case(9, (33, 70), 0.8, [(W,), (W,), (ZP, (0, 0, 0), 1.005),
                                                                (ZP, (0, 0, 0), 0.995), (P,), (P,)], steps=45),
+    # the pull pattern (two buffers, every step gathers): walls, solids and open
+    # faces, periodic Z faces, partial bounce-back
+    "cavity_d3q19_f64_pull": Case(19, (10, 9, 300), 0.55, cavity_faces3(), steps=61, pattern="pull"),
+    "channel_spheres_d3q27_f32_pull": Case(27, (24, 12, 70), 0.6, channel_faces3(), steps=30, init_seed=6,
+                                           solid=spheres((24, 12, 70)), storage="f32", pattern="pull"),
+    "zouhe_vel_pres_d3q19_f64_periodic_z_pull": Case(19, (20, 9, 70), 0.7,
+                                                     [(ZV, (0.03, 0.005, 0.002)), (ZP, (0, 0, 0), 0.99), (W,), (W,),
+                                                      (P,), (P,)], steps=27, init_seed=9, pattern="pull"),
+    "channel_pbb_d2q9_f64_pull": Case(9, (96, 40), 0.6, [(ZV, (0.04, 0)), (OUT, (0, 0, 0), 1.0), (W,), (W,), (P,), (P,)],
+                                      steps=50, s=inputs.smooth_solid_fraction(96, 40, seed=4, sigma=3, edge=8),
+                                      pattern="pull"),
+    "periodic_d3q27_f16_pull": Case(27, (7, 6, 128), 0.9, steps=12, init_seed=3, storage="f16", pattern="pull"),
 }
 
 
@@ -113,18 +125,43 @@ def test_parity_vs_oracle(name):
 @pytest.mark.parametrize("q,shape", [(9, (40, 130)), (19, (6, 7, 130)), (27, (5, 6, 66))])
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 def test_inplace_equals_double_buffer_bitwise(q, shape, storage):
-    """The in-place AA pattern and the double-buffer push pattern run the same
-    arithmetic; their moments agree bitwise after even and odd step counts."""
+    """The in-place AA pattern, the double-buffer push pattern and the pull
+    pattern run the same arithmetic; their moments agree bitwise after even and
+    odd step counts (and after the pull pattern's first, local step)."""
     import torch
-    _announce(f"inplace-vs-double q={q} {storage}")
+    _announce(f"inplace-vs-double-vs-pull q={q} {storage}")
     faces = [(ZV, (0.03, 0, 0)), (OUT, (0, 0, 0), 1.0), (W,), (W, (0.02, 0, 0)), (W,), (W,)]
-    for steps in (6, 7):
-        a = Case(q, shape, 0.6, faces, steps=steps, storage=storage, init_seed=20, pattern="inplace")
-        b = Case(q, shape, 0.6, faces, steps=steps, storage=storage, init_seed=20, pattern="double")
-        ga, gb = gpu_run(a), gpu_run(b)
-        assert np.array_equal(ga[0], gb[0]) and np.array_equal(ga[1], gb[1]), steps
-        del ga, gb
+    for steps in (1, 6, 7):
+        res = [gpu_run(Case(q, shape, 0.6, faces, steps=steps, storage=storage, init_seed=20, pattern=pat))
+               for pat in ("inplace", "double", "pull")]
+        for k, g in enumerate(res[1:], 1):
+            assert np.array_equal(res[0][0], g[0]) and np.array_equal(res[0][1], g[1]), (steps, k)
+        del res
         torch.cuda.synchronize()
+
+
+def test_pull_pattern_graph_replay_equals_steps():
+    """A graph of pull steps replays what lbm_step does, replay after replay;
+    a graph captured before the first (local) step is refused afterwards."""
+    import torch
+    _announce("pull graph replay")
+    case = Case(19, (8, 9, 130), 0.6, cavity_faces3(), steps=0, storage="f32", init_seed=21, pattern="pull")
+    a, b = gpu_sim(case), gpu_sim(case)
+    c = gpu_sim(case)
+    c.capture_graph(2)
+    c.graph_launch()           # from t = 0: the local step, then a pull step
+    a.step(1)
+    b.step(1)
+    b.capture_graph(2)
+    for k in range(3):
+        a.step(2)
+        b.graph_launch()
+        torch.cuda.synchronize()
+        ra, ua = a.moments()
+        rb, ub = b.moments()
+        assert torch.equal(ra, rb) and torch.equal(ua, ub), k
+    with pytest.raises(lbm.LbmError):
+        c.graph_launch()       # t > 0 now: the captured local step no longer applies
 
 
 def test_uniform_rest_with_walls_fixed_point():
@@ -217,6 +254,9 @@ PAIR_CASES = {
     "cavity_d3q19_rows768": (19, (4, 5, 768), [(W,), (W, (0, 0.02, 0.01)), (W,), (W,), (W,), (W, (0.05, 0.01, 0))]),
     "cavity_d3q27_rows1024": (27, (3, 4, 1024), [(W,)] * 5 + [(W, (0.04, 0.02, 0.0))]),
     "pbb_d2q9": (9, (24, 256), [(W,), (W,), (W,), (W, (0.06, 0.0)), (P,), (P,)]),
+    # one wavefront per row (both Z walls in every wavefront), moving walls on Y and Z faces
+    "cavity_d3q19_rows128": (19, (5, 6, 128), [(W,), (W,), (W,), (W, (0.02, 0, 0.01)), (W, (0.01, 0.02, 0)),
+                                               (W, (0.05, 0.01, 0))]),
 }
 
 

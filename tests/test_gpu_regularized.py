@@ -63,13 +63,14 @@ def test_regularized_double_buffer_equals_in_place():
     import torch
     base = CASES["d3q27_pres_pres"]
     out = []
-    for pattern in ("inplace", "double"):
+    for pattern in ("inplace", "double", "pull"):
         case = Case(base.q, base.shape, base.tau, base.faces, steps=13, storage="f32", pattern=pattern,
                     init_seed=base.init_seed)
         sim = gpu_sim(case)
         sim.step(13)
         out.append(sim.moments())
-    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+    for o in out[1:]:
+        assert torch.equal(out[0][0], o[0]) and torch.equal(out[0][1], o[1])
 
 
 def test_batch_with_regularized_faces_equals_single_domains():
