@@ -559,6 +559,30 @@ def kbc_figures(torch, lbm, steps=60):
     return res
 
 
+def pattern_size_figures(torch, lbm, steps=10):
+    """In-place vs pull pattern on D3Q19 FP32 walls-only cavities from 4M to
+    268M cells: the in-place neighbour step stores Z-shifted addresses, whose
+    cost shows once the state outgrows the 256 MB Infinity Cache; the pull
+    pattern stores only aligned cell-local slots."""
+    res = {}
+    for shape in ((64, 256, 256), (256, 256, 256), (1024, 256, 256), (4096, 256, 256), (1024, 512, 512)):
+        N = int(np.prod(shape))
+        row = {"GB_state": round(N * 76 / 1e9, 2)}
+        for pattern in ("inplace", "pull"):
+            sim = lbm.Sim("D3Q19", shape, 0.6, faces=cavity_faces(lbm), storage="f32", pattern=pattern)
+            sim.use_current_stream()
+            sim.init_equilibrium()
+            sim.step(4)
+            with Timer(torch) as T:
+                sim.step(steps)
+            mlups = N * steps / (T.ms / 1e3) / 1e6
+            row[pattern] = {"MLUPS": round(mlups, 1), "frac": round(mlups * 152 / 1e3 / PEAK_HBM_GBPS, 4)}
+            del sim
+            torch.cuda.empty_cache()
+        res["x".join(str(v) for v in shape)] = row
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -573,7 +597,8 @@ def main():
                     help="skip the FP16/BF16, adjoint, batched and D3Q27 channel figures")
     ap.add_argument("--extra", default=None,
                     choices=["storage_f16_bf16", "adjoint_forward_ratio", "batched_cavities", "d3q27_channel_spheres",
-                             "d3q19_forced_channel", "d3q19_regularized_channel", "kbc_cavities"],
+                             "d3q19_forced_channel", "d3q19_regularized_channel", "kbc_cavities",
+                             "pattern_sizes"],
                     help="run only this secondary figure and print it as one JSON line (for profiling)")
     args = ap.parse_args()
 
@@ -591,7 +616,8 @@ def main():
                "d3q27_channel_spheres": lambda: channel_spheres_figures(torch, lbm),
                "d3q19_forced_channel": lambda: forced_channel_figures(torch, lbm),
                "d3q19_regularized_channel": lambda: regularized_channel_figures(torch, lbm),
-               "kbc_cavities": lambda: kbc_figures(torch, lbm)}
+               "kbc_cavities": lambda: kbc_figures(torch, lbm),
+               "pattern_sizes": lambda: pattern_size_figures(torch, lbm)}
         print(json.dumps({"extra": args.extra, "result": fns[args.extra]()}), flush=True)
         return
 
@@ -678,7 +704,8 @@ def main():
                         ("d3q27_channel_spheres", lambda: channel_spheres_figures(torch, lbm)),
                         ("d3q19_forced_channel", lambda: forced_channel_figures(torch, lbm)),
                         ("d3q19_regularized_channel", lambda: regularized_channel_figures(torch, lbm)),
-                        ("kbc_cavities", lambda: kbc_figures(torch, lbm))):
+                        ("kbc_cavities", lambda: kbc_figures(torch, lbm)),
+                        ("pattern_sizes", lambda: pattern_size_figures(torch, lbm))):
             t0 = time.perf_counter()
             try:
                 extras[key] = fn()

@@ -462,14 +462,14 @@ hipError_t step_t(const Launch &g, int mode, bool has_s) {
     if constexpr (sizeof(ST) == 2) {
         // two cells per lane (walls and, in the even step, periodic faces on its
         // own path); not with a body force or the KBC collision.  pair 1: even
-        // steps; 2: even and odd steps (measurement).
-        if (!g.force && !g.kbc && g.pair && mode < 2 && (mode == 0 || g.pair == 2)) {
+        // and pull steps; 2: odd steps too (measurement).
+        if (!g.force && !g.kbc && g.pair && mode != 2 && (mode != 1 || g.pair == 2)) {
             // no solid cells and walls on every lattice face: the variant without
             // the per-cell fallback (D3Q19 even step 99 vs 109 VGPRs; 2% faster)
             const bool walls = !p.flags && (p.wallmask & all_face_bits<L>()) == all_face_bits<L>();
 #define LBM_PAIR_CASE(M, S, NF)                                                                                     \
     if (mode == M && has_s == S && walls == NF)                                                                     \
-        hipLaunchKernelGGL((k_step_pair<L, ST, M, S, NF>), dim3(g.pgrid), dim3(g.pblock), 0, g.stream, p, A);
+        hipLaunchKernelGGL((k_step_pair<L, ST, M, S, NF>), dim3(g.pgrid), dim3(g.pblock), 0, g.stream, p, A, B);
             LBM_PAIR_CASE(0, false, false)
             LBM_PAIR_CASE(1, false, false)
             LBM_PAIR_CASE(0, true, false)
@@ -478,6 +478,10 @@ hipError_t step_t(const Launch &g, int mode, bool has_s) {
             LBM_PAIR_CASE(1, false, true)
             LBM_PAIR_CASE(0, true, true)
             LBM_PAIR_CASE(1, true, true)
+            LBM_PAIR_CASE(3, false, false)
+            LBM_PAIR_CASE(3, true, false)
+            LBM_PAIR_CASE(3, false, true)
+            LBM_PAIR_CASE(3, true, true)
 #undef LBM_PAIR_CASE
             return hipGetLastError();
         }

@@ -105,8 +105,8 @@ __device__ __forceinline__ float wall_term(const Params<float> &p, uint32_t cr, 
 // would otherwise set the kernel's register allocation (109 vs 64 VGPRs for
 // the D3Q19 FP16 even step).
 template <class L, class ST, int MODE, bool HAS_S, bool NOFB = false>
-__device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict__ A, int X, int Y, int z0,
-                                          int pending) {
+__device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict__ A, ST *__restrict__ B, int X,
+                                          int Y, int z0, int pending) {
     constexpr int Q = L::Q;
     constexpr uint32_t kFaces = all_face_bits<L>();
     constexpr uint32_t kXY = 0xFu;  // faces of the X and Y axes
@@ -121,12 +121,15 @@ __device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict
     if (!NOFB && !__all(plain && ((e0 | e1) & kFaces & ~sel_faces) == 0)) {
         // (the even step's select path takes periodic faces too)
         constexpr int XF = (HAS_S ? 1 : 0) | (MODE == 0 ? 4 : 0);
-        step_cell<L, ST, MODE, XF, 1>(p, A, nullptr, X, Y, z0, pending);
-        step_cell<L, ST, MODE, XF, 1>(p, A, nullptr, X, Y, z0 + 1, pending);
+        step_cell<L, ST, MODE, XF, 1>(p, A, B, X, Y, z0, pending);
+        step_cell<L, ST, MODE, XF, 1>(p, A, B, X, Y, z0 + 1, pending);
         return;
     }
     uint32_t *W = reinterpret_cast<uint32_t *>(A);            // pairs: element index / 2
     uint16_t *H = reinterpret_cast<uint16_t *>(A);
+    // the pull step (MODE 3) gathers from A like the odd step and stores the
+    // cell's own opposite slots into B like the even step
+    uint32_t *WO = reinterpret_cast<uint32_t *>(MODE == 3 ? B : A);
     const uint32_t exy = e0 & kXY;                              // X / Y faces: the same for the whole row
     // ---- read: pairs of h_i(z0), h_i(z0 + 1) -------------------------------------
     uint32_t u[Q];
@@ -209,8 +212,8 @@ __device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict
         constexpr int cz = L::c[I][2];
         constexpr uint32_t fb = src_face_bits<L>(O);  // faces x + c_i can lie across
         const uint32_t v = out[I];
-        if constexpr (MODE == 0) {
-            st32<true>(W + (pidx<Q>(O, cell0) >> 1), v);
+        if constexpr (MODE == 0 || MODE == 3) {
+            st32<true>(WO + (pidx<Q>(O, cell0) >> 1), v);
         } else if (exy & fb) {
             // destination row across an X / Y wall: both values bounce into own slot O
             st32<true>(W + (pidx<Q>(O, cell0) >> 1), v);
@@ -241,12 +244,13 @@ __device__ __forceinline__ void step_pair(const Params<float> &p, ST *__restrict
 
 // one lane per cell pair; grid: rows x (nZ / 2 / blockDim.x)
 template <class L, class ST, int MODE, bool HAS_S, bool NOFB = false>
-__global__ void __launch_bounds__(kMaxBlock) k_step_pair(const Params<float> p, ST *__restrict__ A) {
+__global__ void __launch_bounds__(kMaxBlock) k_step_pair(const Params<float> p, ST *__restrict__ A,
+                                                         ST *__restrict__ B) {
     const int per_row = (p.nZ >> 1) / (int)blockDim.x;
     const int b = (int)blockIdx.x;
     const int r = b / per_row;
     const int z0 = 2 * ((b - r * per_row) * (int)blockDim.x + (int)threadIdx.x);
-    step_pair<L, ST, MODE, HAS_S, NOFB>(p, A, r / p.nY, r % p.nY, z0, p.zh_pending);
+    step_pair<L, ST, MODE, HAS_S, NOFB>(p, A, B, r / p.nY, r % p.nY, z0, p.zh_pending);
 }
 
 }  // namespace lbm

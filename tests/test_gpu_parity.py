@@ -270,13 +270,16 @@ def test_pair_kernel_matches_one_cell_per_lane_bitwise(name, storage, monkeypatc
     solid = spheres(shape) if name.startswith("spheres") else None
     sfrac = inputs.smooth_solid_fraction(*shape, seed=4, sigma=3, edge=4) if name.startswith("pbb") else None
     res = {}
-    # never / even steps / even and odd steps
+    # never / even steps / even and odd steps; the pull pattern (pull steps)
     for pair in ("0", "1", "2"):
         monkeypatch.setenv("LBM_PAIR", pair)
         for steps in (7, 8):
             res[(pair, steps)] = gpu_run(Case(q, shape, 0.6, faces, steps=steps, storage=storage, init_seed=55,
                                               solid=solid, s=sfrac))
-    for pair in ("1", "2"):
-        for steps in (7, 8):
-            a, b = res[("0", steps)], res[(pair, steps)]
-            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), (pair, steps)
+            if pair != "2":
+                res[(pair, steps, "pull")] = gpu_run(Case(q, shape, 0.6, faces, steps=steps, storage=storage,
+                                                          init_seed=55, solid=solid, s=sfrac, pattern="pull"))
+    for key in [("1", 7), ("1", 8), ("2", 7), ("2", 8), ("0", 7, "pull"), ("0", 8, "pull"), ("1", 7, "pull"),
+                ("1", 8, "pull")]:
+        a, b = res[("0", key[1])], res[key]
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), key
