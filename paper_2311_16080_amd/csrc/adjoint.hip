@@ -153,7 +153,10 @@ __device__ __forceinline__ typename Store<ST>::CT adjoint_cell(const Params<type
     const uint32_t e = edge_bits(p, X, Y, Z);
     const uint32_t irr = irregular_mask<L>(e, nbm);
     CT h[Q];
-    unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(F, cell); });
+    {
+        const int64_t sc = sidx<ST>(p, cell);   // F is in the forward path's storage layout
+        unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(F, sc); });
+    }
     const int zf = zh_face_of(p, e);
     if (zf >= 0 && pending) zouhe<L>(h, p, zf);
     CT drho = 0, jx = 0, jy = 0, jz = 0;
@@ -464,7 +467,10 @@ __device__ __forceinline__ void seed_cell(const Params<typename Store<ST>::CT> &
     }
     const uint32_t e = edge_bits(p, X, Y, Z);
     CT h[Q];
-    unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(F, cell); });
+    {
+        const int64_t sc = sidx<ST>(p, cell);   // F is in the forward path's storage layout
+        unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(F, sc); });
+    }
     const int zf = zh_face_of(p, e);
     if (zf >= 0 && pending) zouhe<L>(h, p, zf);
     CT drho = 0, jx = 0, jy = 0, jz = 0;
@@ -522,19 +528,21 @@ __device__ __forceinline__ void materialize_cell(const Params<typename Store<ST>
         if (fl & 1) return;
         if (fl & 2) nbm = p.nbm[cell];
     }
-    const uint32_t e = edge_bits(p, X, Y, Z);
+    const uint32_t e = edge_bits_st<ST>(p, X, Y, Z);
     const uint32_t irr = irregular_mask<L>(e, nbm);
+    const int64_t sc = sidx<ST>(p, cell);
+    const int64_t sm = smul<ST>(p);
     unroll<Q>([&](auto I) {
         constexpr int O = opp<L>(I);
         ST v;
         if (!((irr >> I) & 1u)) {
-            const int64_t src = cell - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
+            const int64_t src = sc - sm * ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
             v = A[pidx<Q>(O, src)];
         } else {
             const Nb nb = classify_src<L>(p, X, Y, Z, I, nbm);
-            v = (nb.kind == NB_FLUID) ? A[pidx<Q>(O, nb.cell)] : A[pidx<Q>(I, cell)];
+            v = (nb.kind == NB_FLUID) ? A[pidx<Q>(O, sidx<ST>(p, nb.cell))] : A[pidx<Q>(I, sc)];
         }
-        D[pidx<Q>(I, cell)] = v;  // opposite slots share the storage scale
+        D[pidx<Q>(I, sc)] = v;  // opposite slots share the storage scale
     });
 }
 

@@ -194,6 +194,8 @@ static void fill_params(Params<CT> &p, const lbm_ctx *c) {
     // faster on every lattice; the rotation stays available for measurement
     p.zrot = (c->zrot > 0 && c->nZ >= 64 && !c->flat) ? 32 : 0;
     p.flat = c->flat;
+    p.spk = c->split;
+    p.nh = c->N / 2;
     p.ft = face_table<CT>(c);
     p.flags = c->flags;
     p.nbm = c->nbm;
@@ -238,6 +240,8 @@ static void map_faces(lbm_ctx *c, const lbm_bc *bc) {
     }
 }
 
+static void setup_mapping(lbm_ctx *c);
+
 static void setup_shape(lbm_ctx *c, int lattice, int nx, int ny, int nz, double tau) {
     c->lattice = lattice;
     c->Q = lattice_q(lattice);
@@ -259,6 +263,22 @@ static void setup_shape(lbm_ctx *c, int lattice, int nx, int ny, int nz, double 
     // population layout (core.hpp, pidx)
     c->plane = tiled_cells(c->N);
     c->tau = tau;
+    setup_mapping(c);
+}
+
+// Lanes -> cells.  2-byte storage on a 3-D box of even nX runs in split pairs
+// (the two X-halves share each 32-bit word, core.hpp): blocks of 256 lanes in
+// storage order, and one lane per pair in the two-cell step.
+static void setup_mapping(lbm_ctx *c) {
+    const bool two = c->opt.storage == LBM_F16 || c->opt.storage == LBM_BF16;
+    c->split = (two && c->split_req != 0 && c->pair && !c->batch && c->D == 3 && c->nX >= 4 && c->nX % 2 == 0) ? 1 : 0;
+    if (c->split) {
+        c->flat = 1;
+        c->block = 256;
+        c->zblocks = 1;
+        c->grid = (c->N + 255) / 256;
+        return;
+    }
     // threads per block along Z: LBM_BLOCK if set, else the size among 256 /
     // 128 / 192 that launches the fewest lanes per row (ties: in that order;
     // measured on a 768 x 256 x 384 channel: 128 lanes per block run 20%
@@ -321,6 +341,8 @@ extern "C" lbm_ctx *lbm_create(int lattice, int nx, int ny, int nz, double tau, 
         if (wo && (wo[0] == '0' || wo[0] == '1')) c->walls_only = wo[0] - '0';
         const char *fl = std::getenv("LBM_FLAT");
         if (fl && (fl[0] == '0' || fl[0] == '1')) c->flat_req = fl[0] - '0';
+        const char *sp = std::getenv("LBM_SPLIT");
+        if (sp && (sp[0] == '0' || sp[0] == '1')) c->split_req = sp[0] - '0';
         const char *bl = std::getenv("LBM_BLOCK");
         if (bl) {
             const int v = std::atoi(bl);
@@ -358,6 +380,7 @@ extern "C" int lbm_set_options(lbm_ctx *c, const lbm_options *o) {
     if (c->nlinks && o->compute != c->opt.compute)
         return fail(LBM_ESTATE, "the compute type cannot change while curved links are set (lbm_set_curved_links)");
     c->opt = *o;
+    if (!c->batch) setup_mapping(c);   // the storage type decides the split-pair layout
     refresh_params(c);
     return LBM_OK;
 }
@@ -529,6 +552,13 @@ Launch lbm::make_launch(lbm_ctx *c) {
     g.kbc = c->collision == LBM_KBC ? 1 : 0;
     g.walls_only = c->walls_only;
     if (g.force || g.kbc) return g;   // these run on the one-cell-per-lane kernel
+    if (c->split) {
+        // split pairs: one lane per pair of cells
+        g.pair = c->pair;
+        g.pblock = 256;
+        g.pgrid = (unsigned)((c->N / 2 + 255) / 256);
+        return g;
+    }
     // two cells per lane for 2-byte storage: rows of nZ % 128 == 0 cells, no
     // lane rotation or XCD remap (the pair kernel's row mapping is fixed)
     if ((c->opt.storage == LBM_F16 || c->opt.storage == LBM_BF16) && c->pair && !c->batch && c->nZ % 128 == 0 &&
@@ -986,7 +1016,7 @@ extern "C" int lbm_save(lbm_ctx *c, void *host, size_t bytes) {
     std::memcpy(h.magic, "LBMSTAT1", 8);
     h.lattice = c->lattice;
     h.storage = c->opt.storage;
-    h.pattern = c->opt.pattern;
+    h.pattern = c->opt.pattern | (c->split ? 0x100 : 0);   // the split-pair layout is part of the image
     h.Q = c->Q;
     h.N = c->N;
     h.plane = c->plane;
@@ -1005,7 +1035,8 @@ extern "C" int lbm_load(lbm_ctx *c, const void *host, size_t bytes) {
     StateHeader h;
     std::memcpy(&h, host, sizeof h);
     if (std::memcmp(h.magic, "LBMSTAT1", 8) != 0) return fail(LBM_EINVAL, "not a state image");
-    if (h.lattice != c->lattice || h.storage != c->opt.storage || h.pattern != c->opt.pattern || h.N != c->N ||
+    if (h.lattice != c->lattice || h.storage != c->opt.storage || h.pattern != (c->opt.pattern | (c->split ? 0x100 : 0)) ||
+        h.N != c->N ||
         h.plane != c->plane || h.Q != c->Q)
         return fail(LBM_EINVAL, "state image does not match this context (lattice/storage/pattern/shape)");
     if (bytes < lbm_state_bytes(c)) return fail(LBM_EINVAL, "buffer too small: need %zu bytes", lbm_state_bytes(c));

@@ -79,6 +79,8 @@ struct Params {
     int xcd_remap;         // give each XCD a contiguous range of rows
     int zrot;              // lane rotation within a Z row (block_cell)
     int flat;              // lanes cover consecutive cells of the whole grid (rows not a multiple of 64 cells)
+    int spk;               // 2-byte storage in split pairs (the two X-halves share a 32-bit word)
+    int64_t nh;            // cells of the low X-half (split pairs)
     const uint8_t *flags;  // N bytes or null: bit0 solid, bit1 a neighbour is solid
     const uint32_t *nbm;   // N words: bit k set when x - c_k is a solid cell
     const float *s;        // N or null: partial bounce-back solid fraction
@@ -162,6 +164,31 @@ __host__ __device__ __forceinline__ int64_t pidx(int i, int64_t cell) {
     return (int64_t)(((uint64_t)t << kTileLog) | (c & (uint32_t)(kTile - 1)));
 }
 __host__ __device__ constexpr int64_t tiled_cells(int64_t n) { return (n + kTile - 1) / kTile * kTile; }
+
+// Split pairs (2-byte storage, nX even).  The cell (X', Y, Z) of the low
+// X-half and the cell (X' + nX/2, Y, Z) of the high half share one 32-bit word
+// per population: storage index 2 c' + h with c' = (X' nY + Y) nZ + Z and
+// h = 1 for the high half, tiled like a cell index.  A neighbour in the same
+// half lies 2 x its cell offset away in storage indices, so a two-cell step
+// moves aligned 32-bit words under every lattice shift; only the planes
+// X' = nX/2 - 1 and X = nX/2, whose X-neighbours sit in the other half (the
+// seam), take the general path.  Other storage types: the cell index itself.
+template <class ST, class CT>
+__device__ __forceinline__ int64_t sidx(const Params<CT> &p, int64_t cell) {
+    if constexpr (sizeof(ST) == 2) {
+        if (p.spk) {
+            const int64_t h = cell >= p.nh ? 1 : 0;
+            return 2 * (cell - h * p.nh) + h;
+        }
+    }
+    return cell;
+}
+// storage-index step of one cell-index step within a half
+template <class ST, class CT>
+__device__ __forceinline__ int64_t smul(const Params<CT> &p) {
+    if constexpr (sizeof(ST) == 2) return p.spk ? 2 : 1;
+    return 1;
+}
 
 template <class L, int I, class ST>
 __device__ __forceinline__ const ST *pop_ptr(const ST *base, int64_t cell) {
@@ -400,12 +427,24 @@ __device__ __forceinline__ void regularize(CT *h, const Params<CT> &p, int face)
     });
 }
 
-// Edge bits of a cell: which box faces it sits on.
+// Edge bits of a cell: which box faces it sits on (bits 0-5), and with split
+// pairs the seam (bit 6: X = nX/2 - 1, whose +X neighbour is in the high half;
+// bit 7: X = nX/2, whose -X neighbour is in the low half).
 template <class CT>
 __device__ __forceinline__ uint32_t edge_bits(const Params<CT> &p, int X, int Y, int Z) {
     return (uint32_t)(X == 0) | ((uint32_t)(X == p.nX - 1) << 1) | ((uint32_t)(Y == 0) << 2) |
            ((uint32_t)(Y == p.nY - 1) << 3) | ((uint32_t)(Z == 0) << 4) | ((uint32_t)(Z == p.nZ - 1) << 5);
 }
+// the same with the seam bits of split pairs, for kernels that address
+// populations of storage type ST by neighbour offsets
+template <class ST, class CT>
+__device__ __forceinline__ uint32_t edge_bits_st(const Params<CT> &p, int X, int Y, int Z) {
+    uint32_t e = edge_bits(p, X, Y, Z);
+    if constexpr (sizeof(ST) == 2)
+        if (p.spk) e |= ((uint32_t)(2 * X + 2 == p.nX) << 6) | ((uint32_t)(2 * X == p.nX) << 7);
+    return e;
+}
+constexpr uint32_t kSeams = 0xC0u;
 
 // Periodic Z faces in the select paths.  A wavefront spans Z, so only its
 // lanes at Z = 0 or nZ - 1 wrap: the Z step of a neighbour address is -1 / +1
@@ -426,9 +465,11 @@ __device__ __forceinline__ int64_t src_off(const Params<CT> &p, const ZWrap &w) 
 }
 constexpr uint32_t kZFaces = 48u;
 
-// Which directions have a source that is not a plain in-box fluid neighbour.
+// Which directions have a source that is not a plain in-box fluid neighbour
+// of the same split-pair half (a seam counts like the X face it mirrors).
 template <class L>
 __device__ __forceinline__ uint32_t irregular_mask(uint32_t e, uint32_t nbm) {
+    e |= ((e >> 6) & 1u) << 1 | ((e >> 7) & 1u);
     uint32_t m = nbm;
     unroll<L::Q>([&](auto I) {
         constexpr uint32_t dm = src_face_bits<L>(I);

@@ -48,6 +48,8 @@ struct lbm_ctx {
     int block_req = 0;               // LBM_BLOCK = 64 / 128 / 192 / 256 (threads per block, along Z); 0: by row length
     int flat = 0;                    // blocks cover consecutive cells of the grid (rows not a multiple of 64 cells)
     int flat_req = -1;               // LBM_FLAT = 0 / 1 forces the row / flat mapping (measurement); -1: by row length
+    int split = 0;                   // 2-byte storage in split pairs (core.hpp, sidx)
+    int split_req = -1;              // LBM_SPLIT = 0 / 1: split pairs off / on where possible (default on)
 
     // device
     int device = -1;

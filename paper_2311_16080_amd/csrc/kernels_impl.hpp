@@ -39,8 +39,22 @@ namespace lbm {
 // (X, Y, Z from the flat index), so rows whose length is not a multiple of 64
 // cells still give aligned, fully occupied wavefronts; a wavefront may then
 // hold the end of one row and the start of the next.
-template <class CT>
+// PK (2-byte storage): with split pairs the lanes follow storage order, the
+// cells of the two X-halves alternating, so that one-cell-per-lane kernels
+// touch whole 32-bit words.
+template <bool PK = false, class CT>
 __device__ __forceinline__ bool block_cell_at(const Params<CT> &p, int b, int G, int &X, int &Y, int &Z) {
+    if (PK && p.spk) {
+        const uint32_t v = (uint32_t)b * blockDim.x + threadIdx.x;
+        const uint32_t c = v >> 1;
+        const uint32_t nz = (uint32_t)p.nZ, ny = (uint32_t)p.nY, hx = (uint32_t)(p.nX >> 1);
+        const uint32_t r = c / nz;
+        Z = (int)(c - r * nz);
+        Y = (int)(r % ny);
+        const uint32_t xh = r / ny;
+        X = (int)(xh + (v & 1u) * hx);
+        return xh < hx;
+    }
     if (p.flat) {
         const uint32_t cell = (uint32_t)b * blockDim.x + threadIdx.x;
         const uint32_t nz = (uint32_t)p.nZ, ny = (uint32_t)p.nY;
@@ -59,9 +73,9 @@ __device__ __forceinline__ bool block_cell_at(const Params<CT> &p, int b, int G,
     Z = (lin >= p.zrot) ? lin - p.zrot : lin - p.zrot + p.nZ;
     return lin < p.nZ;
 }
-template <class CT>
+template <bool PK = false, class CT>
 __device__ __forceinline__ bool block_cell(const Params<CT> &p, int &X, int &Y, int &Z) {
-    return block_cell_at(p, (int)blockIdx.x, (int)gridDim.x, X, Y, Z);
+    return block_cell_at<PK>(p, (int)blockIdx.x, (int)gridDim.x, X, Y, Z);
 }
 
 // One cell of one step.  p: the domain's parameters; A (and B for the push
@@ -100,6 +114,9 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
     using CT = typename Store<ST>::CT;
     constexpr int Q = L::Q;
     const int64_t cell = ((int64_t)X * p.nY + Y) * p.nZ + Z;
+    // populations are addressed by storage index: sc for this cell, sm per cell step
+    const int64_t sc = sidx<ST>(p, cell);
+    const int64_t sm = smul<ST>(p);
     uint32_t nbm = 0;
     if (p.flags) {
         const uint8_t fl = p.flags[cell];
@@ -108,7 +125,7 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
     }
     CT fx = 0, fy = 0, fz = 0;
     if constexpr (FRC) load_body_force(p, cell, fx, fy, fz);   // issued with the population loads
-    const uint32_t e = edge_bits(p, X, Y, Z);
+    const uint32_t e = edge_bits_st<ST>(p, X, Y, Z);
     const uint32_t irr = irregular_mask<L>(e, nbm);
 
     // Wavefronts of interior cells only (no face, no solid neighbour): plain
@@ -118,11 +135,11 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
         if constexpr (GATHER) {
             unroll<Q>([&](auto I) {
                 constexpr int O = opp<L>(I);
-                const int64_t src = cell - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
+                const int64_t src = sc - sm * ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
                 h[I] = ldh<L, ST, O, (L::c[I][2] == 0) ? NTA : NTZL>(A, src);
             });
         } else {
-            unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I, NTA>(A, cell); });
+            unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I, NTA>(A, sc); });
         }
         CT hp[Q];
         CT rho, ux, uy, uz;
@@ -133,9 +150,9 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
         unroll<Q>([&](auto I) {
             constexpr int O = opp<L>(I);
             if constexpr (LOCAL_W) {
-                sth<L, ST, O, NTA>(W, cell, hp[I]);
+                sth<L, ST, O, NTA>(W, sc, hp[I]);
             } else {
-                const int64_t dst = cell + ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
+                const int64_t dst = sc + sm * ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
                 sth<L, ST, I, (L::c[I][2] == 0) ? NTA : NTZS>(W, dst, hp[I]);
             }
         });
@@ -150,7 +167,7 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
     // periodic face bounces back, as there.
     constexpr uint32_t kFaces = all_face_bits<L>();
     const uint32_t sel_faces = p.wallmask | (PZ ? (MODE == 0 ? p.permask : (p.permask & kZFaces)) : 0u);
-    if (__all((e & kFaces & ~sel_faces) == 0)) {
+    if (__all((e & (kFaces | kSeams) & ~sel_faces) == 0)) {
         const ZWrap zw = (PZ && MODE != 0) ? z_wrap(p, e & p.permask) : ZWrap{-1, 1};
         // wall faces of this cell (without PZ, e's lattice faces are all walls here)
         const uint32_t we = PZ ? (e & p.wallmask) : e;
@@ -160,12 +177,12 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
                 constexpr int O = opp<L>(I);
                 // x - c_i is across a wall or solid
                 const bool wall = ((we & src_face_bits<L>(I)) | (nbm & (1u << I))) != 0;
-                const ST *nb = pop_ptr<L, O>(A, cell + src_off<L, I>(p, zw));
-                const ST *ptr = wall ? pop_ptr<L, I>(A, cell) : nb;
+                const ST *nb = pop_ptr<L, O>(A, sc + sm * src_off<L, I>(p, zw));
+                const ST *ptr = wall ? pop_ptr<L, I>(A, sc) : nb;
                 h[I] = ldp<L, ST, O, (L::c[I][2] == 0) ? NTA : NTZL>(ptr);  // w_O = w_I
             });
         } else {
-            unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I, NTA>(A, cell); });
+            unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I, NTA>(A, sc); });
         }
         CT hp[Q];
         CT rho, ux, uy, uz;
@@ -179,10 +196,10 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
             constexpr bool NTW = (LOCAL_W || L::c[I][2] == 0) ? NTA : NTZS;
             const uint32_t cr = we & fb;
             const bool wall = (cr | (nbm & (1u << O))) != 0;  // x + c_i is across a wall or solid
-            ST *own = pop_ptr<L, O>(W, cell);
+            ST *own = pop_ptr<L, O>(W, sc);
             ST *ptr = own;
             if constexpr (!LOCAL_W)
-                ptr = wall ? own : pop_ptr<L, I>(W, cell + src_off<L, O>(p, zw));  // x + c_i = x - c_opp(i)
+                ptr = wall ? own : pop_ptr<L, I>(W, sc + sm * src_off<L, O>(p, zw));  // x + c_i = x - c_opp(i)
             CT v = hp[I];
             if (cr && !(cr & p.staticmask)) {
                 // moving wall: the lowest-index face crossed (static walls win);
@@ -211,15 +228,15 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
             constexpr int O = opp<L>(I);
             const ST *ptr;
             if (!((irr >> I) & 1u)) {
-                ptr = pop_ptr<L, O>(A, cell - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]));
+                ptr = pop_ptr<L, O>(A, sc - sm * ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]));
             } else {
                 const Nb nb = classify_src<L>(p, X, Y, Z, I, nbm);
-                ptr = (nb.kind == NB_FLUID) ? pop_ptr<L, O>(A, nb.cell) : pop_ptr<L, I>(A, cell);
+                ptr = (nb.kind == NB_FLUID) ? pop_ptr<L, O>(A, sidx<ST>(p, nb.cell)) : pop_ptr<L, I>(A, sc);
             }
             h[I] = ldp<L, ST, O, (L::c[I][2] == 0) ? NTA : NTZL>(ptr);  // w_O = w_I
         });
     } else {
-        unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I, NTA>(A, cell); });
+        unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I, NTA>(A, sc); });
     }
 
     const int zf = zh_face_of(p, e);
@@ -239,15 +256,15 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
         ST *ptr;
         CT v = hp[I];
         if (!((irr >> O) & 1u)) {
-            if constexpr (LOCAL_W) ptr = pop_ptr<L, O>(W, cell);
-            else ptr = pop_ptr<L, I>(W, cell + ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]));
+            if constexpr (LOCAL_W) ptr = pop_ptr<L, O>(W, sc);
+            else ptr = pop_ptr<L, I>(W, sc + sm * ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]));
         } else {
             const Nb nb = classify_src<L>(p, X, Y, Z, O, nbm);   // the cell x + c_i
             if (nb.kind == NB_FLUID) {
-                if constexpr (LOCAL_W) ptr = pop_ptr<L, O>(W, cell);
-                else ptr = pop_ptr<L, I>(W, nb.cell);
+                if constexpr (LOCAL_W) ptr = pop_ptr<L, O>(W, sc);
+                else ptr = pop_ptr<L, I>(W, sidx<ST>(p, nb.cell));
             } else {
-                ptr = pop_ptr<L, O>(W, cell);
+                ptr = pop_ptr<L, O>(W, sc);
                 v = fill_value<L, I>(p, nb, hp[I], perim, rho, ux, uy, uz);
             }
         }
@@ -259,7 +276,7 @@ template <class L, class ST, int MODE, int XF, int NT>
 __global__ void __launch_bounds__(kMaxBlock) k_step(const Params<typename Store<ST>::CT> p, ST *__restrict__ A,
                                                     ST *__restrict__ B) {
     int X, Y, Z;
-    if (!block_cell(p, X, Y, Z)) return;
+    if (!block_cell<sizeof(ST) == 2>(p, X, Y, Z)) return;
     step_cell<L, ST, MODE, XF, NT>(p, A, B, X, Y, Z, p.zh_pending);
 }
 
@@ -277,7 +294,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_init(const Params<typename Store<
                                                     int64_t N) {
     using CT = typename Store<ST>::CT;
     int X, Y, Z;
-    if (!block_cell(p, X, Y, Z)) return;
+    if (!block_cell<sizeof(ST) == 2>(p, X, Y, Z)) return;
     const int64_t cell = ((int64_t)X * p.nY + Y) * p.nZ + Z;
     const bool solid = p.flags && (p.flags[cell] & 1);
     CT rho = rho_in ? (CT)rho_in[cell] : p.rho0;
@@ -294,9 +311,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_init(const Params<typename Store<
     }
     const CT usq15 = (CT)1.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     const CT drho = rho - p.rho0;
+    const int64_t sc = sidx<ST>(p, cell);
     unroll<L::Q>([&](auto I) {
         CT v = solid ? (CT)0 : heq<L, I>(drho, rho, u[0], u[1], u[2], usq15);
-        sth<L, ST, I>(A, cell, v);
+        sth<L, ST, I>(A, sc, v);
     });
 }
 
@@ -320,22 +338,24 @@ __device__ __forceinline__ bool moments_cell(const Params<typename Store<ST>::CT
         if (fl & 1) return false;
         if (fl & 2) nbm = p.nbm[cell];
     }
-    const uint32_t e = edge_bits(p, X, Y, Z);
+    const uint32_t e = edge_bits_st<ST>(p, X, Y, Z);
     const uint32_t irr = irregular_mask<L>(e, nbm);
+    const int64_t sc = sidx<ST>(p, cell);
+    const int64_t sm = smul<ST>(p);
     CT h[Q];
     if constexpr (ODD) {
         unroll<Q>([&](auto I) {
             constexpr int O = opp<L>(I);
             if (!((irr >> I) & 1u)) {
-                const int64_t src = cell - ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
+                const int64_t src = sc - sm * ((int64_t)L::c[I][0] * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2]);
                 h[I] = ldh<L, ST, O>(A, src);
             } else {
                 const Nb nb = classify_src<L>(p, X, Y, Z, I, nbm);
-                h[I] = (nb.kind == NB_FLUID) ? ldh<L, ST, O>(A, nb.cell) : ldh<L, ST, I>(A, cell);
+                h[I] = (nb.kind == NB_FLUID) ? ldh<L, ST, O>(A, sidx<ST>(p, nb.cell)) : ldh<L, ST, I>(A, sc);
             }
         });
     } else {
-        unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(A, cell); });
+        unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(A, sc); });
     }
     const int zf = zh_face_of(p, e);
     if (zf >= 0 && (ODD || pending)) zouhe<L>(h, p, zf);
@@ -400,7 +420,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_moments(const Params<typename Sto
                                                        int64_t N) {
     using CT = typename Store<ST>::CT;
     int X, Y, Z;
-    const bool inside = block_cell(p, X, Y, Z);
+    const bool inside = block_cell<sizeof(ST) == 2>(p, X, Y, Z);
     double m[5] = {0, 0, 0, 0, 0};
     if (inside) {
         CT rho, ux, uy, uz;
@@ -460,6 +480,28 @@ hipError_t step_t(const Launch &g, int mode, bool has_s) {
     ST *A = static_cast<ST *>(g.A);
     ST *B = static_cast<ST *>(g.B);
     if constexpr (sizeof(ST) == 2) {
+        // split pairs: every step but the push step on the two-cell kernel
+        if (p.spk && g.pair && !g.force && !g.kbc && mode != 2) {
+            // no solid cells and walls on every lattice face: the kernel without the
+            // per-cell fallback
+            const bool nofb = !p.flags && (p.wallmask & all_face_bits<L>()) == all_face_bits<L>();
+#define LBM_SPLIT_CASE(M, S, NF) \
+    if (mode == M && has_s == S && nofb == NF) hipLaunchKernelGGL((k_step_split<L, ST, M, S, NF>), dim3(g.pgrid), dim3(g.pblock), 0, g.stream, p, A, B);
+            LBM_SPLIT_CASE(0, false, false)
+            LBM_SPLIT_CASE(1, false, false)
+            LBM_SPLIT_CASE(3, false, false)
+            LBM_SPLIT_CASE(0, true, false)
+            LBM_SPLIT_CASE(1, true, false)
+            LBM_SPLIT_CASE(3, true, false)
+            LBM_SPLIT_CASE(0, false, true)
+            LBM_SPLIT_CASE(1, false, true)
+            LBM_SPLIT_CASE(3, false, true)
+            LBM_SPLIT_CASE(0, true, true)
+            LBM_SPLIT_CASE(1, true, true)
+            LBM_SPLIT_CASE(3, true, true)
+#undef LBM_SPLIT_CASE
+            return hipGetLastError();
+        }
         // two cells per lane (walls and, in the even step, periodic faces on its
         // own path); not with a body force or the KBC collision.  pair 1: even
         // and pull steps; 2: odd steps too (measurement).
@@ -492,8 +534,9 @@ hipError_t step_t(const Launch &g, int mode, bool has_s) {
     // bandwidth there), so D3Q19 keeps the full kernel.
     if constexpr (L::Q != 19) {
         constexpr int NTD0 = sizeof(ST) == 2 ? 0 : 1;
+        // (not with split pairs: their seam planes need the general path)
         if ((p.wallmask & all_face_bits<L>()) == all_face_bits<L>() && !has_s && !g.force && !g.kbc &&
-            g.nt == NTD0 && g.walls_only) {
+            g.nt == NTD0 && g.walls_only && !p.spk) {
             if (mode == 0)
                 hipLaunchKernelGGL((k_step<L, ST, 0, 16, NTD0>), dim3(g.grid), dim3(g.block), 0, g.stream, p, A, B);
             else if (mode == 1)
@@ -650,7 +693,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_forces(const Params<typename Stor
 #pragma unroll
     for (int k = 0; k < kForceSlots; ++k) part[k] = 0.0;
     bool links = false;
-    if (block_cell_at(p, (int)(b0 + (int64_t)blockIdx.x), (int)G, X, Y, Z)) {
+    if (block_cell_at<sizeof(ST) == 2>(p, (int)(b0 + (int64_t)blockIdx.x), (int)G, X, Y, Z)) {
         const int64_t cell = ((int64_t)X * p.nY + Y) * p.nZ + Z;
         uint32_t nbm = 0;
         bool solid = false;
@@ -668,7 +711,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_forces(const Params<typename Stor
                     const bool wall = cr != 0;
                     if (wall || ((nbm >> O) & 1u)) {
                         links = true;
-                        const double back = (double)ldh<L, ST, O>(A, cell) + weight<L>(O) * (double)p.rho0;
+                        const double back = (double)ldh<L, ST, O>(A, sidx<ST>(p, cell)) + weight<L>(O) * (double)p.rho0;
                         double term = 0.0;
                         int base = 0;
                         if (wall) {
@@ -762,7 +805,7 @@ __global__ void __launch_bounds__(256) k_bouzidi(const Params<typename Store<ST>
             w = (CT)weight<L>(I);
         }
     });
-    auto ld = [&](int d, int64_t cell) -> CT { return Store<ST>::ld(A + pidx<L::Q>(d, cell)); };
+    auto ld = [&](int d, int64_t cell) -> CT { return Store<ST>::ld(A + pidx<L::Q>(d, sidx<ST>(p, cell))); };
     const CT q = lt.q[k];
     const CT a = ld(o, xb);
     CT r;
@@ -785,7 +828,7 @@ __global__ void __launch_bounds__(256) k_bouzidi(const Params<typename Store<ST>
             r = a / (q * ((CT)2 * q + (CT)1)) + ((CT)2 * q - (CT)1) / q * d + ((CT)1 - (CT)2 * q) / ((CT)1 + (CT)2 * q) * e;
         }
     }
-    Store<ST>::st(A + pidx<L::Q>(o, xb), r);
+    Store<ST>::st(A + pidx<L::Q>(o, sidx<ST>(p, xb)), r);
     lt.dlt[k] = Store<ST>::scaled ? (a - r) * w : (a - r);
 }
 

@@ -254,3 +254,160 @@ __global__ void __launch_bounds__(kMaxBlock) k_step_pair(const Params<float> p, 
 }
 
 }  // namespace lbm
+
+namespace lbm {
+
+// ---- split pairs -----------------------------------------------------------
+// 2-byte storage with the box's two X-halves sharing each 32-bit word (core.hpp,
+// sidx): lane t owns the pair c' = t, the cell (X', Y, Z) of the low half and
+// (X' + nX/2, Y, Z) of the high half.  Every lattice shift moves both cells of a
+// pair to the same neighbouring pair, so the step reads and writes aligned
+// 32-bit words in every direction -- the Z-shifted ones one word apart, as a
+// 4-byte population would be.  Wavefronts whose cells meet only wall faces (and
+// in the local steps periodic faces) take this path; any other wavefront
+// (solids, open faces) runs step_cell once per cell.  Per cell the arithmetic is
+// step_cell's, so both give bitwise-equal states.
+//
+// The planes X' = 0 and X' = nX/2 - 1 hold an X face in one half and the seam
+// in the other.  NOFB (no solid cells, walls on every lattice face; the host
+// checks) keeps them on this path: there the directions that cross the X face
+// in one half and the seam in the other move each half on its own -- the
+// bounced half from or into the cell's own slot, the other half from or into
+// the cell across the seam, in the other half -- with 16-bit accesses.
+// Without NOFB those planes take the per-cell fallback in gathering steps.
+template <class L, class ST, int MODE, bool HAS_S, bool NOFB = false>
+__device__ __forceinline__ void step_split(const Params<float> &p, ST *__restrict__ A, ST *__restrict__ B, int Xh,
+                                           int Y, int Z, int pending) {
+    constexpr int Q = L::Q;
+    constexpr uint32_t kFaces = all_face_bits<L>();
+    constexpr bool GATHER = (MODE == 1 || MODE == 3);
+    const int hx = p.nX >> 1;
+    const int64_t c0 = ((int64_t)Xh * p.nY + Y) * p.nZ + Z;   // low-half cell; its pair index
+    const uint32_t e0 = edge_bits(p, Xh, Y, Z);
+    const uint32_t e1 = edge_bits(p, Xh + hx, Y, Z);
+    const bool xlo = Xh == 0, xhi = Xh == hx - 1;              // X' edge planes
+    if constexpr (!NOFB) {
+        bool plain = true;
+        if (p.flags) plain = (p.flags[c0] | p.flags[c0 + p.nh]) == 0;
+        const uint32_t sel_faces = p.wallmask | (MODE == 0 ? p.permask : 0u);
+        const bool xedge = GATHER && (xlo || xhi);
+        if (!__all(plain && !xedge && ((e0 | e1) & kFaces & ~sel_faces) == 0)) {
+            constexpr int XF = (HAS_S ? 1 : 0) | (MODE == 0 ? 4 : 0);
+            step_cell<L, ST, MODE, XF, 1>(p, A, B, Xh, Y, Z, pending);
+            step_cell<L, ST, MODE, XF, 1>(p, A, B, Xh + hx, Y, Z, pending);
+            return;
+        }
+    }
+    const uint32_t *WA = reinterpret_cast<const uint32_t *>(A);
+    const uint16_t *HA = reinterpret_cast<const uint16_t *>(A);
+    uint32_t *WO = reinterpret_cast<uint32_t *>(MODE == 3 ? B : A);
+    uint16_t *HO = reinterpret_cast<uint16_t *>(MODE == 3 ? B : A);
+    const int64_t s0 = 2 * c0;                     // storage index of the pair's low cell
+    const uint32_t eyz = e0 & ~3u;                 // Y / Z faces, the same for both cells
+    const int64_t hsx = (int64_t)hx * p.sX;        // pair-index step between the X' edge planes
+    // ---- read ---------------------------------------------------------------------
+    uint32_t u[Q];
+    unroll<Q>([&](auto I) {
+        constexpr int O = opp<L>(I);
+        constexpr int cx = L::c[I][0], cz = L::c[I][2];
+        if constexpr (!GATHER) {
+            u[I] = ld32<true>(WA + (pidx<Q>(I, s0) >> 1));
+        } else {
+            // x - c_i across a Y / Z wall: both cells bounce back (own slot I);
+            // across the X face / seam of an edge plane: own slot here, the seam
+            // half below
+            const bool wall = (eyz & src_face_bits<L>(I)) != 0;
+            const bool split = NOFB && ((cx == 1 && xlo) || (cx == -1 && xhi));
+            const int64_t off = (int64_t)cx * p.sX + (int64_t)L::c[I][1] * p.sY + cz;
+            const int64_t a = (wall || split) ? pidx<Q>(I, s0) : pidx<Q>(O, s0 - 2 * off);
+            u[I] = ld32<cz == 0>(WA + (a >> 1));
+        }
+    });
+    if constexpr (NOFB && GATHER) {
+        if (__any(xlo || xhi)) {
+            unroll<Q>([&](auto I) {
+                constexpr int O = opp<L>(I);
+                constexpr int cx = L::c[I][0];
+                if constexpr (cx != 0) {
+                    const bool wall = (eyz & src_face_bits<L>(I)) != 0;
+                    const int64_t off = (int64_t)cx * p.sX + (int64_t)L::c[I][1] * p.sY + L::c[I][2];
+                    if (!wall && cx == 1 && xlo) {
+                        // low cell (X = 0): bounced, own low half; high cell (X = nX/2):
+                        // from X = nX/2 - 1, the low half of pair X' = nX/2 - 1
+                        const uint32_t v = HA[pidx<Q>(O, 2 * (c0 - off + hsx))];
+                        u[I] = (u[I] & 0xffffu) | (v << 16);
+                    } else if (!wall && cx == -1 && xhi) {
+                        // low cell (X = nX/2 - 1): from X = nX/2, the high half of pair
+                        // X' = 0; high cell (X = nX - 1): bounced, own high half
+                        const uint32_t v = HA[pidx<Q>(O, 2 * (c0 - off - hsx) + 1)];
+                        u[I] = (u[I] & 0xffff0000u) | v;
+                    }
+                }
+            });
+        }
+    }
+    // ---- collide the two cells (step_cell's arithmetic) ------------------------------
+    uint32_t out[Q];
+    {
+        float h[Q], hp[Q];
+        float r, ux, uy, uz;
+        unroll<Q>([&](auto I) { h[I] = hval<L, ST, I>(u[I]); });
+        const float sv = HAS_S ? p.s[c0] : 0.f;
+        collide<L>(h, hp, p, sv, HAS_S, r, ux, uy, uz);
+        unroll<Q>([&](auto I) {
+            out[I] = hbits<L, ST, I>(wall_term<L, opp<L>(I)>(p, e0 & p.wallmask & src_face_bits<L>(opp<L>(I)), hp[I]));
+        });
+    }
+    {
+        float h[Q], hp[Q];
+        float r, ux, uy, uz;
+        unroll<Q>([&](auto I) { h[I] = hval<L, ST, I>(u[I] >> 16); });
+        const float sv = HAS_S ? p.s[c0 + p.nh] : 0.f;
+        collide<L>(h, hp, p, sv, HAS_S, r, ux, uy, uz);
+        unroll<Q>([&](auto I) {
+            out[I] |= hbits<L, ST, I>(wall_term<L, opp<L>(I)>(p, e1 & p.wallmask & src_face_bits<L>(opp<L>(I)), hp[I])) << 16;
+        });
+    }
+    // ---- write ----------------------------------------------------------------------
+    unroll<Q>([&](auto I) {
+        constexpr int O = opp<L>(I);
+        constexpr int cx = L::c[I][0], cz = L::c[I][2];
+        if constexpr (MODE == 0 || MODE == 3) {
+            st32<true>(WO + (pidx<Q>(O, s0) >> 1), out[I]);
+        } else {
+            // x + c_i across a Y / Z wall: both values bounce into own slot O
+            const bool wall = (eyz & src_face_bits<L>(O)) != 0;
+            const int64_t off = (int64_t)cx * p.sX + (int64_t)L::c[I][1] * p.sY + cz;
+            if (NOFB && !wall && cx == -1 && xlo) {
+                // low cell (X = 0) bounces into its own slot O; the high cell (X = nX/2)
+                // writes X = nX/2 - 1, the low half of pair X' = nX/2 - 1
+                HO[pidx<Q>(O, s0)] = (uint16_t)out[I];
+                HO[pidx<Q>(I, 2 * (c0 + off + hsx))] = (uint16_t)(out[I] >> 16);
+            } else if (NOFB && !wall && cx == 1 && xhi) {
+                // the low cell (X = nX/2 - 1) writes X = nX/2, the high half of pair
+                // X' = 0; the high cell (X = nX - 1) bounces into its own slot O
+                HO[pidx<Q>(I, 2 * (c0 + off - hsx) + 1)] = (uint16_t)out[I];
+                HO[pidx<Q>(O, s0) + 1] = (uint16_t)(out[I] >> 16);
+            } else {
+                const int64_t a = wall ? pidx<Q>(O, s0) : pidx<Q>(I, s0 + 2 * off);
+                st32<cz == 0>(WO + (a >> 1), out[I]);
+            }
+        }
+    });
+}
+
+// one lane per pair; grid: ceil(N / 2 / blockDim.x)
+template <class L, class ST, int MODE, bool HAS_S, bool NOFB>
+__global__ void __launch_bounds__(kMaxBlock) k_step_split(const Params<float> p, ST *__restrict__ A,
+                                                          ST *__restrict__ B) {
+    const uint32_t c = (uint32_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nz = (uint32_t)p.nZ, ny = (uint32_t)p.nY;
+    const uint32_t r = c / nz;
+    const int Z = (int)(c - r * nz);
+    const int Y = (int)(r % ny);
+    const int Xh = (int)(r / ny);
+    if (Xh >= (p.nX >> 1)) return;
+    step_split<L, ST, MODE, HAS_S, NOFB>(p, A, B, Xh, Y, Z, p.zh_pending);
+}
+
+}  // namespace lbm

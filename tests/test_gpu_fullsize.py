@@ -68,10 +68,11 @@ def test_tgv_128_fp64_1000_steps():
 
 
 # ---- C2: 256^3 cavity, 1000 steps --------------------------------------------------------
-def _cavity_u_plane(storage, sample_cells):
+def _cavity_u_plane(storage, sample_cells, pattern="inplace"):
     import torch
     n = 256
-    sim = lbm.Sim("D3Q19", (n, n, n), 0.55, faces=[(W,)] * 5 + [(W, (0.05, 0.0, 0.0))], storage=storage)
+    sim = lbm.Sim("D3Q19", (n, n, n), 0.55, faces=[(W,)] * 5 + [(W, (0.05, 0.0, 0.0))], storage=storage,
+                  pattern=pattern)
     sim.init_equilibrium()
     sim.step(1000)
     rho, u = sim.moments(dtype=torch.float32)
@@ -84,8 +85,10 @@ def _cavity_u_plane(storage, sample_cells):
     return py, px, us, sums
 
 
-@pytest.mark.parametrize("storage,tol,mass_tol", [("f32", 1e-5, 1e-6), ("f16", 1e-3, 1e-6), ("bf16", 2e-2, 1e-4)])
-def test_cavity256_1000_steps_vs_oracle(storage, tol, mass_tol):
+@pytest.mark.parametrize("storage,tol,mass_tol,pattern", [("f32", 1e-5, 1e-6, "inplace"), ("f16", 1e-3, 1e-6, "inplace"),
+                                                          ("bf16", 2e-2, 1e-4, "inplace"), ("f16", 1e-3, 1e-6, "pull"),
+                                                          ("bf16", 2e-2, 1e-4, "pull")])
+def test_cavity256_1000_steps_vs_oracle(storage, tol, mass_tol, pattern):
     """The field bound (FP32 1e-5, FP16 1e-3 rel-L2 of u) is gated on a
     uniform random sample of 262144 cells, an unbiased estimate of the
     whole-field rel-L2.  The two whole planes through the centre are gated at
@@ -98,15 +101,15 @@ def test_cavity256_1000_steps_vs_oracle(storage, tol, mass_tol):
     path = os.path.join(GOLDEN, "cavity256_d3q19_1000.npz")
     if not os.path.exists(path):
         pytest.skip("run tests/golden/make_golden.py cavity256 first")
-    _announce(f"cavity 256^3 {storage} 1000 steps")
+    _announce(f"cavity 256^3 {storage} {pattern} 1000 steps")
     ref = np.load(path)
     if "u_sample" not in ref.files:
         pytest.skip("stored run predates the sampled golden; rerun tests/golden/make_golden.py cavity256")
-    py, px, us, sums = _cavity_u_plane(storage, ref["sample_cells"])
+    py, px, us, sums = _cavity_u_plane(storage, ref["sample_cells"], pattern)
     ey = float(np.linalg.norm(py - ref["u_y128"]) / np.linalg.norm(ref["u_y128"]))
     ex = float(np.linalg.norm(px - ref["u_x128"]) / np.linalg.norm(ref["u_x128"]))
     es = float(np.linalg.norm(us - ref["u_sample"]) / np.linalg.norm(ref["u_sample"]))
-    print(f"[case] cavity256 {storage}: u rel-L2 over the cell sample {es:.3e}, on y = 128 {ey:.3e}, "
+    print(f"[case] cavity256 {storage} {pattern}: u rel-L2 over the cell sample {es:.3e}, on y = 128 {ey:.3e}, "
           f"on x = 128 {ex:.3e}; KE {sums[4]:.6e} vs {ref['sums'][4]:.6e}", flush=True)
     assert es <= tol
     assert ey <= 2 * tol and ex <= 2 * tol
