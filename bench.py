@@ -467,7 +467,8 @@ def forced_channel_figures(torch, lbm, steps=100, adj_steps=40, K=10):
     h = 128 (768 x 256 x 384 cells), driven by F_x = Re_tau^2 nu^2 / h^3 at
     Re_tau = 180 through the exact-difference method; once as a uniform force,
     once as a per-cell field (3 more FP32 reads per cell), plus the adjoint /
-    forward time ratio with the field gradient requested."""
+    forward time ratio with the field gradient requested; the forced runs also
+    with the pull pattern."""
     from paper_2311_16080_amd import inputs
     h = 128
     shape = (6 * h, 2 * h, 3 * h)
@@ -514,6 +515,21 @@ def forced_channel_figures(torch, lbm, steps=100, adj_steps=40, K=10):
                                          "dL_dforce": [float(v) for v in dforce]}
             del dfield
             sim.tape_free()
+        del sim
+        torch.cuda.empty_cache()
+    # the pull pattern (two buffers, 5.7 GB): cell-local aligned stores
+    res["pull"] = {}
+    for kind, bpc in (("uniform", 152), ("field", 164)):
+        sim = lbm.Sim("D3Q19", shape, tau, faces=faces, storage="f32", pattern="pull")
+        sim.use_current_stream()
+        sim.init_equilibrium()
+        sim.set_force([Fx, 0.0, 0.0], field if kind == "field" else None)
+        sim.step(10)
+        with Timer(torch) as T:
+            sim.step(steps)
+        mlups = N * steps / (T.ms / 1e3) / 1e6
+        gbps = mlups * 1e6 * bpc / 1e9
+        res["pull"][kind] = {"MLUPS": round(mlups, 1), "GBps": round(gbps, 1), "frac": round(gbps / PEAK_HBM_GBPS, 4)}
         del sim
         torch.cuda.empty_cache()
     return res
