@@ -62,6 +62,7 @@ for _order in (1, 2):
 CASES["spheres_d3q19_f64_o2_double"] = ("sph", dict(q=19, order=2, pattern="double", steps=17))
 CASES["spheres_d3q19_f64_o2_pull"] = ("sph", dict(q=19, order=2, pattern="pull", steps=17))
 CASES["cylinder_d2q9_f64_o1_pull"] = ("cyl", dict(order=1, pattern="pull"))
+CASES["spheres_d3q27_f16_o1_pull"] = ("sph", dict(q=27, storage="f16", order=1, pattern="pull"))
 CASES["spheres_d3q27_f16_o1"] = ("sph", dict(q=27, storage="f16", order=1))
 
 

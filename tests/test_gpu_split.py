@@ -101,16 +101,17 @@ def test_split_pairs_forces_kbc_and_force_field(monkeypatch):
         assert np.array_equal(x, y)
 
 
-def test_split_pairs_tape_and_checkpoint(monkeypatch):
+@pytest.mark.parametrize("pattern", ["inplace", "pull"])
+def test_split_pairs_tape_and_checkpoint(pattern, monkeypatch):
     """The adjoint reads the split layout through its checkpoints; a saved image
     reloads into a context of the same layout and is refused by the other."""
     import torch
-    _announce("split tape / checkpoint")
+    _announce(f"split tape / checkpoint {pattern}")
     grads = {}
     images = {}
     for split in ("0", "1"):
         monkeypatch.setenv("LBM_SPLIT", split)
-        c = _case("pbb_d3q19", "f16", 0)
+        c = _case("pbb_d3q19", "f16", 0, pattern)
         sim = gpu_sim(c)
         sim.step(3)
         sim.tape_begin(4, 10)
@@ -129,6 +130,6 @@ def test_split_pairs_tape_and_checkpoint(monkeypatch):
     # dL/dtau: FP64 block sums over the two layouts' lane mappings, equal to rounding
     assert abs(grads["0"][1] - grads["1"][1]) <= 1e-12 * abs(grads["0"][1])
     monkeypatch.setenv("LBM_SPLIT", "1")
-    sim = gpu_sim(_case("pbb_d3q19", "f16", 0))
+    sim = gpu_sim(_case("pbb_d3q19", "f16", 0, pattern))
     with pytest.raises(lbm.LbmError):
         sim.load(images["0"])
