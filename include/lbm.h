@@ -409,8 +409,10 @@ int64_t lbm_tape_id(const lbm_ctx *ctx);
  * tape, if the state moved since the tape ended, or if lbm_set_params,
  * lbm_set_solid, lbm_set_solid_fraction, lbm_set_force or lbm_set_collision
  * was called after the tape began (the recorded steps no longer match the
- * parameters the adjoint would use); LBM_EUNSUPPORTED when a domain has
- * regularized faces or curved links.
+ * parameters the adjoint would use); LBM_EUNSUPPORTED with curved links,
+ * with the KBC collision, and with regularized faces on a batch context or
+ * with a body force (the regularized closure's transpose covers single
+ * domains without one).
  */
 int lbm_backward(lbm_ctx *ctx, const void *dL_drho, const void *dL_du, int dtype,
                  float *dL_ds, double *dL_dtau, double *dL_duw);

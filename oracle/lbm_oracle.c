@@ -524,6 +524,58 @@ void orc_zouhe_closure(const orc_sim *S, int face, double *f) { open_closure(S, 
  *                              (rho0, u_in) or (rho_w, u(x, t)) instead.
  * work: caller-provided buffers of N*q (post-collision) and N*3 (velocity).
  * ------------------------------------------------------------------------- */
+/* Streaming and boundary fill into fluid cell k (steps 2 and 3 up to the open-
+ * face closure): out[i] = f_i(x, t+1) before the closure, with the unknowns of
+ * an open face set to 0.  Returns the open face whose closure the cell takes,
+ * or -1.  fpost: post-collision populations, vel: velocities of every cell. */
+static int gather_cell(const orc_sim *S, long k, const double *fpost, const double *vel, double *out)
+{
+    const int q = S->q;
+    int x[3];
+    x[2] = (int)(k % S->nz);
+    x[1] = (int)((k / S->nz) % S->ny);
+    x[0] = (int)(k / ((long)S->nz * S->ny));
+    const double *u_here = vel + (size_t)k * 3;
+    int zh_face = -1;
+    int perimeter = on_wall_face(S, x);
+    for (int i = 0; i < q; ++i) {
+        const int *c = cvec(q, i);
+        orc_src src = classify(S, x, c);
+        switch (src.kind) {
+        case SRC_FLUID:
+            out[i] = fpost[src.cell * q + i];
+            break;
+        case SRC_WALL: {
+            const int o = opposite(q, i);
+            const double qv = S->qlink ? S->qlink[(size_t)k * q + o] : 0.0;
+            if (src.wall_face < 0 && qv > 0.0) {
+                /* a solid cell with a curved-wall link along c_o = -c_i */
+                out[i] = bouzidi_fill(S, x, o, qv, fpost);
+                break;
+            }
+            double cu = c[0] * src.uw[0] + c[1] * src.uw[1] + c[2] * src.uw[2];
+            out[i] = fpost[(size_t)k * q + o] + 6.0 * weight(q, i) * S->rho0 * cu;
+            break;
+        }
+        case SRC_OUTFLOW:
+            out[i] = feq_i(q, i, S->face[src.face].rho, u_here);
+            break;
+        case SRC_ZOUHE: {
+            const orc_face *F = &S->face[src.face];
+            if (perimeter) {
+                if (vel_face(F->type)) out[i] = feq_i(q, i, S->rho0, F->u);
+                else out[i] = feq_i(q, i, F->rho, u_here);
+            } else {
+                out[i] = 0.0;          /* unknown: filled by the closure */
+                zh_face = src.face;
+            }
+            break;
+        }
+        }
+    }
+    return zh_face;
+}
+
 static void step_impl(const orc_sim *S, const double *f, double *fn, double *fpost, double *vel)
 {
     const int q = S->q;
@@ -552,48 +604,7 @@ static void step_impl(const orc_sim *S, const double *f, double *fn, double *fpo
             for (int i = 0; i < q; ++i) out[i] = 0.0;   /* solid cells carry no state */
             continue;
         }
-        int x[3];
-        x[2] = (int)(k % S->nz);
-        x[1] = (int)((k / S->nz) % S->ny);
-        x[0] = (int)(k / ((long)S->nz * S->ny));
-        const double *u_here = vel + (size_t)k * 3;
-        int zh_face = -1;
-        int perimeter = on_wall_face(S, x);
-        for (int i = 0; i < q; ++i) {
-            const int *c = cvec(q, i);
-            orc_src src = classify(S, x, c);
-            switch (src.kind) {
-            case SRC_FLUID:
-                out[i] = fpost[src.cell * q + i];
-                break;
-            case SRC_WALL: {
-                const int o = opposite(q, i);
-                const double qv = S->qlink ? S->qlink[(size_t)k * q + o] : 0.0;
-                if (src.wall_face < 0 && qv > 0.0) {
-                    /* a solid cell with a curved-wall link along c_o = -c_i */
-                    out[i] = bouzidi_fill(S, x, o, qv, fpost);
-                    break;
-                }
-                double cu = c[0] * src.uw[0] + c[1] * src.uw[1] + c[2] * src.uw[2];
-                out[i] = fpost[(size_t)k * q + o] + 6.0 * weight(q, i) * S->rho0 * cu;
-                break;
-            }
-            case SRC_OUTFLOW:
-                out[i] = feq_i(q, i, S->face[src.face].rho, u_here);
-                break;
-            case SRC_ZOUHE: {
-                const orc_face *F = &S->face[src.face];
-                if (perimeter) {
-                    if (vel_face(F->type)) out[i] = feq_i(q, i, S->rho0, F->u);
-                    else out[i] = feq_i(q, i, F->rho, u_here);
-                } else {
-                    out[i] = 0.0;          /* unknown: filled by the closure below */
-                    zh_face = src.face;
-                }
-                break;
-            }
-            }
-        }
+        int zh_face = gather_cell(S, k, fpost, vel, out);
         if (zh_face >= 0) open_closure(S, zh_face, out);
     }
 }
@@ -724,10 +735,6 @@ int orc_adjoint_step(const orc_sim *S, const double *f, const double *a_next, do
 {
     const int q = S->q;
     const long N = (long)S->nx * S->ny * S->nz;
-    /* the regularized closure rewrites the known populations too and is not
-     * affine for pressure faces: its transpose is not written here */
-    for (int fc = 0; fc < 6; ++fc)
-        if (S->face[fc].type == ORC_REG_VEL || S->face[fc].type == ORC_REG_PRES) return -2;
     if (S->collision != 0) return -2;   /* the adjoint covers BGK only */
     double *ag = (double *)calloc((size_t)N * q, sizeof(double));
     double *apost = (double *)calloc((size_t)N * q, sizeof(double));
@@ -739,8 +746,28 @@ int orc_adjoint_step(const orc_sim *S, const double *f, const double *a_next, do
     }
     double duw[18] = {0};
 
-    /* (3) transpose of the Zou-He closure: unknowns i in U are
-     * f_i = sum_j A_ij g_j + b_i over known j, so dL/dg_j += A_ij dL/df_i. */
+    /* recompute the forward quantities of this step */
+    for (long k = 0; k < N; ++k) {
+        if (S->solid && S->solid[k]) continue;
+        double rho, u[3];
+        collide(S, f + (size_t)k * q, fpost + (size_t)k * q, &rho, u);
+        if (S->s) {
+            double s = S->s[k], mixed[27];
+            for (int i = 0; i < q; ++i)
+                mixed[i] = (1.0 - s) * fpost[(size_t)k * q + i] + s * f[(size_t)k * q + opposite(q, i)];
+            for (int i = 0; i < q; ++i) fpost[(size_t)k * q + i] = mixed[i];
+        }
+        for (int a = 0; a < 3; ++a) vel[(size_t)k * 3 + a] = u[a];
+    }
+
+    /* (3) transpose of the open-face closure.  Zou-He: unknowns i in U are
+     * f_i = sum_j A_ij g_j + b_i over known j, so dL/dg_j += A_ij dL/df_i.
+     * Regularized: every population is rewritten, f_i = R_i(g) over the known
+     * g_j, and R is a polynomial of degree at most 2 in them (rho or u_n is
+     * affine in g, the equilibrium quadratic in u, the rest linear), so the
+     * central difference (R(g + e_j) - R(g - e_j)) / 2 is its exact derivative;
+     * dL/dg_j = sum_i dR_i/dg_j dL/df_i, taken at this step's g (gather_cell
+     * from the post-collision state). */
     for (long k = 0; k < N; ++k) {
         if (S->solid && S->solid[k]) continue;
         int x[3];
@@ -757,7 +784,22 @@ int orc_adjoint_step(const orc_sim *S, const double *f, const double *a_next, do
         const double *an = a_next + (size_t)k * q;
         double *g = ag + (size_t)k * q;
         for (int i = 0; i < q; ++i) g[i] = unknown[i] ? 0.0 : an[i];
-        if (zh_face >= 0) {
+        const int reg = zh_face >= 0 && (S->face[zh_face].type == ORC_REG_VEL || S->face[zh_face].type == ORC_REG_PRES);
+        if (reg) {
+            double g0[27], gp[27], gm[27];
+            gather_cell(S, k, fpost, vel, g0);
+            for (int j = 0; j < q; ++j) {
+                if (unknown[j]) continue;
+                for (int i = 0; i < q; ++i) gp[i] = gm[i] = g0[i];
+                gp[j] += 1.0;
+                gm[j] -= 1.0;
+                open_closure(S, zh_face, gp);
+                open_closure(S, zh_face, gm);
+                double v = 0.0;
+                for (int i = 0; i < q; ++i) v += 0.5 * (gp[i] - gm[i]) * an[i];
+                g[j] = v;
+            }
+        } else if (zh_face >= 0) {
             double A[27][27], b[27];
             closure_matrix(S, zh_face, A, b);
             for (int i = 0; i < q; ++i) {
@@ -766,20 +808,6 @@ int orc_adjoint_step(const orc_sim *S, const double *f, const double *a_next, do
                     if (!unknown[j]) g[j] += A[i][j] * an[i];
             }
         }
-    }
-
-    /* recompute the forward quantities of this step */
-    for (long k = 0; k < N; ++k) {
-        if (S->solid && S->solid[k]) continue;
-        double rho, u[3];
-        collide(S, f + (size_t)k * q, fpost + (size_t)k * q, &rho, u);
-        if (S->s) {
-            double s = S->s[k], mixed[27];
-            for (int i = 0; i < q; ++i)
-                mixed[i] = (1.0 - s) * fpost[(size_t)k * q + i] + s * f[(size_t)k * q + opposite(q, i)];
-            for (int i = 0; i < q; ++i) fpost[(size_t)k * q + i] = mixed[i];
-        }
-        for (int a = 0; a < 3; ++a) vel[(size_t)k * 3 + a] = u[a];
     }
 
     /* (2) transpose of stream + fill: scatter each destination's adjoint */

@@ -119,6 +119,96 @@ __device__ __forceinline__ void zouhe_transpose(CT *a, const Params<CT> &p, int 
     unroll<L::Q>([&](auto I) { a[I] = (cn[I] == 1) ? (CT)0 : add[I]; });
 }
 
+// Transpose of the regularized closure at a face cell (the forward is
+// regularize() in core.hpp), taken at the cell's pre-closure populations g: the
+// adjoints a of every post-closure population become the adjoints of the known
+// g_j; those of the unknowns (overwritten) become 0.  Forward, in deviation
+// variables:
+//   known = sum_Z g + 2 sum_O g;  velocity face: rho = rho0 + (known + rho0 u_n)/(1 - u_n),
+//   u = u_w;  pressure face: rho = rho_w, u_n = (rho_w - rho0 - known)/rho_w, u = u_n n;
+//   n_i = g_i - heq_i(rho, u) (unknowns: n_opp(i));  P = sum_i c_i c_i n_i;
+//   out_i = heq_i + 4.5 w_i (c_i c_i - I/3) : P.
+// Reverse: dP from the out_i; dn_i = c_i c_i : dP; unknowns pass dn to their
+// opposites; dg_j = dn_j; dheq_i = a_i - dn_i (knowns), a_i (unknowns); then
+// rho (velocity) or u_n (pressure) carry sum_i dheq_i dheq_i/d(.) back to the
+// knowns with weight 1 (Z) or 2 (O).
+template <class L, class CT>
+__device__ __forceinline__ void regularize_transpose(CT *a, const Params<CT> &p, int face, const CT *g) {
+    constexpr int Q = L::Q;
+    const int ax = face >> 1;
+    const int sg = (face & 1) ? -1 : 1;
+    int cn[Q];
+    unroll<Q>([&](auto I) {
+        const int ca = (ax == 0) ? L::c[I][0] : ((ax == 1) ? L::c[I][1] : L::c[I][2]);
+        cn[I] = sg * ca;
+    });
+    const FaceTab<CT> &F = *p.ft;
+    const bool vel = F.type[face] == F_REG_VEL;
+    CT known = 0;
+    unroll<Q>([&](auto I) { known += (cn[I] == 0) ? g[I] : ((cn[I] == -1) ? (CT)2 * g[I] : (CT)0); });
+    CT rho, u[3], un;
+    if (vel) {
+        u[0] = F.uw[face][0];
+        u[1] = F.uw[face][1];
+        u[2] = F.uw[face][2];
+        un = (CT)sg * ((ax == 0) ? u[0] : ((ax == 1) ? u[1] : u[2]));
+        rho = p.rho0 + (known + p.rho0 * un) / ((CT)1 - un);
+    } else {
+        rho = F.rho[face];
+        un = (rho - p.rho0 - known) / rho;
+        u[0] = (ax == 0) ? (CT)sg * un : (CT)0;
+        u[1] = (ax == 1) ? (CT)sg * un : (CT)0;
+        u[2] = (ax == 2) ? (CT)sg * un : (CT)0;
+    }
+    const CT uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    // adjoint of the momentum flux P (symmetric; off-diagonal entries once)
+    CT d00 = 0, d11 = 0, d22 = 0, d01 = 0, d02 = 0, d12 = 0;
+    unroll<Q>([&](auto I) {
+        constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
+        const CT t = (CT)(4.5 * weight<L>(I)) * a[I];
+        d00 += t * (CT)((cx != 0 ? 1.0 : 0.0) - 1.0 / 3.0);
+        d11 += t * (CT)((cy != 0 ? 1.0 : 0.0) - 1.0 / 3.0);
+        d22 += t * (CT)((cz != 0 ? 1.0 : 0.0) - 1.0 / 3.0);
+        if constexpr (cx * cy != 0) d01 += t * (CT)(2 * cx * cy);
+        if constexpr (cx * cz != 0) d02 += t * (CT)(2 * cx * cz);
+        if constexpr (cy * cz != 0) d12 += t * (CT)(2 * cy * cz);
+    });
+    // adjoint of the non-equilibrium parts n_i (P00 = sum_{c_x != 0} n, P01 = sum c_x c_y n, ...)
+    CT dn[Q];
+    unroll<Q>([&](auto I) {
+        constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
+        CT v = 0;
+        if constexpr (cx != 0) v += d00;
+        if constexpr (cy != 0) v += d11;
+        if constexpr (cz != 0) v += d22;
+        if constexpr (cx * cy != 0) v += (CT)(cx * cy) * d01;
+        if constexpr (cx * cz != 0) v += (CT)(cx * cz) * d02;
+        if constexpr (cy * cz != 0) v += (CT)(cy * cz) * d12;
+        dn[I] = v;
+    });
+    // unknowns copy their opposite's n
+    unroll<Q>([&](auto I) {
+        constexpr int O = opp<L>(I);
+        if (cn[I] == 1) dn[O] += dn[I];
+    });
+    // equilibrium: out_i = heq_i + ..., n_i = g_i - heq_i (knowns)
+    CT drho = 0, du[3] = {0, 0, 0};
+    unroll<Q>([&](auto I) {
+        const CT dheq = a[I] - ((cn[I] == 1) ? (CT)0 : dn[I]);
+        const CT cu = (CT)L::c[I][0] * u[0] + (CT)L::c[I][1] * u[1] + (CT)L::c[I][2] * u[2];
+        drho += dheq * (CT)weight<L>(I) * ((CT)1 + (CT)3 * cu + (CT)4.5 * cu * cu - (CT)1.5 * uu);
+        unroll<3>([&](auto A) {
+            du[A] += dheq * (CT)weight<L>(I) * rho * ((CT)3 * (CT)L::c[I][A] + (CT)9 * cu * (CT)L::c[I][A] - (CT)3 * u[A]);
+        });
+    });
+    // rho (velocity face) or u_n (pressure face) back to the knowns
+    const CT dknown = vel ? drho / ((CT)1 - un) : -(CT)sg * ((ax == 0) ? du[0] : ((ax == 1) ? du[1] : du[2])) / rho;
+    unroll<Q>([&](auto I) {
+        const CT m = (cn[I] == 0) ? (CT)1 : ((cn[I] == -1) ? (CT)2 : (CT)0);
+        a[I] = (cn[I] == 1) ? (CT)0 : dn[I] + m * dknown;
+    });
+}
+
 // Adjoint step at time t for one fluid cell.  F: natural state f(t) (storage
 // type ST, the forward path's tiled layout); An: a(t+1); Ao: a(t).  The
 // adjoint populations are compute-type planes, a_i(x) at i * plane + x: the
@@ -128,7 +218,9 @@ __device__ __forceinline__ void zouhe_transpose(CT *a, const Params<CT> &p, int 
 // (HAS_S).  FRC: the body force is on; dF (or null): per-cell dL/dF
 // accumulators, 3 planes of N (internal axes).  Returns
 // sum_i lambda_i (f_i - feq_i), the cell's dL/dtau * tau^2.
-template <class L, class ST, bool HAS_S, bool FRC = false>
+// REG: regularized faces may occur (the pre-closure populations are kept for
+// the closure's transpose).
+template <class L, class ST, bool HAS_S, bool FRC = false, bool REG = false>
 __device__ __forceinline__ typename Store<ST>::CT adjoint_cell(const Params<typename Store<ST>::CT> &p,
                                                                const ST *__restrict__ F,
                                                                const typename Store<ST>::CT *__restrict__ An,
@@ -158,6 +250,8 @@ __device__ __forceinline__ typename Store<ST>::CT adjoint_cell(const Params<type
         unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(F, sc); });
     }
     const int zf = zh_face_of(p, e);
+    CT hpre[REG ? Q : 1];
+    if constexpr (REG) unroll<Q>([&](auto I) { hpre[I] = h[I]; });
     if (zf >= 0 && pending) zouhe<L>(h, p, zf);
     CT drho = 0, jx = 0, jy = 0, jz = 0;
     unroll<Q>([&](auto I) {
@@ -212,7 +306,8 @@ __device__ __forceinline__ typename Store<ST>::CT adjoint_cell(const Params<type
             unroll<Q>([&](auto K) {
                 if ((irr >> K) & 1u) {
                     const Nb ns = classify_src<L>(p, X, Y, Z, K, nbm);
-                    if (ns.kind == NB_OUT || (ns.kind == NB_ZH && perim && p.ft->type[ns.face] == F_ZH_PRES)) {
+                    if (ns.kind == NB_OUT ||
+                        (ns.kind == NB_ZH && perim && (p.ft->type[ns.face] == F_ZH_PRES || p.ft->type[ns.face] == F_REG_PRES))) {
                         const CT aK = An[(int64_t)K * P + cell];
                         const CT rf = p.ft->rho[ns.face];
                         const CT cu = (CT)L::c[K][0] * ux + (CT)L::c[K][1] * uy + (CT)L::c[K][2] * uz;
@@ -302,7 +397,14 @@ __device__ __forceinline__ typename Store<ST>::CT adjoint_cell(const Params<type
         if constexpr (HAS_S) v += s * b[O];
         a[J] = v;
     });
-    if (zf >= 0 && pending) zouhe_transpose<L>(a, p, zf);
+    if (zf >= 0 && pending) {
+        if constexpr (REG) {
+            if (p.ft->type[zf] >= F_REG_VEL) regularize_transpose<L>(a, p, zf, hpre);
+            else zouhe_transpose<L>(a, p, zf);
+        } else {
+            zouhe_transpose<L>(a, p, zf);
+        }
+    }
     unroll<Q>([&](auto I) { Ao[(int64_t)I * P + cell] = a[I]; });
     return gt;
 }
@@ -341,7 +443,7 @@ struct AdjWaves {
 #define LBM_ADJ_ATTR_F __attribute__((amdgpu_waves_per_eu(AdjWaves<L, ST, FRC>::value)))
 #endif
 
-template <class L, class ST, bool HAS_S, bool FRC>
+template <class L, class ST, bool HAS_S, bool FRC, bool REG>
 __global__ void __launch_bounds__(kMaxBlock) LBM_ADJ_ATTR_F k_adjoint(const Params<typename Store<ST>::CT> p, const ST *__restrict__ F,
                                                        const typename Store<ST>::CT *__restrict__ An,
                                                        typename Store<ST>::CT *__restrict__ Ao,
@@ -350,7 +452,7 @@ __global__ void __launch_bounds__(kMaxBlock) LBM_ADJ_ATTR_F k_adjoint(const Para
     int X, Y, Z;
     double g = 0.0;
     if (adj_block_cell(p, X, Y, Z))
-        g = (double)adjoint_cell<L, ST, HAS_S, FRC>(p, F, An, Ao, ds, X, Y, Z, p.zh_pending, dF, N);
+        g = (double)adjoint_cell<L, ST, HAS_S, FRC, REG>(p, F, An, Ao, ds, X, Y, Z, p.zh_pending, dF, N);
     block_add(g, acc, blockIdx.x);
 }
 
@@ -472,6 +574,8 @@ __device__ __forceinline__ void seed_cell(const Params<typename Store<ST>::CT> &
         unroll<Q>([&](auto I) { h[I] = ldh<L, ST, I>(F, sc); });
     }
     const int zf = zh_face_of(p, e);
+    CT hpre[Q];   // pre-closure populations (regularized faces)
+    unroll<Q>([&](auto I) { hpre[I] = h[I]; });
     if (zf >= 0 && pending) zouhe<L>(h, p, zf);
     CT drho = 0, jx = 0, jy = 0, jz = 0;
     unroll<Q>([&](auto I) {
@@ -501,7 +605,10 @@ __device__ __forceinline__ void seed_cell(const Params<typename Store<ST>::CT> &
         const CT gc = (CT)L::c[I][0] * gx + (CT)L::c[I][1] * gy + (CT)L::c[I][2] * gz;
         a[I] = gr + (gc - gdotu) * inv;
     });
-    if (zf >= 0 && pending) zouhe_transpose<L>(a, p, zf);
+    if (zf >= 0 && pending) {
+        if (p.ft->type[zf] >= F_REG_VEL) regularize_transpose<L>(a, p, zf, hpre);
+        else zouhe_transpose<L>(a, p, zf);
+    }
     unroll<Q>([&](auto I) { Ao[(int64_t)I * P + cell] = a[I]; });
 }
 
@@ -626,14 +733,17 @@ static hipError_t adj_dispatch(const AdjLaunch &g) {
                 hipLaunchKernelGGL((k_adjoint_batch<L, ST>), grid, block, 0, g.stream, bd, static_cast<const ST *>(g.F),
                                    static_cast<const CT *>(g.An), static_cast<CT *>(g.Ao), g.acc, g.pending);
             else {
-#define LBM_ADJ(S, FR)                                                                                             \
-    hipLaunchKernelGGL((k_adjoint<L, ST, S, FR>), grid, block, 0, g.stream, p, static_cast<const ST *>(g.F),       \
+#define LBM_ADJ(S, FR, RG)                                                                                         \
+    hipLaunchKernelGGL((k_adjoint<L, ST, S, FR, RG>), grid, block, 0, g.stream, p, static_cast<const ST *>(g.F),   \
                        static_cast<const CT *>(g.An), static_cast<CT *>(g.Ao), static_cast<CT *>(g.ds), g.acc,    \
                        static_cast<CT *>(g.dF), g.N);
-                if (g.ds && g.force) LBM_ADJ(true, true)
-                else if (g.ds) LBM_ADJ(true, false)
-                else if (g.force) LBM_ADJ(false, true)
-                else LBM_ADJ(false, false)
+                // (regularized faces with a body force are refused by the host)
+                if (g.reg && g.ds) LBM_ADJ(true, false, true)
+                else if (g.reg) LBM_ADJ(false, false, true)
+                else if (g.ds && g.force) LBM_ADJ(true, true, false)
+                else if (g.ds) LBM_ADJ(true, false, false)
+                else if (g.force) LBM_ADJ(false, true, false)
+                else LBM_ADJ(false, false, false)
 #undef LBM_ADJ
             }
             break;

@@ -199,6 +199,17 @@ extern "C" int lbm_tape_free(lbm_ctx *c) {
     return LBM_OK;
 }
 
+// Regularized faces: their closure's transpose (adjoint.hip) runs on single
+// domains without a body force.
+static bool has_regularized_face(const lbm_ctx *c) {
+    for (int d = 0; d < c->ndomains; ++d) {
+        const lbm_face *fc = c->batch ? c->dom[d].iface : c->iface;
+        for (int f = 0; f < 6; ++f)
+            if (fc[f].type == LBM_REG_VELOCITY || fc[f].type == LBM_REG_PRESSURE) return true;
+    }
+    return false;
+}
+
 namespace {
 struct Backward {
     lbm_ctx *c;
@@ -217,6 +228,7 @@ struct Backward {
         g.block = (unsigned)c->block;
         g.stream = c->stream;
         g.pending = (t > 0) ? 1 : 0;
+        g.reg = has_regularized_face(c) ? 1 : 0;
         if (c->batch) {
             g.batch = &bl.b;
             g.grid = bl.grid;
@@ -264,17 +276,6 @@ struct Backward {
 };
 }  // namespace
 
-// The regularized closure rewrites the known populations too (and is not
-// affine on pressure faces); its transpose is not written.
-static bool has_regularized_face(const lbm_ctx *c) {
-    for (int d = 0; d < c->ndomains; ++d) {
-        const lbm_face *fc = c->batch ? c->dom[d].iface : c->iface;
-        for (int f = 0; f < 6; ++f)
-            if (fc[f].type == LBM_REG_VELOCITY || fc[f].type == LBM_REG_PRESSURE) return true;
-    }
-    return false;
-}
-
 static int backward_impl(lbm_ctx *c, const void *dL_drho, const void *dL_du, int dtype, float *dL_ds,
                          double *dL_dtau, double *dL_duw, void *dL_dfield, double *dL_dforce) {
     if (!c) return fail(LBM_EINVAL, "null context");
@@ -282,7 +283,8 @@ static int backward_impl(lbm_ctx *c, const void *dL_drho, const void *dL_du, int
     if ((dL_drho || dL_du || dL_dfield) && dtype != LBM_F64 && dtype != LBM_F32)
         return fail(LBM_EINVAL, "dtype must be LBM_F64 or LBM_F32");
     if (!c->tape) return fail(LBM_ESTATE, "no tape recorded");
-    if (has_regularized_face(c)) return fail(LBM_EUNSUPPORTED, "the adjoint of regularized faces is not implemented");
+    if (has_regularized_face(c) && (c->batch || c->force_on || want_force))
+        return fail(LBM_EUNSUPPORTED, "the adjoint of regularized faces covers single domains without a body force");
     if (c->nlinks) return fail(LBM_EUNSUPPORTED, "the adjoint of interpolated bounce-back is not implemented");
     if (c->collision != LBM_BGK) return fail(LBM_EUNSUPPORTED, "the adjoint covers the BGK collision only");
     if (want_force && c->batch) return fail(LBM_EUNSUPPORTED, "body forces are not supported on batch contexts");

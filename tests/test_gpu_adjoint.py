@@ -19,6 +19,7 @@ from paper_2311_16080_amd import inputs, lbm
 pytestmark = pytest.mark.gpu
 
 W, P, ZV, ZP, OUT = lbm.WALL, lbm.PERIODIC, lbm.ZOUHE_VELOCITY, lbm.ZOUHE_PRESSURE, lbm.EQ_OUTFLOW
+RV, RP = lbm.REG_VELOCITY, lbm.REG_PRESSURE
 
 
 def _announce(name):
@@ -100,6 +101,33 @@ def zperiodic3d(storage, steps=14):
                 storage=storage, init_seed=63, solid=sol)
 
 
+def reg_channel2d(storage, steps=16):
+    """Regularized inlet and outlet, a moving wall, partial bounce-back."""
+    return Case(9, (40, 24), 0.6, [(RV, (0.04, 0.0)), (RP, (0, 0, 0), 1.0), (W,), (W, (0.03, 0.0)), (P,), (P,)],
+                steps=steps, storage=storage, init_seed=64,
+                s=inputs.smooth_solid_fraction(40, 24, seed=5, sigma=3, edge=4))
+
+
+def reg_zouhe_mixed2d(storage, steps=14):
+    """A regularized velocity inlet with a Zou-He pressure outlet."""
+    return Case(9, (40, 24), 0.8, [(RV, (0.03, 0.0)), (ZP, (0, 0, 0), 1.0), (W,), (W,), (P,), (P,)], steps=steps,
+                storage=storage, init_seed=65)
+
+
+def reg_zopen3d(storage, steps=10):
+    """Regularized faces across the contiguous axis (z), a moving wall."""
+    return Case(19, (8, 10, 70), 0.7, [(W,), (W,), (W,), (W, (0.02, 0, 0)), (RV, (0.0, 0.01, 0.03)),
+                                       (RP, (0, 0, 0), 1.0)], steps=steps, storage=storage, init_seed=66)
+
+
+def reg_prespres3d(storage, steps=8):
+    """D3Q27 pressure-driven channel with regularized faces and a solid cube."""
+    sol = np.zeros((20, 9, 66), np.uint8)
+    sol[8:12, 3:6, 20:40] = 1
+    return Case(27, (20, 9, 66), 0.6, [(RP, (0, 0, 0), 1.01), (RP, (0, 0, 0), 0.99), (W,), (W,), (P,), (P,)],
+                steps=steps, storage=storage, init_seed=67, solid=sol)
+
+
 ADJ_CASES = {
     "channel2d_pbb_f64_K5": (channel2d("f64"), 5, 0, 1e-10),
     "channel2d_pbb_f64_K24": (channel2d("f64"), 24, 0, 1e-10),
@@ -113,6 +141,13 @@ ADJ_CASES = {
     "channel2d_pbb_f64_K5_pull": (replace(channel2d("f64"), pattern="pull"), 5, 0, 1e-10),
     "cavity3d_f64_K6_oddstart_pull": (replace(cavity3d("f64"), pattern="pull"), 6, 3, 1e-10),
     "spheres3d_d3q27_f32_K4_pull": (replace(spheres3d("f32"), pattern="pull"), 4, 1, 1e-4),
+    # regularized faces: the closure's transpose (its momentum-flux projection)
+    "reg_channel2d_f64_K5": (reg_channel2d("f64"), 5, 0, 1e-10),
+    "reg_channel2d_f32_K5": (reg_channel2d("f32"), 5, 0, 1e-4),
+    "reg_zouhe_mixed2d_f64_K4_oddstart": (reg_zouhe_mixed2d("f64"), 4, 3, 1e-10),
+    "reg_zopen3d_f64_K4_oddstart": (reg_zopen3d("f64"), 4, 3, 1e-10),
+    "reg_zopen3d_f32_K5": (reg_zopen3d("f32"), 5, 0, 1e-4),
+    "reg_prespres3d_d3q27_f64_K3_pull": (replace(reg_prespres3d("f64"), pattern="pull"), 3, 1, 1e-10),
 }
 
 

@@ -2,7 +2,8 @@
 in test_oracle_regularized.py): inlet / outlet combinations on every lattice,
 open faces across the contiguous axis, mixed with Zou-He and outflow faces,
 solids, all storages, both AA parities; batch domains equal single-domain
-runs bitwise; the adjoint refuses them."""
+runs bitwise; the adjoint (compared with the oracle's in test_gpu_adjoint.py)
+refuses them on batches and with body forces."""
 import sys
 
 import numpy as np
@@ -95,11 +96,22 @@ def test_batch_with_regularized_faces_equals_single_domains():
         assert torch.equal(u_b[:, off[d]:off[d] + n].reshape((2,) + shapes[d]), u)
 
 
-def test_adjoint_refuses_regularized_faces():
+def test_adjoint_of_regularized_faces_refusals():
+    """The regularized closure's transpose runs on single domains without a
+    body force: a force (set, or asked for by backward_force) is refused."""
     import torch
-    _announce("regularized adjoint refused")
+    _announce("regularized adjoint refusals")
     case = Case(9, (24, 16), 0.7, [(RV, (0.03, 0.0)), (OUT, (0, 0, 0), 1.0), (W,), (W,), (P,), (P,)], storage="f32")
     sim = gpu_sim(case)
+    sim.tape_begin(2, 4)
+    sim.step(4)
+    sim.tape_end()
+    with pytest.raises(lbm.LbmError) as ei:
+        sim.backward_force(None, torch.zeros((2, 24, 16), device="cuda"))
+    assert ei.value.code == lbm.LBM_EUNSUPPORTED
+    ds, dtau, _ = sim.backward(None, torch.zeros((2, 24, 16), device="cuda"))
+    assert dtau[0] == 0.0
+    sim.set_force([1e-5, 0.0])
     sim.tape_begin(2, 4)
     sim.step(4)
     sim.tape_end()

@@ -4,7 +4,8 @@ The adjoint is the exact transpose of the derivative of the forward map, so it
 is pinned by linear algebra on the forward oracle alone:
 * a dense Jacobian built column by column with central differences on a tiny
   grid (walls, a moving wall, a solid cell, Zou-He, outflow, partial
-  bounce-back) equals the transpose the adjoint applies, row by row;
+  bounce-back, regularized velocity and pressure faces) equals the transpose
+  the adjoint applies, row by row;
 * the dot-product identity <w, J v> = <J^T w, v> on a larger grid;
 * finite-difference gradients of a velocity loss through several steps with
   respect to the solid fraction s, tau and the lid velocity.
@@ -12,7 +13,7 @@ is pinned by linear algebra on the forward oracle alone:
 import numpy as np
 import pytest
 
-from oracle import Face, OUTFLOW, Sim, WALL, ZOUHE_PRES, ZOUHE_VEL
+from oracle import Face, OUTFLOW, REG_PRES, REG_VEL, Sim, WALL, ZOUHE_PRES, ZOUHE_VEL
 
 
 def _scene(q, kind, rng):
@@ -36,6 +37,13 @@ def _scene(q, kind, rng):
         if q != 9:
             faces[4] = Face(WALL)
             faces[5] = Face(WALL)
+    elif kind == "regularized":
+        # regularized velocity inlet and pressure outlet; walls on y (perimeter
+        # cells), periodic z
+        faces[0] = Face(REG_VEL, (0.04, 0.01 if q != 9 else 0.0, 0))
+        faces[1] = Face(REG_PRES, (0, 0, 0), 0.995)
+        faces[2] = Face(WALL)
+        faces[3] = Face(WALL, (0.03, 0, 0))
     solid = np.zeros((nx, ny, nz), np.uint8)
     solid[nx // 2, ny // 2, nz // 2] = 1
     s = np.clip(0.3 + 0.2 * rng.standard_normal((nx, ny, nz)), 0, 1)
@@ -55,9 +63,9 @@ def _step(S, f):
     return g
 
 
-@pytest.mark.parametrize("kind", ["cavity", "channel", "pressure"])
+@pytest.mark.parametrize("kind", ["cavity", "channel", "pressure", "regularized"])
 def test_dense_jacobian_transpose_d2q9(oracle_mod, kind):
-    rng = np.random.default_rng({"cavity": 1, "channel": 2, "pressure": 3}[kind])
+    rng = np.random.default_rng({"cavity": 1, "channel": 2, "pressure": 3, "regularized": 4}[kind])
     S, f = _scene(9, kind, rng)
     fluid = ~S.solid.astype(bool)
     idx = [(x, y, z, i) for x, y, z in zip(*np.nonzero(fluid)) for i in range(9)]
@@ -81,7 +89,7 @@ def test_dense_jacobian_transpose_d2q9(oracle_mod, kind):
 
 
 @pytest.mark.parametrize("q", [9, 19, 27])
-@pytest.mark.parametrize("kind", ["cavity", "channel", "pressure"])
+@pytest.mark.parametrize("kind", ["cavity", "channel", "pressure", "regularized"])
 def test_dot_product_identity(oracle_mod, q, kind):
     rng = np.random.default_rng(7 + q)
     S, f = _scene(q, kind, rng)
@@ -115,10 +123,10 @@ def _loss(S, f0, nsteps, target):
     return np.sum(((u - target) * fluid[..., None]) ** 2)
 
 
-@pytest.mark.parametrize("q", [9, 19])
-def test_parameter_gradients_match_finite_differences(oracle_mod, q):
+@pytest.mark.parametrize("q,kind", [(9, "channel"), (19, "channel"), (9, "regularized"), (19, "regularized")])
+def test_parameter_gradients_match_finite_differences(oracle_mod, q, kind):
     rng = np.random.default_rng(11 + q)
-    S, f0 = _scene(q, "channel", rng)
+    S, f0 = _scene(q, kind, rng)
     nsteps = 6
     target = 0.02 * rng.standard_normal(S.shape + (3,))
     L, dlds, dtau, duw = _loss_and_grad(S, f0, nsteps, target)

@@ -17,7 +17,7 @@
 import numpy as np
 import pytest
 
-from oracle import Face, PERIODIC, REG_PRES, REG_VEL, Sim, WALL, ZOUHE_VEL, equilibrium, tables
+from oracle import Face, PERIODIC, REG_PRES, REG_VEL, Sim, WALL, equilibrium, tables
 
 
 def _normal(face):
@@ -133,11 +133,3 @@ def test_pressure_driven_poiseuille():
     ex = G / (2 * rho[x0, :, 0].mean() * nu) * y * (ny - y)
     err = np.max(np.abs(u[x0, :, 0, 0] - ex)) / ex.max()
     assert err < 2e-3
-
-
-def test_regularized_faces_have_no_oracle_adjoint():
-    S = Sim(q=9, nx=6, ny=5, nz=1, faces=[Face(REG_VEL, (0.03, 0, 0)), Face(ZOUHE_VEL, (0.03, 0, 0)), Face(WALL),
-                                          Face(WALL), Face(PERIODIC), Face(PERIODIC)])
-    f = S.equilibrium_state()
-    with pytest.raises(NotImplementedError):
-        S.adjoint_step(f, np.zeros_like(f))
