@@ -283,9 +283,26 @@ __device__ __forceinline__ Nb classify_src(const Params<CT> &p, int X, int Y, in
 }
 
 // ---- equilibrium in deviation form: feq_i - w_i rho0 -------------------------
+// c_I . u with the components of c_I (0 or +-1) resolved at compile time: the
+// same value, rounded the same way, as the full product sum, without the
+// multiplications by zero the compiler has to keep in IEEE arithmetic.
+template <class L, int I, class CT>
+__device__ __forceinline__ CT cdot(CT ux, CT uy, CT uz) {
+    constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
+    CT v = (cx > 0) ? ux : ((cx < 0) ? -ux : (CT)0);
+    if constexpr (cx == 0) {
+        if constexpr (cy != 0) v = (cy > 0) ? uy : -uy;
+        if constexpr (cz != 0) v = (cy != 0) ? ((cz > 0) ? v + uz : v - uz) : ((cz > 0) ? uz : -uz);
+    } else {
+        if constexpr (cy != 0) v = (cy > 0) ? v + uy : v - uy;
+        if constexpr (cz != 0) v = (cz > 0) ? v + uz : v - uz;
+    }
+    return v;
+}
+
 template <class L, int I, class CT>
 __device__ __forceinline__ CT heq(CT drho, CT rho, CT ux, CT uy, CT uz, CT usq15) {
-    const CT cu = (CT)3 * ((CT)L::c[I][0] * ux + (CT)L::c[I][1] * uy + (CT)L::c[I][2] * uz);
+    const CT cu = (CT)3 * cdot<L, I>(ux, uy, uz);
     return (CT)weight<L>(I) * (drho + rho * (cu + (CT)0.5 * cu * cu - usq15));
 }
 
@@ -527,8 +544,24 @@ template <class L, class CT>
 __device__ __forceinline__ void kbc_relax(const CT *h, CT *hp, const Params<CT> &p, CT drho, CT rho, CT ux, CT uy,
                                           CT uz, CT usq15) {
     constexpr int Q = L::Q;
+    // equilibria of opposite directions together: with cu = 3 c_i.u,
+    // heq_i = sym + anti and heq_opp(i) = sym - anti, sym = w_i (drho + rho (cu^2/2 - 1.5 u^2)),
+    // anti = w_i rho cu
     CT e[Q];
-    unroll<Q>([&](auto I) { e[I] = heq<L, I>(drho, rho, ux, uy, uz, usq15); });
+    const CT tx = (CT)3 * ux, ty = (CT)3 * uy, tz = (CT)3 * uz;
+    unroll<Q>([&](auto I) {
+        constexpr int O = opp<L>(I);
+        if constexpr (I == 0) {
+            e[0] = (CT)weight<L>(0) * (drho - rho * usq15);
+        } else if constexpr (I < O) {
+            const CT cu = cdot<L, I>(tx, ty, tz);
+            const CT wr = (CT)weight<L>(I) * rho;
+            const CT sym = wr * ((CT)0.5 * cu * cu - usq15) + (CT)weight<L>(I) * drho;
+            const CT anti = wr * cu;
+            e[I] = sym + anti;
+            e[O] = sym - anti;
+        }
+    });
     CT P00 = 0, P11 = 0, P22 = 0, P01 = 0, P02 = 0, P12 = 0;
     unroll<Q>([&](auto I) {
         constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
@@ -536,47 +569,58 @@ __device__ __forceinline__ void kbc_relax(const CT *h, CT *hp, const Params<CT> 
         if constexpr (cx != 0) P00 += n;
         if constexpr (cy != 0) P11 += n;
         if constexpr (cz != 0) P22 += n;
-        if constexpr (cx * cy != 0) P01 += (CT)(cx * cy) * n;
-        if constexpr (cx * cz != 0) P02 += (CT)(cx * cz) * n;
-        if constexpr (cy * cz != 0) P12 += (CT)(cy * cz) * n;
+        if constexpr (cx * cy != 0) P01 += (cx * cy > 0) ? n : -n;
+        if constexpr (cx * cz != 0) P02 += (cx * cz > 0) ? n : -n;
+        if constexpr (cy * cz != 0) P12 += (cy * cz > 0) ? n : -n;
     });
     const CT trD = (P00 + P11 + P22) * (CT)(1.0 / L::D);
-    // shear part of direction I (recomputed where needed: a handful of operations
-    // instead of Q more live registers)
+    // shear part: the deviatoric flux on the axis directions ((P_aa - tr P / D) / 2)
+    // and the face diagonals (c_a c_b P_ab / 4); zero on rest and corner directions
+    const CT sa0 = (CT)0.5 * (P00 - trD), sa1 = (CT)0.5 * (P11 - trD), sa2 = (CT)0.5 * (P22 - trD);
+    const CT sb01 = (CT)0.25 * P01, sb02 = (CT)0.25 * P02, sb12 = (CT)0.25 * P12;
+    auto has_shear = [](auto I) constexpr {
+        constexpr int nzc = (L::c[I][0] != 0) + (L::c[I][1] != 0) + (L::c[I][2] != 0);
+        return nzc == 1 || nzc == 2;
+    };
     auto shear = [&](auto I) -> CT {
         constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
         constexpr int nzc = (cx != 0) + (cy != 0) + (cz != 0);
         if constexpr (nzc == 1) {
-            const CT Paa = (cx != 0) ? P00 : ((cy != 0) ? P11 : P22);
-            return (CT)0.5 * (Paa - trD);
-        } else if constexpr (nzc == 2) {
-            const CT Pab = (cz == 0) ? P01 : ((cy == 0) ? P02 : P12);
-            constexpr int sgn = (cz == 0) ? cx * cy : ((cy == 0) ? cx * cz : cy * cz);
-            return (CT)(0.25 * sgn) * Pab;
+            return (cx != 0) ? sa0 : ((cy != 0) ? sa1 : sa2);
         } else {
-            return (CT)0;
+            constexpr int sgn = (cz == 0) ? cx * cy : ((cy == 0) ? cx * cz : cy * cz);
+            const CT b = (cz == 0) ? sb01 : ((cy == 0) ? sb02 : sb12);
+            return (sgn > 0) ? b : -b;
         }
     };
+    // entropic scalar products <s|dh> and <dh|dh> with weights 1 / feq_i
     CT sh = 0, hh = 0;
     unroll<Q>([&](auto I) {
-        const CT v = shear(I);
-        const CT dh = (h[I] - e[I]) - v;
-        // entropic weights 1 / feq_i: the hardware reciprocal in FP32 (the
-        // weights only scale the two scalar products)
+        const CT n = h[I] - e[I];
+        // the hardware reciprocal in FP32 (the weights only scale the two products)
         const CT feq = e[I] + (CT)weight<L>(I) * p.rho0;
         CT inv_feq;
         if constexpr (sizeof(CT) == 4) inv_feq = __builtin_amdgcn_rcpf(feq);
         else inv_feq = (CT)1 / feq;
-        sh += v * dh * inv_feq;
-        hh += dh * dh * inv_feq;
+        if constexpr (has_shear(I)) {
+            const CT v = shear(I);
+            const CT dh = n - v;
+            const CT wd = dh * inv_feq;
+            sh += wd * v;
+            hh += wd * dh;
+        } else {
+            hh += n * inv_feq * n;
+        }
     });
     const CT beta = (CT)0.5 * p.omega;
     const CT ib = (CT)1 / beta;
     const CT gamma = (hh > (CT)0) ? ib - ((CT)2 - ib) * sh / hh : (CT)2;
+    // hp = h - beta (2 s + gamma dh) = h - beta gamma n - beta (2 - gamma) s
+    const CT bg = beta * gamma, bs = beta * ((CT)2 - gamma);
     unroll<Q>([&](auto I) {
-        const CT v = shear(I);
-        const CT dh = (h[I] - e[I]) - v;
-        hp[I] = h[I] - beta * ((CT)2 * v + gamma * dh);
+        const CT t = h[I] - bg * (h[I] - e[I]);
+        if constexpr (has_shear(I)) hp[I] = t - bs * shear(I);
+        else hp[I] = t;
     });
 }
 

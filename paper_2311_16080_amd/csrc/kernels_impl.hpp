@@ -273,16 +273,18 @@ __device__ __forceinline__ void step_cell(const Params<typename Store<ST>::CT> &
 }
 
 // Waves per SIMD the register allocation leaves room for: the compiler's
-// choice, except the local step of the walls-only KBC variant on D3Q27, held
-// at 3 (<= 168 VGPRs, 3 spilled): measured on the 256^3 cavity 774 -> 636 us.
-// Its gathering steps spill 20-29 registers at 3 and run slower (901 -> 1067 us).
-template <class L, int MODE, int XF>
+// choice, except the walls-only KBC variant on D3Q27 in FP32, held at 3
+// (<= 168 VGPRs; its steps need 151-167 without spilling).  At 2 waves its
+// local step ran 774 us on the 256^3 cavity against 636 us at 3; at 4 waves
+// (128 VGPRs) every step spills 30-44 registers.  FP64 and the 2-byte storages
+// would spill at 3.
+template <class L, class ST, int MODE, int XF>
 struct StepWaves {
-    static constexpr int value = (L::Q == 27 && MODE == 0 && (XF & 24) == 24) ? 3 : 1;
+    static constexpr int value = (L::Q == 27 && (XF & 24) == 24 && std::is_same<ST, float>::value) ? 3 : 1;
 };
 
 template <class L, class ST, int MODE, int XF, int NT>
-__global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(StepWaves<L, MODE, XF>::value)))
+__global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(StepWaves<L, ST, MODE, XF>::value)))
 k_step(const Params<typename Store<ST>::CT> p, ST *__restrict__ A, ST *__restrict__ B) {
     int X, Y, Z;
     if (!block_cell<sizeof(ST) == 2>(p, X, Y, Z)) return;
