@@ -428,19 +428,21 @@ __device__ __forceinline__ void block_add(double v, double *acc, int64_t row) {
 // step is latency bound: measured on D3Q19 FP32 256^3, 4 waves (<= 128 VGPRs)
 // run 15% faster than the compiler's 3, 5 waves spill.
 // FP64 arithmetic keeps the compiler's choice.
-// With the body force (more live values) D3Q19 FP32 asks for 3 waves:
-// at 4 it spills.
-template <class L, class ST, bool FRC = false>
+// With the body force or regularized faces (more live values) D3Q19 FP32
+// asks for 3 waves and D3Q27 for 2: one more spills.
+template <class L, class ST, bool FRC = false, bool REG = false>
 struct AdjWaves {
     static constexpr bool f64 = sizeof(typename Store<ST>::CT) == 8;
-    static constexpr int value = f64 ? 1 : ((L::Q == 19) ? (FRC ? 3 : 4) : ((L::Q == 27) ? 3 : 1));
+    static constexpr int value = f64 ? 1
+                                     : ((L::Q == 19) ? ((FRC || REG) ? 3 : 4)
+                                                     : ((L::Q == 27) ? ((FRC || REG) ? 2 : 3) : 1));
 };
 #ifdef LBM_ADJ_WAVES
 #define LBM_ADJ_ATTR __attribute__((amdgpu_waves_per_eu(LBM_ADJ_WAVES)))
 #define LBM_ADJ_ATTR_F LBM_ADJ_ATTR
 #else
 #define LBM_ADJ_ATTR __attribute__((amdgpu_waves_per_eu(AdjWaves<L, ST>::value)))
-#define LBM_ADJ_ATTR_F __attribute__((amdgpu_waves_per_eu(AdjWaves<L, ST, FRC>::value)))
+#define LBM_ADJ_ATTR_F __attribute__((amdgpu_waves_per_eu(AdjWaves<L, ST, FRC, REG>::value)))
 #endif
 
 template <class L, class ST, bool HAS_S, bool FRC, bool REG>
