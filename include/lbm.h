@@ -404,7 +404,9 @@ int64_t lbm_tape_id(const lbm_ctx *ctx);
  *              (zero if no s field is set);
  *   dL_dtau  : host double[n_domains], gradient w.r.t. each domain's tau;
  *   dL_duw   : host double[n_domains * 6 * 3], gradient w.r.t. each face's
- *              wall velocity (LBM_WALL faces only; other entries 0).
+ *              wall velocity (moving LBM_WALL faces only: a wall at rest
+ *              takes no moving-wall term, and its entries are 0, as are
+ *              those of other faces).
  * The forward state is left unchanged.  Synchronises.  LBM_ESTATE without a
  * tape, if the state moved since the tape ended, or if lbm_set_params,
  * lbm_set_solid, lbm_set_solid_fraction, lbm_set_force or lbm_set_collision

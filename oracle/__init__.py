@@ -290,8 +290,6 @@ class Sim:
                                     _dp(np.ascontiguousarray(a_next)), _dp(a_out),
                                     dlds.ctypes.data if self.s is not None else None,
                                     _dp(dtau), _dp(duw), dldf.ctypes.data)
-        if rc == -2:
-            raise NotImplementedError("the oracle adjoint covers the BGK collision only")
         if rc != 0:
             raise MemoryError("oracle allocation failed")
         out = (a_out, dlds.reshape(self.shape), float(dtau[0]), duw.reshape(6, 3))

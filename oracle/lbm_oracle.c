@@ -26,6 +26,7 @@
  * the 3-D Zou-He closure, the outflow velocity, the partial bounce-back
  * variant) are listed in the design notes; each is restated at its use below.
  */
+#include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -227,6 +228,78 @@ static void collide_f(const orc_sim *S, const double *f, double *fstar, double *
 static void collide(const orc_sim *S, const double *f, double *fstar, double *rho, double u[3])
 {
     collide_f(S, f, fstar, rho, u, NULL);
+}
+
+/* The KBC collision of one cell, moments and equilibrium included, in complex
+ * arithmetic: the same operations as moments, feq_i and kbc_collide above,
+ * for the complex-step derivative of the adjoint (Squire & Trapp 1998): for a
+ * map g that is real-analytic at x, Im g(x + i h e_j) / h = dg/dx_j + O(h^2)
+ * with no difference of nearby values, so h = 1e-30 gives the derivative to
+ * rounding.  gamma's branch is taken on the real part. */
+static void kbc_collide_cx(int q, const double complex *f, double complex tau, double complex *fstar)
+{
+    const double cs2 = 1.0 / 3.0;
+    double complex rho = 0.0, j[3] = {0.0, 0.0, 0.0}, u[3];
+    for (int i = 0; i < q; ++i) {
+        const int *c = cvec(q, i);
+        rho += f[i];
+        for (int a = 0; a < 3; ++a) j[a] += c[a] * f[i];
+    }
+    for (int a = 0; a < 3; ++a) u[a] = j[a] / rho;
+    double complex feq[27], fneq[27], ds[27], dh[27];
+    const double complex uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int i = 0; i < q; ++i) {
+        const int *c = cvec(q, i);
+        double complex cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+        feq[i] = weight(q, i) * rho * (1.0 + cu / cs2 + cu * cu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+        fneq[i] = f[i] - feq[i];
+    }
+    double complex P[3][3] = {{0.0}};
+    for (int i = 0; i < q; ++i) {
+        const int *c = cvec(q, i);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) P[a][b] += c[a] * c[b] * fneq[i];
+    }
+    for (int i = 0; i < q; ++i) {
+        const int *c = cvec(q, i);
+        int nz = (c[0] != 0) + (c[1] != 0) + (c[2] != 0);
+        double complex v = 0.0;
+        if (nz == 1) {
+            int a = (c[0] != 0) ? 0 : ((c[1] != 0) ? 1 : 2);
+            if (q == 9) v = (a == 0 ? 1.0 : -1.0) * (P[0][0] - P[1][1]) / 4.0;
+            else v = (2.0 * P[a][a] - P[(a + 1) % 3][(a + 1) % 3] - P[(a + 2) % 3][(a + 2) % 3]) / 6.0;
+        } else if (nz == 2) {
+            int a = (c[0] == 0) ? 1 : 0;
+            int b = (c[2] != 0) ? 2 : 1;
+            v = c[a] * c[b] * P[a][b] / 4.0;
+        }
+        ds[i] = v;
+        dh[i] = fneq[i] - v;
+    }
+    double complex beta = 0.5 / tau, sh = 0.0, hh = 0.0;
+    for (int i = 0; i < q; ++i) {
+        sh += ds[i] * dh[i] / feq[i];
+        hh += dh[i] * dh[i] / feq[i];
+    }
+    double complex gamma = (creal(hh) > 0.0) ? 1.0 / beta - (2.0 - 1.0 / beta) * sh / hh : 2.0;
+    for (int i = 0; i < q; ++i) fstar[i] = f[i] - beta * (2.0 * ds[i] + gamma * dh[i]);
+}
+
+/* d f*_i / d f_j (jac) and d f*_i / d tau (dtau) of the KBC collision at f,
+ * by the complex step. */
+static void kbc_jacobian(int q, const double *f, double tau, double jac[27][27], double dtau[27])
+{
+    const double hstep = 1e-30;
+    double complex fc[27], out[27];
+    for (int j = 0; j < q; ++j) {
+        for (int i = 0; i < q; ++i) fc[i] = f[i];
+        fc[j] += hstep * I;
+        kbc_collide_cx(q, fc, tau, out);
+        for (int i = 0; i < q; ++i) jac[i][j] = cimag(out[i]) / hstep;
+    }
+    for (int i = 0; i < q; ++i) fc[i] = f[i];
+    kbc_collide_cx(q, fc, tau + hstep * I, out);
+    for (int i = 0; i < q; ++i) dtau[i] = cimag(out[i]) / hstep;
 }
 
 void orc_collide_cell(const orc_sim *S, const double *f, double *fstar)
@@ -690,7 +763,9 @@ void orc_sums(const orc_sim *S, const double *f, double *sums)
  *       was read from (fluid source, bounced own slot, or the velocity of the
  *       cell for equilibrium fills);
  *   (1) collision + mix: per cell, the explicit q x q Jacobian of
- *       f°(f) = (1-s)[f - (f - feq(rho(f), u(f)))/tau] + s f_opp.
+ *       f°(f) = (1-s)[f - (f - feq(rho(f), u(f)))/tau] + s f_opp
+ *       (KBC: (1-s) f*(f) + s f_opp, f* the KBC collision, whose Jacobian
+ *       and tau derivative are taken by the complex step).
  * work: N*q (adjoint of the gathered values), N*q (adjoint of f°), N*3
  * (adjoint of u(x,t)).
  * ------------------------------------------------------------------------- */
@@ -735,7 +810,6 @@ int orc_adjoint_step(const orc_sim *S, const double *f, const double *a_next, do
 {
     const int q = S->q;
     const long N = (long)S->nx * S->ny * S->nz;
-    if (S->collision != 0) return -2;   /* the adjoint covers BGK only */
     double *ag = (double *)calloc((size_t)N * q, sizeof(double));
     double *apost = (double *)calloc((size_t)N * q, sizeof(double));
     double *au = (double *)calloc((size_t)N * 3, sizeof(double));
@@ -856,10 +930,13 @@ int orc_adjoint_step(const orc_sim *S, const double *f, const double *a_next, do
         double rho, u[3];
         moments(q, fk, &rho, u);
         double s = S->s ? S->s[k] : 0.0;
-        /* J_ij = d f°_i / d f_j */
+        /* J_ij = d f°_i / d f_j; KBC: the collision's Jacobian jk and its
+         * tau derivative dk by the complex step */
         double J[27][27];
-        double dfeq[27][27], dfeqF[27][27];
+        double dfeq[27][27], dfeqF[27][27], jk[27][27], dk[27];
+        const int kbc = S->collision == 1;
         feq_jacobian(q, rho, u, dfeq);
+        if (kbc) kbc_jacobian(q, fk, S->tau, jk, dk);
         /* body force (exact-difference method): f* gains feq(rho, u') - feq(rho, u),
          * u' = (j + F) / rho, whose Jacobian is that of feq at u' minus that at u */
         const double *F = S->edm ? S->edm + (size_t)k * 3 : NULL;
@@ -870,7 +947,7 @@ int orc_adjoint_step(const orc_sim *S, const double *f, const double *a_next, do
         }
         for (int i = 0; i < q; ++i)
             for (int j = 0; j < q; ++j)
-                J[i][j] = (1.0 - s) * (((i == j) ? 1.0 : 0.0) * (1.0 - omega) + omega * dfeq[i][j]
+                J[i][j] = (1.0 - s) * ((kbc ? jk[i][j] : ((i == j) ? 1.0 : 0.0) * (1.0 - omega) + omega * dfeq[i][j])
                                        + (F ? dfeqF[i][j] - dfeq[i][j] : 0.0))
                           + s * ((j == opposite(q, i)) ? 1.0 : 0.0);
         double *ao = a_out + (size_t)k * q;
@@ -884,8 +961,13 @@ int orc_adjoint_step(const orc_sim *S, const double *f, const double *a_next, do
         }
         /* parameters */
         double fstar[27];
+        if (kbc) {
+            double feq[27];
+            for (int i = 0; i < q; ++i) feq[i] = feq_i(q, i, rho, u);
+            kbc_collide(q, fk, feq, S->tau, fstar);
+        }
         for (int i = 0; i < q; ++i) {
-            fstar[i] = fk[i] - omega * (fk[i] - feq_i(q, i, rho, u));
+            if (!kbc) fstar[i] = fk[i] - omega * (fk[i] - feq_i(q, i, rho, u));
             if (F) fstar[i] += feq_i(q, i, rho, up) - feq_i(q, i, rho, u);
         }
         /* d f°_i / d F = (1-s) d feq_i(rho, u') / d u' / rho */
@@ -902,8 +984,9 @@ int orc_adjoint_step(const orc_sim *S, const double *f, const double *a_next, do
             for (int i = 0; i < q; ++i) g += ap[i] * (fk[opposite(q, i)] - fstar[i]);
             dLds[k] += g;
         }
-        /* d f°_i / d tau = (1-s) (f_i - feq_i) / tau^2 */
-        for (int i = 0; i < q; ++i) dtau += ap[i] * (1.0 - s) * (fk[i] - feq_i(q, i, rho, u)) / (S->tau * S->tau);
+        /* d f°_i / d tau = (1-s) (f_i - feq_i) / tau^2 (BGK), (1-s) dk_i (KBC) */
+        for (int i = 0; i < q; ++i)
+            dtau += ap[i] * (1.0 - s) * (kbc ? dk[i] : (fk[i] - feq_i(q, i, rho, u)) / (S->tau * S->tau));
     }
     if (dLdtau) *dLdtau += dtau;
     if (dLduw) for (int m = 0; m < 18; ++m) dLduw[m] += duw[m];

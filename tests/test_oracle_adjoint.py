@@ -4,8 +4,8 @@ The adjoint is the exact transpose of the derivative of the forward map, so it
 is pinned by linear algebra on the forward oracle alone:
 * a dense Jacobian built column by column with central differences on a tiny
   grid (walls, a moving wall, a solid cell, Zou-He, outflow, partial
-  bounce-back, regularized velocity and pressure faces) equals the transpose
-  the adjoint applies, row by row;
+  bounce-back, regularized velocity and pressure faces, the KBC collision)
+  equals the transpose the adjoint applies, row by row;
 * the dot-product identity <w, J v> = <J^T w, v> on a larger grid;
 * finite-difference gradients of a velocity loss through several steps with
   respect to the solid fraction s, tau and the lid velocity.
@@ -13,10 +13,16 @@ is pinned by linear algebra on the forward oracle alone:
 import numpy as np
 import pytest
 
-from oracle import Face, OUTFLOW, REG_PRES, REG_VEL, Sim, WALL, ZOUHE_PRES, ZOUHE_VEL
+from oracle import KBC, Face, OUTFLOW, REG_PRES, REG_VEL, Sim, WALL, ZOUHE_PRES, ZOUHE_VEL
+
+KINDS = ["cavity", "channel", "pressure", "regularized", "kbc_cavity", "kbc_channel"]
 
 
 def _scene(q, kind, rng):
+    collision = 0
+    if kind.startswith("kbc_"):
+        # the KBC collision (its Jacobian is the oracle's complex step)
+        collision, kind = KBC, kind[4:]
     if q == 9:
         nx, ny, nz = 6, 5, 1
     else:
@@ -47,7 +53,7 @@ def _scene(q, kind, rng):
     solid = np.zeros((nx, ny, nz), np.uint8)
     solid[nx // 2, ny // 2, nz // 2] = 1
     s = np.clip(0.3 + 0.2 * rng.standard_normal((nx, ny, nz)), 0, 1)
-    S = Sim(q=q, nx=nx, ny=ny, nz=nz, tau=0.67, faces=faces, solid=solid, s=s)
+    S = Sim(q=q, nx=nx, ny=ny, nz=nz, tau=0.67, faces=faces, solid=solid, s=s, collision=collision)
     u = 0.03 * rng.standard_normal((nx, ny, nz, 3))
     if q == 9:
         u[..., 2] = 0
@@ -57,19 +63,26 @@ def _scene(q, kind, rng):
     return S, f
 
 
+def _fd_step(kind):
+    # KBC's gamma is a ratio of two entropic products of the small non-shear
+    # part, so its third derivatives are large: central differences need a
+    # smaller step there (truncation 6e-8 at 1e-6, 9e-10 at 1e-7)
+    return 1e-7 if kind.startswith("kbc_") else 1e-6
+
+
 def _step(S, f):
     g = f.copy()
     S.run(g, 1)
     return g
 
 
-@pytest.mark.parametrize("kind", ["cavity", "channel", "pressure", "regularized"])
+@pytest.mark.parametrize("kind", KINDS)
 def test_dense_jacobian_transpose_d2q9(oracle_mod, kind):
-    rng = np.random.default_rng({"cavity": 1, "channel": 2, "pressure": 3, "regularized": 4}[kind])
+    rng = np.random.default_rng(1 + KINDS.index(kind))
     S, f = _scene(9, kind, rng)
     fluid = ~S.solid.astype(bool)
     idx = [(x, y, z, i) for x, y, z in zip(*np.nonzero(fluid)) for i in range(9)]
-    eps = 1e-6
+    eps = _fd_step(kind)
     J = np.zeros((len(idx), len(idx)))
     for col, k in enumerate(idx):
         fp, fm = f.copy(), f.copy()
@@ -89,14 +102,16 @@ def test_dense_jacobian_transpose_d2q9(oracle_mod, kind):
 
 
 @pytest.mark.parametrize("q", [9, 19, 27])
-@pytest.mark.parametrize("kind", ["cavity", "channel", "pressure", "regularized"])
+@pytest.mark.parametrize("kind", KINDS)
 def test_dot_product_identity(oracle_mod, q, kind):
+    if q == 19 and kind.startswith("kbc_"):
+        pytest.skip("KBC runs on D2Q9 and D3Q27")
     rng = np.random.default_rng(7 + q)
     S, f = _scene(q, kind, rng)
     fluid = ~S.solid.astype(bool)
     v = rng.standard_normal(f.shape) * fluid[..., None]
     w = rng.standard_normal(f.shape) * fluid[..., None]
-    eps = 1e-6
+    eps = _fd_step(kind)
     Jv = (_step(S, f + eps * v) - _step(S, f - eps * v)) / (2 * eps)
     JTw, _, _, _ = S.adjoint_step(f, w)
     lhs = np.sum(w * Jv)
@@ -123,7 +138,8 @@ def _loss(S, f0, nsteps, target):
     return np.sum(((u - target) * fluid[..., None]) ** 2)
 
 
-@pytest.mark.parametrize("q,kind", [(9, "channel"), (19, "channel"), (9, "regularized"), (19, "regularized")])
+@pytest.mark.parametrize("q,kind", [(9, "channel"), (19, "channel"), (9, "regularized"), (19, "regularized"),
+                                    (9, "kbc_channel"), (27, "kbc_channel")])
 def test_parameter_gradients_match_finite_differences(oracle_mod, q, kind):
     rng = np.random.default_rng(11 + q)
     S, f0 = _scene(q, kind, rng)
