@@ -362,8 +362,9 @@ int lbm_set_force(lbm_ctx *ctx, const double *force, const void *field, double e
  * gamma = 1/beta - (2 - 1/beta) <ds|dh> / <dh|dh> with <x|y> = sum x_i y_i / feq_i
  * (the minimiser of the quadratic entropy; BGK when dh = 0 or tau = 1).
  * LBM_EINVAL for an unknown model; LBM_EUNSUPPORTED for KBC on D3Q19, on batch
- * contexts or with a partial bounce-back field; lbm_backward returns
- * LBM_EUNSUPPORTED while KBC is set.  Drops a captured graph.
+ * contexts or with a partial bounce-back field; lbm_backward differentiates
+ * KBC steps (gamma's dependence on the state included) except with a body
+ * force or regularized faces.  Drops a captured graph.
  */
 int lbm_set_collision(lbm_ctx *ctx, int model);
 
@@ -412,9 +413,9 @@ int64_t lbm_tape_id(const lbm_ctx *ctx);
  * lbm_set_solid, lbm_set_solid_fraction, lbm_set_force or lbm_set_collision
  * was called after the tape began (the recorded steps no longer match the
  * parameters the adjoint would use); LBM_EUNSUPPORTED with curved links,
- * with the KBC collision, and with regularized faces on a batch context or
- * with a body force (the regularized closure's transpose covers single
- * domains without one).
+ * and with regularized faces or the KBC collision on a batch context or with
+ * a body force (their transposes cover single domains without one; KBC also
+ * not with regularized faces).
  */
 int lbm_backward(lbm_ctx *ctx, const void *dL_drho, const void *dL_du, int dtype,
                  float *dL_ds, double *dL_dtau, double *dL_duw);

@@ -209,6 +209,155 @@ __device__ __forceinline__ void regularize_transpose(CT *a, const Params<CT> &p,
     });
 }
 
+// Shear part of direction I in the KBC collision (core.hpp, kbc_relax): the
+// deviatoric flux (P_aa - tr P / D) / 2 on the axis directions, c_a c_b P_ab / 4
+// on the face diagonals, zero on rest and corners.  sa[a] = (P_aa - tr P / D) / 2,
+// sb = {P_xy, P_xz, P_yz} / 4.
+template <class L, int I>
+__device__ __forceinline__ constexpr bool kbc_has_shear() {
+    constexpr int nzc = (L::c[I][0] != 0) + (L::c[I][1] != 0) + (L::c[I][2] != 0);
+    return nzc == 1 || nzc == 2;
+}
+
+template <class L, int I, class CT>
+__device__ __forceinline__ CT kbc_shear_of(const CT *sa, const CT *sb) {
+    constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
+    constexpr int nzc = (cx != 0) + (cy != 0) + (cz != 0);
+    if constexpr (nzc == 1) {
+        return sa[(cx != 0) ? 0 : ((cy != 0) ? 1 : 2)];
+    } else if constexpr (nzc == 2) {
+        constexpr int sgn = (cz == 0) ? cx * cy : ((cy == 0) ? cx * cz : cy * cz);
+        const CT v = sb[(cz == 0) ? 0 : ((cy == 0) ? 1 : 2)];
+        return (sgn > 0) ? v : -v;
+    } else {
+        return (CT)0;
+    }
+}
+
+// Transpose of the KBC collision at one cell.  Forward, in deviation variables
+// (e_i = heq_i(rho(h), u(h)), n = h - e, P = sum c c n, s = shear(P),
+// dh = n - s, feq = e + w rho0, sh = <s|dh>, hh = <dh|dh> with weights
+// 1 / feq, gamma = 1/beta - (2 - 1/beta) sh / hh (2 when hh = 0)):
+//   f*_i = h_i - beta (2 s_i + gamma dh_i).
+// Given lam_i = dL/df*_i, writes dL/dh_j to a[] by reverse accumulation through
+// gamma, sh, hh (and the feq in their weights), s(P), n and the equilibrium's
+// rho and u; returns sum_i lam_i df*_i/dtau * tau^2 =
+// sum lam s + (sum lam dh) (gamma - (1 + sh / hh) / beta) / 2.
+template <class L, class CT>
+__device__ __forceinline__ CT kbc_transpose(const CT *h, const CT *lam, CT *a, const Params<CT> &p, CT drho, CT rho,
+                                            CT inv, CT ux, CT uy, CT uz, CT usq15) {
+    constexpr int Q = L::Q;
+    CT e[Q];
+    unroll<Q>([&](auto I) { e[I] = heq<L, I>(drho, rho, ux, uy, uz, usq15); });
+    CT P00 = 0, P11 = 0, P22 = 0, P01 = 0, P02 = 0, P12 = 0;
+    unroll<Q>([&](auto I) {
+        constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
+        const CT n = h[I] - e[I];
+        if constexpr (cx != 0) P00 += n;
+        if constexpr (cy != 0) P11 += n;
+        if constexpr (cz != 0) P22 += n;
+        if constexpr (cx * cy != 0) P01 += (cx * cy > 0) ? n : -n;
+        if constexpr (cx * cz != 0) P02 += (cx * cz > 0) ? n : -n;
+        if constexpr (cy * cz != 0) P12 += (cy * cz > 0) ? n : -n;
+    });
+    const CT trD = (P00 + P11 + P22) * (CT)(1.0 / L::D);
+    const CT sa[3] = {(CT)0.5 * (P00 - trD), (CT)0.5 * (P11 - trD), (CT)0.5 * (P22 - trD)};
+    const CT sb[3] = {(CT)0.25 * P01, (CT)0.25 * P02, (CT)0.25 * P12};
+    auto inv_feq = [&](auto I) -> CT {
+        const CT feq = e[I] + (CT)weight<L>(I) * p.rho0;
+        if constexpr (sizeof(CT) == 4) return __builtin_amdgcn_rcpf(feq);   // as the forward step
+        else return (CT)1 / feq;
+    };
+    CT sh = 0, hh = 0, A = 0, LS = 0;
+    unroll<Q>([&](auto I) {
+        const CT v = kbc_shear_of<L, I>(sa, sb);
+        const CT dh = (h[I] - e[I]) - v;
+        const CT wd = dh * inv_feq(I);
+        sh += wd * v;
+        hh += wd * dh;
+        A += lam[I] * dh;
+        LS += lam[I] * v;
+    });
+    const CT beta = (CT)0.5 * p.omega;
+    const CT ib = (CT)1 / beta;
+    const bool pos = hh > (CT)0;
+    const CT r = pos ? sh / hh : (CT)0;
+    const CT gamma = pos ? ib - ((CT)2 - ib) * r : (CT)2;
+    const CT gt = LS + (CT)0.5 * A * (gamma - (pos ? ((CT)1 + r) * ib : (CT)0));
+    // adjoints of sh and hh through gamma (zero when gamma is the constant 2)
+    const CT bsh = pos ? beta * A * ((CT)2 - ib) / hh : (CT)0;
+    const CT bhh = -bsh * r;
+    const CT bg = -beta * gamma;
+    // pass 1: adjoint of P through the shear parts
+    CT bP00 = 0, bP11 = 0, bP22 = 0, bP01 = 0, bP02 = 0, bP12 = 0, btr = 0;
+    unroll<Q>([&](auto I) {
+        if constexpr (kbc_has_shear<L, I>()) {
+            constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
+            constexpr int nzc = (cx != 0) + (cy != 0) + (cz != 0);
+            const CT v = kbc_shear_of<L, I>(sa, sb);
+            const CT dh = (h[I] - e[I]) - v;
+            const CT iv = inv_feq(I);
+            const CT bdh = bg * lam[I] + bsh * v * iv + (CT)2 * bhh * dh * iv;
+            const CT bs = (CT)(-2) * beta * lam[I] + bsh * dh * iv - bdh;
+            if constexpr (nzc == 1) {
+                if constexpr (cx != 0) bP00 += (CT)0.5 * bs;
+                if constexpr (cy != 0) bP11 += (CT)0.5 * bs;
+                if constexpr (cz != 0) bP22 += (CT)0.5 * bs;
+                btr -= (CT)0.5 * bs;
+            } else {
+                constexpr int sgn = (cz == 0) ? cx * cy : ((cy == 0) ? cx * cz : cy * cz);
+                const CT t = (sgn > 0) ? (CT)0.25 * bs : (CT)(-0.25) * bs;
+                if constexpr (cz == 0) bP01 += t;
+                else if constexpr (cy == 0) bP02 += t;
+                else bP12 += t;
+            }
+        }
+    });
+    btr *= (CT)(1.0 / L::D);
+    bP00 += btr;
+    bP11 += btr;
+    bP22 += btr;
+    // pass 2: adjoint of n and of the equilibrium; the direct terms of h
+    CT Ae = 0, Vx = 0, Vy = 0, Vz = 0;
+    const CT uu = ux * ux + uy * uy + uz * uz;
+    unroll<Q>([&](auto I) {
+        constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
+        const CT v = kbc_shear_of<L, I>(sa, sb);
+        const CT dh = (h[I] - e[I]) - v;
+        const CT iv = inv_feq(I);
+        const CT bdh = bg * lam[I] + bsh * v * iv + (CT)2 * bhh * dh * iv;
+        const CT bfeq = -(bsh * v + bhh * dh) * dh * iv * iv;
+        CT bn = bdh;
+        if constexpr (cx != 0) bn += bP00;
+        if constexpr (cy != 0) bn += bP11;
+        if constexpr (cz != 0) bn += bP22;
+        if constexpr (cx * cy != 0) bn += (cx * cy > 0) ? bP01 : -bP01;
+        if constexpr (cx * cz != 0) bn += (cx * cz > 0) ? bP02 : -bP02;
+        if constexpr (cy * cz != 0) bn += (cy * cz > 0) ? bP12 : -bP12;
+        a[I] = lam[I] + bn;
+        const CT be = bfeq - bn;
+        const CT cu = cdot<L, I>(ux, uy, uz);
+        const CT wb = (CT)weight<L>(I) * be;
+        Ae += wb * ((CT)1 + (CT)3 * cu + (CT)4.5 * cu * cu - (CT)1.5 * uu);
+        const CT t9 = wb * rho * ((CT)3 + (CT)9 * cu);
+        if constexpr (cx != 0) Vx += (cx > 0) ? t9 : -t9;
+        if constexpr (cy != 0) Vy += (cy > 0) ? t9 : -t9;
+        if constexpr (cz != 0) Vz += (cz > 0) ? t9 : -t9;
+        const CT w3 = (CT)3 * wb * rho;
+        Vx -= w3 * ux;
+        Vy -= w3 * uy;
+        Vz -= w3 * uz;
+    });
+    // pass 3: rho and u of the equilibrium back to every h_j (d rho / d h_j = 1,
+    // d u / d h_j = (c_j - u) / rho)
+    const CT uV = (ux * Vx + uy * Vy + uz * Vz) * inv;
+    unroll<Q>([&](auto J) {
+        const CT cV = cdot<L, J>(Vx, Vy, Vz);
+        a[J] += Ae - uV + cV * inv;
+    });
+    return gt;
+}
+
 // Adjoint step at time t for one fluid cell.  F: natural state f(t) (storage
 // type ST, the forward path's tiled layout); An: a(t+1); Ao: a(t).  The
 // adjoint populations are compute-type planes, a_i(x) at i * plane + x: the
@@ -219,8 +368,8 @@ __device__ __forceinline__ void regularize_transpose(CT *a, const Params<CT> &p,
 // accumulators, 3 planes of N (internal axes).  Returns
 // sum_i lambda_i (f_i - feq_i), the cell's dL/dtau * tau^2.
 // REG: regularized faces may occur (the pre-closure populations are kept for
-// the closure's transpose).
-template <class L, class ST, bool HAS_S, bool FRC = false, bool REG = false>
+// the closure's transpose).  KB: the KBC collision (no body force).
+template <class L, class ST, bool HAS_S, bool FRC = false, bool REG = false, bool KB = false>
 __device__ __forceinline__ typename Store<ST>::CT adjoint_cell(const Params<typename Store<ST>::CT> &p,
                                                                const ST *__restrict__ F,
                                                                const typename Store<ST>::CT *__restrict__ An,
@@ -333,70 +482,91 @@ __device__ __forceinline__ typename Store<ST>::CT adjoint_cell(const Params<type
         dz = fz * inv;
         bq = (CT)1.5 * (dx * ((CT)2 * ux + dx) + dy * ((CT)2 * uy + dy) + dz * ((CT)2 * uz + dz));
     }
-    // lambda = (1 - s) b (partial bounce-back), dL/ds, dL/dtau * tau^2, A, V
-    // (force: AFs = sum w lambda cd (9 cu + 4.5 cd), T3 = sum w lambda cd c, cd = c . du)
-    CT gs = 0, gt = 0, Aa = 0, Vx = 0, Vy = 0, Vz = 0, Sw = 0;
-    CT AFs = 0, Tx = 0, Ty = 0, Tz = 0;
-    unroll<Q>([&](auto I) {
-        constexpr int O = opp<L>(I);
-        const CT lam = HAS_S ? ((CT)1 - s) * b[I] : b[I];
-        const CT neq = h[I] - heq<L, I>(drho, rho, ux, uy, uz, usq15);
-        const CT cu = (CT)L::c[I][0] * ux + (CT)L::c[I][1] * uy + (CT)L::c[I][2] * uz;
-        CT cd = 0;
-        if constexpr (FRC) cd = (CT)L::c[I][0] * dx + (CT)L::c[I][1] * dy + (CT)L::c[I][2] * dz;
-        if constexpr (HAS_S) {
-            CT post = h[I] - om * neq;
-            if constexpr (FRC)
-                post += (CT)weight<L>(I) * rho * ((CT)3 * cd + (CT)4.5 * cd * ((CT)2 * cu + cd) - bq);
-            gs += b[I] * (h[O] - post);
-        }
-        gt += lam * neq;
-        const CT wl = (CT)weight<L>(I) * lam;
-        Aa += wl * ((CT)1 - (CT)4.5 * cu * cu + (CT)1.5 * uu);
-        Sw += wl;
-        const CT t9 = (CT)3 + (CT)9 * cu;
-        if constexpr (L::c[I][0] != 0) Vx += wl * t9 * (CT)L::c[I][0];
-        if constexpr (L::c[I][1] != 0) Vy += wl * t9 * (CT)L::c[I][1];
-        if constexpr (L::c[I][2] != 0) Vz += wl * t9 * (CT)L::c[I][2];
-        if constexpr (FRC) {
-            const CT wcd = wl * cd;
-            AFs += wcd * ((CT)9 * cu + (CT)4.5 * cd);
-            if constexpr (L::c[I][0] != 0) Tx += wcd * (CT)L::c[I][0];
-            if constexpr (L::c[I][1] != 0) Ty += wcd * (CT)L::c[I][1];
-            if constexpr (L::c[I][2] != 0) Tz += wcd * (CT)L::c[I][2];
-        }
-    });
-    if constexpr (HAS_S) {
-        if (ds) ds[cell] += gs;
-    }
-    Vx -= (CT)3 * ux * Sw;
-    Vy -= (CT)3 * uy * Sw;
-    Vz -= (CT)3 * uz * Sw;
-    // force: A_F = bq Sw - AFs, V_F = 9 T3 - 3 du Sw; dL/dF = V + V_F
-    CT AF = 0, VFx = 0, VFy = 0, VFz = 0;
-    if constexpr (FRC) {
-        AF = bq * Sw - AFs;
-        VFx = (CT)9 * Tx - (CT)3 * dx * Sw;
-        VFy = (CT)9 * Ty - (CT)3 * dy * Sw;
-        VFz = (CT)9 * Tz - (CT)3 * dz * Sw;
-        if (dF) {
-            dF[cell] += Vx + VFx;
-            dF[N + cell] += Vy + VFy;
-            dF[2 * N + cell] += Vz + VFz;
-        }
-    }
     const CT eu = ex * ux + ey * uy + ez * uz;
     CT a[Q];
-    unroll<Q>([&](auto J) {
-        constexpr int O = opp<L>(J);
-        const CT lam = HAS_S ? ((CT)1 - s) * b[J] : b[J];
-        const CT cV = (CT)L::c[J][0] * Vx + (CT)L::c[J][1] * Vy + (CT)L::c[J][2] * Vz;
-        const CT ce = (CT)L::c[J][0] * ex + (CT)L::c[J][1] * ey + (CT)L::c[J][2] * ez;
-        CT v = ((CT)1 - om) * lam + om * (Aa + cV) + (ce - eu) * inv;
-        if constexpr (FRC) v += AF + (CT)L::c[J][0] * VFx + (CT)L::c[J][1] * VFy + (CT)L::c[J][2] * VFz;
-        if constexpr (HAS_S) v += s * b[O];
-        a[J] = v;
-    });
+    CT gt = 0;
+    if constexpr (KB) {
+        // lambda = (1 - s) b; the KBC collision's transpose; dL/ds against its output
+        CT lam[Q];
+        unroll<Q>([&](auto I) { lam[I] = HAS_S ? ((CT)1 - s) * b[I] : b[I]; });
+        gt = kbc_transpose<L>(h, lam, a, p, drho, rho, inv, ux, uy, uz, usq15);
+        if constexpr (HAS_S) {
+            CT post[Q];
+            kbc_relax<L>(h, post, p, drho, rho, ux, uy, uz, usq15);
+            CT gs = 0;
+            unroll<Q>([&](auto I) { gs += b[I] * (h[opp<L>(I)] - post[I]); });
+            if (ds) ds[cell] += gs;
+        }
+        unroll<Q>([&](auto J) {
+            constexpr int O = opp<L>(J);
+            const CT ce = cdot<L, J>(ex, ey, ez);
+            a[J] += (ce - eu) * inv;
+            if constexpr (HAS_S) a[J] += s * b[O];
+        });
+    } else {
+        // lambda = (1 - s) b (partial bounce-back), dL/ds, dL/dtau * tau^2, A, V
+        // (force: AFs = sum w lambda cd (9 cu + 4.5 cd), T3 = sum w lambda cd c, cd = c . du)
+        CT gs = 0, Aa = 0, Vx = 0, Vy = 0, Vz = 0, Sw = 0;
+        CT AFs = 0, Tx = 0, Ty = 0, Tz = 0;
+        unroll<Q>([&](auto I) {
+            constexpr int O = opp<L>(I);
+            const CT lam = HAS_S ? ((CT)1 - s) * b[I] : b[I];
+            const CT neq = h[I] - heq<L, I>(drho, rho, ux, uy, uz, usq15);
+            const CT cu = (CT)L::c[I][0] * ux + (CT)L::c[I][1] * uy + (CT)L::c[I][2] * uz;
+            CT cd = 0;
+            if constexpr (FRC) cd = (CT)L::c[I][0] * dx + (CT)L::c[I][1] * dy + (CT)L::c[I][2] * dz;
+            if constexpr (HAS_S) {
+                CT post = h[I] - om * neq;
+                if constexpr (FRC)
+                    post += (CT)weight<L>(I) * rho * ((CT)3 * cd + (CT)4.5 * cd * ((CT)2 * cu + cd) - bq);
+                gs += b[I] * (h[O] - post);
+            }
+            gt += lam * neq;
+            const CT wl = (CT)weight<L>(I) * lam;
+            Aa += wl * ((CT)1 - (CT)4.5 * cu * cu + (CT)1.5 * uu);
+            Sw += wl;
+            const CT t9 = (CT)3 + (CT)9 * cu;
+            if constexpr (L::c[I][0] != 0) Vx += wl * t9 * (CT)L::c[I][0];
+            if constexpr (L::c[I][1] != 0) Vy += wl * t9 * (CT)L::c[I][1];
+            if constexpr (L::c[I][2] != 0) Vz += wl * t9 * (CT)L::c[I][2];
+            if constexpr (FRC) {
+                const CT wcd = wl * cd;
+                AFs += wcd * ((CT)9 * cu + (CT)4.5 * cd);
+                if constexpr (L::c[I][0] != 0) Tx += wcd * (CT)L::c[I][0];
+                if constexpr (L::c[I][1] != 0) Ty += wcd * (CT)L::c[I][1];
+                if constexpr (L::c[I][2] != 0) Tz += wcd * (CT)L::c[I][2];
+            }
+        });
+        if constexpr (HAS_S) {
+            if (ds) ds[cell] += gs;
+        }
+        Vx -= (CT)3 * ux * Sw;
+        Vy -= (CT)3 * uy * Sw;
+        Vz -= (CT)3 * uz * Sw;
+        // force: A_F = bq Sw - AFs, V_F = 9 T3 - 3 du Sw; dL/dF = V + V_F
+        CT AF = 0, VFx = 0, VFy = 0, VFz = 0;
+        if constexpr (FRC) {
+            AF = bq * Sw - AFs;
+            VFx = (CT)9 * Tx - (CT)3 * dx * Sw;
+            VFy = (CT)9 * Ty - (CT)3 * dy * Sw;
+            VFz = (CT)9 * Tz - (CT)3 * dz * Sw;
+            if (dF) {
+                dF[cell] += Vx + VFx;
+                dF[N + cell] += Vy + VFy;
+                dF[2 * N + cell] += Vz + VFz;
+            }
+        }
+        unroll<Q>([&](auto J) {
+            constexpr int O = opp<L>(J);
+            const CT lam = HAS_S ? ((CT)1 - s) * b[J] : b[J];
+            const CT cV = (CT)L::c[J][0] * Vx + (CT)L::c[J][1] * Vy + (CT)L::c[J][2] * Vz;
+            const CT ce = (CT)L::c[J][0] * ex + (CT)L::c[J][1] * ey + (CT)L::c[J][2] * ez;
+            CT v = ((CT)1 - om) * lam + om * (Aa + cV) + (ce - eu) * inv;
+            if constexpr (FRC) v += AF + (CT)L::c[J][0] * VFx + (CT)L::c[J][1] * VFy + (CT)L::c[J][2] * VFz;
+            if constexpr (HAS_S) v += s * b[O];
+            a[J] = v;
+        });
+    }
     if (zf >= 0 && pending) {
         if constexpr (REG) {
             if (p.ft->type[zf] >= F_REG_VEL) regularize_transpose<L>(a, p, zf, hpre);
@@ -428,24 +598,24 @@ __device__ __forceinline__ void block_add(double v, double *acc, int64_t row) {
 // step is latency bound: measured on D3Q19 FP32 256^3, 4 waves (<= 128 VGPRs)
 // run 15% faster than the compiler's 3, 5 waves spill.
 // FP64 arithmetic keeps the compiler's choice.
-// With the body force or regularized faces (more live values) D3Q19 FP32
+// With the body force, regularized faces or KBC (more live values) D3Q19 FP32
 // asks for 3 waves and D3Q27 for 2: one more spills.
-template <class L, class ST, bool FRC = false, bool REG = false>
+template <class L, class ST, bool FRC = false, bool REG = false, bool KB = false>
 struct AdjWaves {
     static constexpr bool f64 = sizeof(typename Store<ST>::CT) == 8;
     static constexpr int value = f64 ? 1
-                                     : ((L::Q == 19) ? ((FRC || REG) ? 3 : 4)
-                                                     : ((L::Q == 27) ? ((FRC || REG) ? 2 : 3) : 1));
+                                     : ((L::Q == 19) ? ((FRC || REG || KB) ? 3 : 4)
+                                                     : ((L::Q == 27) ? ((FRC || REG || KB) ? 2 : 3) : 1));
 };
 #ifdef LBM_ADJ_WAVES
 #define LBM_ADJ_ATTR __attribute__((amdgpu_waves_per_eu(LBM_ADJ_WAVES)))
 #define LBM_ADJ_ATTR_F LBM_ADJ_ATTR
 #else
 #define LBM_ADJ_ATTR __attribute__((amdgpu_waves_per_eu(AdjWaves<L, ST>::value)))
-#define LBM_ADJ_ATTR_F __attribute__((amdgpu_waves_per_eu(AdjWaves<L, ST, FRC, REG>::value)))
+#define LBM_ADJ_ATTR_F __attribute__((amdgpu_waves_per_eu(AdjWaves<L, ST, FRC, REG, KB>::value)))
 #endif
 
-template <class L, class ST, bool HAS_S, bool FRC, bool REG>
+template <class L, class ST, bool HAS_S, bool FRC, bool REG, bool KB>
 __global__ void __launch_bounds__(kMaxBlock) LBM_ADJ_ATTR_F k_adjoint(const Params<typename Store<ST>::CT> p, const ST *__restrict__ F,
                                                        const typename Store<ST>::CT *__restrict__ An,
                                                        typename Store<ST>::CT *__restrict__ Ao,
@@ -454,7 +624,7 @@ __global__ void __launch_bounds__(kMaxBlock) LBM_ADJ_ATTR_F k_adjoint(const Para
     int X, Y, Z;
     double g = 0.0;
     if (adj_block_cell(p, X, Y, Z))
-        g = (double)adjoint_cell<L, ST, HAS_S, FRC, REG>(p, F, An, Ao, ds, X, Y, Z, p.zh_pending, dF, N);
+        g = (double)adjoint_cell<L, ST, HAS_S, FRC, REG, KB>(p, F, An, Ao, ds, X, Y, Z, p.zh_pending, dF, N);
     block_add(g, acc, blockIdx.x);
 }
 
@@ -735,17 +905,25 @@ static hipError_t adj_dispatch(const AdjLaunch &g) {
                 hipLaunchKernelGGL((k_adjoint_batch<L, ST>), grid, block, 0, g.stream, bd, static_cast<const ST *>(g.F),
                                    static_cast<const CT *>(g.An), static_cast<CT *>(g.Ao), g.acc, g.pending);
             else {
-#define LBM_ADJ(S, FR, RG)                                                                                         \
-    hipLaunchKernelGGL((k_adjoint<L, ST, S, FR, RG>), grid, block, 0, g.stream, p, static_cast<const ST *>(g.F),   \
+#define LBM_ADJ(S, FR, RG, KB)                                                                                     \
+    hipLaunchKernelGGL((k_adjoint<L, ST, S, FR, RG, KB>), grid, block, 0, g.stream, p,                             \
+                       static_cast<const ST *>(g.F),                                                             \
                        static_cast<const CT *>(g.An), static_cast<CT *>(g.Ao), static_cast<CT *>(g.ds), g.acc,    \
                        static_cast<CT *>(g.dF), g.N);
-                // (regularized faces with a body force are refused by the host)
-                if (g.reg && g.ds) LBM_ADJ(true, false, true)
-                else if (g.reg) LBM_ADJ(false, false, true)
-                else if (g.ds && g.force) LBM_ADJ(true, true, false)
-                else if (g.ds) LBM_ADJ(true, false, false)
-                else if (g.force) LBM_ADJ(false, true, false)
-                else LBM_ADJ(false, false, false)
+                // (regularized faces or KBC with a body force, and KBC with
+                // regularized faces, are refused by the host; KBC runs on D2Q9
+                // and D3Q27)
+                if (g.kbc) {
+                    if constexpr (L::Q != 19) {
+                        if (g.ds) LBM_ADJ(true, false, false, true)
+                        else LBM_ADJ(false, false, false, true)
+                    }
+                } else if (g.reg && g.ds) LBM_ADJ(true, false, true, false)
+                else if (g.reg) LBM_ADJ(false, false, true, false)
+                else if (g.ds && g.force) LBM_ADJ(true, true, false, false)
+                else if (g.ds) LBM_ADJ(true, false, false, false)
+                else if (g.force) LBM_ADJ(false, true, false, false)
+                else LBM_ADJ(false, false, false, false)
 #undef LBM_ADJ
             }
             break;

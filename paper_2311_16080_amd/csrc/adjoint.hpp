@@ -37,6 +37,7 @@ struct AdjLaunch {
     const void *grho, *gu;
     int force;              // ADJ_STEP: the body force is on
     int reg;                // ADJ_STEP: a face is regularized (its closure transpose needs the pre-closure state)
+    int kbc;                // ADJ_STEP: the KBC collision (D2Q9, D3Q27; no body force, no regularized face)
     void *dF;               // dL/dF accumulators (CT, 3 planes of N, internal axes) or null
     void *df_out;           // ADJ_DF_OUT destination (D planes of N, caller axes, in_f64 ? double : float) or null
     double eps;             // ADJ_DF_OUT: scale of the force (rows in acc: D FP64 sums per 256 cells)

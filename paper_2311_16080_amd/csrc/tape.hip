@@ -229,6 +229,7 @@ struct Backward {
         g.stream = c->stream;
         g.pending = (t > 0) ? 1 : 0;
         g.reg = has_regularized_face(c) ? 1 : 0;
+        g.kbc = (c->collision == LBM_KBC) ? 1 : 0;
         if (c->batch) {
             g.batch = &bl.b;
             g.grid = bl.grid;
@@ -286,7 +287,11 @@ static int backward_impl(lbm_ctx *c, const void *dL_drho, const void *dL_du, int
     if (has_regularized_face(c) && (c->batch || c->force_on || want_force))
         return fail(LBM_EUNSUPPORTED, "the adjoint of regularized faces covers single domains without a body force");
     if (c->nlinks) return fail(LBM_EUNSUPPORTED, "the adjoint of interpolated bounce-back is not implemented");
-    if (c->collision != LBM_BGK) return fail(LBM_EUNSUPPORTED, "the adjoint covers the BGK collision only");
+    if (c->collision == LBM_KBC && (c->force_on || want_force || c->batch || has_regularized_face(c)))
+        return fail(LBM_EUNSUPPORTED, "the adjoint of the KBC collision covers single domains without a body force "
+                                      "or regularized faces");
+    if (c->collision != LBM_BGK && c->collision != LBM_KBC)
+        return fail(LBM_EUNSUPPORTED, "the adjoint covers the BGK and KBC collisions");
     if (want_force && c->batch) return fail(LBM_EUNSUPPORTED, "body forces are not supported on batch contexts");
     if (c->tape_recording) lbm_tape_end(c);
     TapeState *T = c->tape;

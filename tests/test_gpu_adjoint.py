@@ -27,7 +27,7 @@ def _announce(name):
     sys.stdout.flush()
 
 
-def _oracle_grads(case, target, t_pre):
+def _oracle_grads(case, target, t_pre, kbc=False):
     import oracle
     from cases import _oface
     faces = [_oface(F) for F in case.faces]
@@ -36,7 +36,7 @@ def _oracle_grads(case, target, t_pre):
     sol = None if case.solid is None else case.solid.reshape(case.oshape).astype(np.uint8)
     sv = None if case.s is None else case.s.reshape(case.oshape).astype(np.float32).astype(np.float64)
     S = oracle.Sim(q=case.q, nx=case.oshape[0], ny=case.oshape[1], nz=case.oshape[2], tau=case.tau, faces=faces,
-                   solid=sol, s=sv)
+                   solid=sol, s=sv, collision=oracle.KBC if kbc else oracle.BGK)
     rho, u = case.init_fields()
     f = S.equilibrium_state(rho=None if rho is None else rho.reshape(case.oshape),
                             u=None if u is None else u.reshape(case.oshape + (case.D,)))
@@ -51,9 +51,11 @@ def _oracle_grads(case, target, t_pre):
     return L, dlds, dtau, duw
 
 
-def _gpu_grads(case, target, K, t_pre):
+def _gpu_grads(case, target, K, t_pre, kbc=False):
     import torch
     sim = gpu_sim(case)
+    if kbc:
+        sim.set_collision("KBC")
     sim.step(t_pre)
     sim.tape_begin(K, case.steps)
     sim.step(case.steps)
@@ -151,13 +153,38 @@ ADJ_CASES = {
 }
 
 
-@pytest.mark.parametrize("name", sorted(ADJ_CASES))
-def test_adjoint_matches_oracle(name):
-    case, K, t_pre, tol = ADJ_CASES[name]
+def kbc_cavity2d(storage, steps=16):
+    return Case(9, (40, 24), 0.53, [(W,), (W,), (W,), (W, (0.05, 0.0)), (P,), (P,)], steps=steps, storage=storage,
+                init_seed=68)
+
+
+def kbc_channel2d(storage, steps=14):
+    return Case(9, (40, 24), 0.56, [(ZV, (0.04, 0.0)), (OUT, (0, 0, 0), 1.0), (W,), (W, (0.03, 0.0)), (P,), (P,)],
+                steps=steps, storage=storage, init_seed=69)
+
+
+def kbc_box3d(storage, steps=8):
+    sol = np.zeros((10, 9, 68), np.uint8)
+    sol[4:7, 3:6, 20:40] = 1
+    return Case(27, (10, 9, 68), 0.52, [(W,)] * 5 + [(W, (0.04, 0.01, 0))], steps=steps, storage=storage,
+                init_seed=71, solid=sol)
+
+
+# the KBC collision (no partial bounce-back: KBC takes no solid fraction)
+KBC_CASES = {
+    "kbc_cavity2d_f64_K5": (kbc_cavity2d("f64"), 5, 0, 1e-10),
+    "kbc_cavity2d_f32_K5": (kbc_cavity2d("f32"), 5, 0, 1e-4),
+    "kbc_channel2d_f64_K4_oddstart": (kbc_channel2d("f64"), 4, 3, 1e-10),
+    "kbc_box3d_d3q27_f64_K3_oddstart": (kbc_box3d("f64"), 3, 1, 1e-10),
+    "kbc_box3d_d3q27_f32_K4_pull": (replace(kbc_box3d("f32"), pattern="pull"), 4, 0, 1e-4),
+}
+
+
+def _compare_with_oracle(name, case, K, t_pre, tol, kbc=False):
     _announce(name)
     target = inputs.random_velocity(case.oshape, case.D, 70, amp=0.02)
-    Lg, dsg, dtaug, duwg, unchanged = _gpu_grads(case, target, K, t_pre)
-    Lo, dso, dtauo, duwo = _oracle_grads(case, target, t_pre)
+    Lg, dsg, dtaug, duwg, unchanged = _gpu_grads(case, target, K, t_pre, kbc)
+    Lo, dso, dtauo, duwo = _oracle_grads(case, target, t_pre, kbc)
     print(f"[case] {name}: L gpu {Lg:.6e} oracle {Lo:.6e}; dtau {dtaug:.6e} vs {dtauo:.6e}", flush=True)
     assert unchanged, "backward changed the forward state"
     assert abs(Lg - Lo) <= max(tol, 1e-12) * abs(Lo) * 10
@@ -173,6 +200,16 @@ def test_adjoint_matches_oracle(name):
         print(f"[case] {name}: dL/du_w rel {e:.3e}", flush=True)
         assert e <= tol
     assert np.all(duwg[~nz] == 0)
+
+
+@pytest.mark.parametrize("name", sorted(ADJ_CASES))
+def test_adjoint_matches_oracle(name):
+    _compare_with_oracle(name, *ADJ_CASES[name])
+
+
+@pytest.mark.parametrize("name", sorted(KBC_CASES))
+def test_adjoint_of_kbc_matches_oracle(name):
+    _compare_with_oracle(name, *KBC_CASES[name], kbc=True)
 
 
 def test_autograd_rollout_matches_finite_differences():

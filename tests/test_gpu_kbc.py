@@ -3,7 +3,8 @@ test_oracle_kbc.py): D2Q9 and D3Q27 with walls, a moving lid, Zou-He /
 outflow faces, solids, periodic faces and a body force, on every storage and
 both AA parities; a near-inviscid cavity over 500 steps (bounded, mass, kinetic
 energy) and element by element over its first 40 steps; double buffer equals
-in place bitwise; the unsupported combinations are refused."""
+in place bitwise; the unsupported combinations are refused (the adjoint of KBC
+is compared with the oracle's in test_gpu_adjoint.py)."""
 import sys
 
 import numpy as np
@@ -149,12 +150,24 @@ def test_kbc_refusals():
     with pytest.raises(lbm.LbmError) as ei:
         sim.set_solid_fraction(np.zeros((24, 16), np.float32))
     assert ei.value.code == lbm.LBM_EUNSUPPORTED
+    # the adjoint covers KBC (compared with the oracle's in test_gpu_adjoint.py),
+    # not KBC with a body force
+    sim.tape_begin(2, 4)
+    sim.step(4)
+    sim.tape_end()
+    _, dtau, _ = sim.backward(None, torch.zeros((2, 24, 16), device="cuda"))
+    assert dtau[0] == 0.0
+    with pytest.raises(lbm.LbmError) as ei:
+        sim.backward_force(None, torch.zeros((2, 24, 16), device="cuda"))
+    assert ei.value.code == lbm.LBM_EUNSUPPORTED
+    sim.set_force([1e-5, 0.0])
     sim.tape_begin(2, 4)
     sim.step(4)
     sim.tape_end()
     with pytest.raises(lbm.LbmError) as ei:
         sim.backward(None, torch.zeros((2, 24, 16), device="cuda"))
     assert ei.value.code == lbm.LBM_EUNSUPPORTED
+    sim.set_force()
     with pytest.raises(lbm.LbmError):
         sim.set_collision(7)
     bs = lbm.BatchSim("D2Q9", [(8, 8)], [0.7], [[(W,), (W,), (W,), (W, (0.05, 0.0)), (P,), (P,)]])
