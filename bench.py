@@ -292,6 +292,14 @@ def adjoint_figures(torch, lbm):
 
     res.append(adjoint_ratio(torch, lbm, "D2Q9 FP32 8192^2 cavity, mean kinetic energy loss", cav2, 50, 10,
                              lambda r, u: _ke_seed(torch, r, u, 8192.0 ** 2)))
+
+    def kbc3():
+        sim = lbm.Sim("D3Q27", (256, 256, 256), 0.5005, faces=cavity_faces(lbm), storage="f32")
+        sim.set_collision("KBC")
+        return sim
+
+    res.append(adjoint_ratio(torch, lbm, "D3Q27 FP32 256^3 KBC cavity at tau = 0.5005, mean kinetic energy loss",
+                             kbc3, 40, 10, lambda r, u: _ke_seed(torch, r, u, 256.0 ** 3)))
     return res
 
 
