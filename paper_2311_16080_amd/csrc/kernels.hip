@@ -63,6 +63,11 @@ static hipError_t dispatch(const Launch &g, int op, int a0, bool b0, const void 
 }
 
 hipError_t launch_step(const Launch &g, int mode, bool has_s) {
+    if (mode == 2 && g.nt_push >= 0 && g.nt_push != g.nt) {
+        Launch h = g;
+        h.nt = g.nt_push;
+        return dispatch(h, OP_STEP, mode, has_s, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
+    }
     return dispatch(g, OP_STEP, mode, has_s, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
 }
 

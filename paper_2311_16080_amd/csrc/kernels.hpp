@@ -30,6 +30,7 @@ struct Launch {
     int force;           // body force on (params carry it)
     int kbc;             // KBC collision
     int walls_only;      // allow the walls-only step variant (LBM_WALLS_ONLY = 0 disables it, for measurement)
+    int nt_push = -1;    // memory hints for push steps (mode 2); -1: as nt
 };
 
 hipError_t launch_step(const Launch &g, int mode, bool has_s);
