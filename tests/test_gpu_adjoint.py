@@ -4,7 +4,7 @@ Loss L = sum over fluid cells of |u(n) - u_T|^2 (u_T a seeded target field).
 Compared: dL/ds (partial bounce-back fraction, per cell), dL/dtau, dL/du_w
 (per face wall velocity).  FP64: rel-L2 / relative error <= 1e-10, except dL/ds,
 which the C-ABI returns as float32 (<= 1e-7, its rounding); FP32 storage and
-arithmetic: <= 1e-4.  The oracle adjoint itself is pinned by finite
+arithmetic: <= 1e-4; FP16 storage (FP32 arithmetic): <= 1e-3.  The oracle adjoint itself is pinned by finite
 differences and dense-Jacobian transposes in test_oracle_adjoint.py.
 """
 import sys
@@ -143,6 +143,10 @@ ADJ_CASES = {
     "channel2d_pbb_f64_K5_pull": (replace(channel2d("f64"), pattern="pull"), 5, 0, 1e-10),
     "cavity3d_f64_K6_oddstart_pull": (replace(cavity3d("f64"), pattern="pull"), 6, 3, 1e-10),
     "spheres3d_d3q27_f32_K4_pull": (replace(spheres3d("f32"), pattern="pull"), 4, 1, 1e-4),
+    # FP16 storage (split pairs on these boxes; FP32 arithmetic): measured 1.5e-4
+    # at most (dL/ds), so the bar is 1e-3
+    "cavity3d_f16_K5": (cavity3d("f16"), 5, 0, 1e-3),
+    "spheres3d_d3q27_f16_K4_pull": (replace(spheres3d("f16"), pattern="pull"), 4, 1, 1e-3),
     # regularized faces: the closure's transpose (its momentum-flux projection)
     "reg_channel2d_f64_K5": (reg_channel2d("f64"), 5, 0, 1e-10),
     "reg_channel2d_f32_K5": (reg_channel2d("f32"), 5, 0, 1e-4),
