@@ -142,6 +142,7 @@ ADJ_CASES = {
     # the pull pattern: the tape's checkpoints hold the gathered layout
     "channel2d_pbb_f64_K5_pull": (replace(channel2d("f64"), pattern="pull"), 5, 0, 1e-10),
     "cavity3d_f64_K6_oddstart_pull": (replace(cavity3d("f64"), pattern="pull"), 6, 3, 1e-10),
+    "cavity3d_f64_K6_oddstart_double": (replace(cavity3d("f64"), pattern="double"), 6, 3, 1e-10),
     "spheres3d_d3q27_f32_K4_pull": (replace(spheres3d("f32"), pattern="pull"), 4, 1, 1e-4),
     # FP16 storage (split pairs on these boxes; FP32 arithmetic): measured 1.5e-4
     # at most (dL/ds), so the bar is 1e-3
