@@ -158,10 +158,12 @@ constexpr int kTileLog = 12;
 constexpr int64_t kTile = (int64_t)1 << kTileLog;
 template <int Q>
 __host__ __device__ __forceinline__ int64_t pidx(int i, int64_t cell) {
-    // 32-bit arithmetic where it fits (cells < 2^31, so tile * Q + i < 2^24)
+    // ((c >> 12) Q + i) 4096 + (c & 4095) written as c + ((c >> 12) (Q - 1) + i) 4096:
+    // the same integer, with no mask and no OR (cells < 2^31, so the bracket
+    // is < 2^24 and fits 32-bit arithmetic; the sum is taken in 64 bits)
     const uint32_t c = (uint32_t)cell;
-    const uint32_t t = (c >> kTileLog) * (uint32_t)Q + (uint32_t)i;
-    return (int64_t)(((uint64_t)t << kTileLog) | (c & (uint32_t)(kTile - 1)));
+    const uint32_t t = (c >> kTileLog) * (uint32_t)(Q - 1) + (uint32_t)i;
+    return (int64_t)((uint64_t)c + ((uint64_t)t << kTileLog));
 }
 __host__ __device__ constexpr int64_t tiled_cells(int64_t n) { return (n + kTile - 1) / kTile * kTile; }
 
